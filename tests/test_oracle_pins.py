@@ -1,0 +1,345 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these compares the oracle with itself: each uses an independent route
+(a library matrix exponential, a library ODE integrator, quadrature of the
+field, a closed-form asymptotic or perturbative result, an exact symmetry, or
+an independent complex-matrix brute force on a tiny grid).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.linalg as sl
+
+import oracle
+from paper_1607_03062_amd import workloads as wl
+
+SX = np.array([[0, 1], [1, 0]], dtype=complex)
+SY = np.array([[0, -1j], [1j, 0]], dtype=complex)
+I2 = np.eye(2, dtype=complex)
+
+CFG1 = wl.config1()
+G1, F1 = CFG1["grid"], CFG1["field"]
+
+
+def sin2_E(E0, w, cycles):
+    """The workload's field E(t) = E0 sin^2(pi t/T) sin(w t) on [0, T], typed from its definition."""
+    T = cycles * 2 * math.pi / w
+
+    def E(t):
+        if t < 0 or t > T:
+            return 0.0
+        return E0 * math.sin(math.pi * t / T) ** 2 * math.sin(w * t)
+
+    return E, T
+
+
+# ---------------------------------------------------------------------------
+# Spinors and the single step (Sec. II Eqs. (3)-(4); Sec. III Eqs. (11)-(13))
+
+
+@pytest.mark.parametrize("valley", [1, -1])
+def test_spinors_orthonormal_eigenvectors(valley):
+    """u, v are unit, orthogonal (u^dagger v = 0) and are the positive / negative
+    energy eigenvectors of the valley Hamiltonian +-sigma.P (pin Q10)."""
+    rng = np.random.default_rng(10)
+    for _ in range(50):
+        Px, Py = rng.normal(size=2) * rng.choice([1e-3, 1.0, 30.0])
+        u, v = oracle.spinors(Px, Py, valley)
+        E = math.hypot(Px, Py)
+        H = valley * (SX * Px + SY * Py)
+        assert abs(np.vdot(u, u) - 1) < 1e-15 and abs(np.vdot(v, v) - 1) < 1e-15
+        assert abs(np.vdot(u, v)) < 1e-15
+        assert np.max(np.abs(H @ u - E * u)) <= 1e-14 * max(E, 1)
+        assert np.max(np.abs(H @ v + E * v)) <= 1e-14 * max(E, 1)
+
+
+@pytest.mark.parametrize("valley", [1, -1])
+@pytest.mark.parametrize("scheme", ["midpoint", "strang"])
+def test_step_equals_matrix_exponential(scheme, valley):
+    """One oracle step equals scipy's expm of the same operator (pin Q4):
+    midpoint: exp(-i g dt sigma.P); strang: exp(-i g dt py sy/2) exp(-i g dt Px sx) exp(-i g dt py sy/2)."""
+    rng = np.random.default_rng(4)
+    cases = [(0.0, 0.0, 0.01, 0.0), (0.3, 0.0, 0.02, -0.1), (0.0, 0.7, 0.05, 0.0)]
+    cases += [tuple(rng.normal(size=2) * 2) + (float(rng.uniform(1e-3, 0.3)), float(rng.normal())) for _ in range(40)]
+    for px, py, dt, A in cases:
+        U = oracle.step_matrix(px, py, dt, A, scheme, valley)
+        Px = px + A
+        if scheme == "midpoint":
+            ref = sl.expm(-1j * valley * dt * (SX * Px + SY * py))
+        else:
+            hy = sl.expm(-0.5j * valley * dt * py * SY)
+            ref = hy @ sl.expm(-1j * valley * dt * Px * SX) @ hy
+        assert np.max(np.abs(U - ref)) < 1e-15
+        assert np.max(np.abs(U.conj().T @ U - I2)) < 1e-15  # unitary (norm conservation, Sec. III)
+
+
+# ---------------------------------------------------------------------------
+# Field (gauge A_0 = 0, E = -dA/dt; Sec. II after Eq. (2))
+
+
+def test_sin2_vector_potential_is_minus_integral_of_E():
+    """A(t) = -int_0^t E for the sin^2 pulse, against adaptive quadrature of E typed from its
+    definition (pin Q11); A(T) = 0 for an integer number of cycles."""
+    for E0, w, cyc in [(0.1, 0.5, 8), (0.3, 0.25, 20), (0.45, 0.9, 4)]:
+        Efun, T = sin2_E(E0, w, cyc)
+        f = wl.sin2(E0, w, cyc)
+        ts = np.linspace(0, T, 23)
+        A = oracle.field_A(f, ts)
+        for t, a in zip(ts, A):
+            q = -si.quad(Efun, 0, t, limit=400, epsabs=1e-15, epsrel=1e-14)[0] if t > 0 else 0.0
+            assert abs(a - q) < 2e-13 * max(1.0, E0 / w)
+        assert abs(oracle.field_A(f, [T])[0]) < 1e-15
+        assert abs(oracle.field_A(f, [2 * T])[0]) < 1e-15  # constant after the pulse
+
+
+def test_constant_and_pulse_vector_potentials():
+    f = wl.constant(0.2, 200.0)
+    assert np.allclose(oracle.field_A(f, [0, 10, 200, 300]), [0, -2.0, -40.0, -40.0], rtol=0, atol=1e-15)
+    # the paper's rise / flat / fall pulse: A = -int E, continuous across the joins
+    p = {"kind": "pulse", "E0": 1.0, "omega": 0.4876, "phi": 0.3, "omega_rise": 0.0609, "omega_fall": 0.0609,
+         "duration": 70.9}
+    tr = math.pi / (2 * p["omega_rise"])
+    tf = p["duration"] - math.pi / (2 * p["omega_fall"])
+
+    def E(t):
+        if t < 0 or t > p["duration"]:
+            return 0.0
+        if t < tr:
+            env = math.sin(p["omega_rise"] * t) ** 2
+        elif t > tf:
+            env = math.cos(p["omega_fall"] * (t - tf)) ** 2
+        else:
+            env = 1.0
+        return p["E0"] * env * math.cos(p["omega"] * t + p["phi"])
+
+    # oracle_E follows the same reading of Eq. (14)
+    ts = np.linspace(0, p["duration"], 41)
+    assert np.allclose(oracle.field_E(p, ts), [E(t) for t in ts], rtol=0, atol=1e-15)
+    for t in ts:
+        q = -si.quad(E, 0, t, points=[x for x in (tr, tf) if x < t], limit=400, epsabs=1e-14, epsrel=1e-13)[0]
+        assert abs(oracle.field_A(p, [t])[0] - q) < 1e-12
+    # the envelope reaches zero at the end of the fall window
+    assert abs(oracle.field_E(p, [p["duration"]])[0]) < 1e-15
+
+
+def test_density_scale():
+    """rho = 4 int d^2p/(2 pi)^2 n: with n = 1 on the node grid the rectangle rule gives 4 * area / (2 pi)^2."""
+    g = {"nx": 7, "ny": 5, "px": (-1.5, 2.0), "py": (-0.5, 1.5)}
+    rho = oracle.density(g, np.ones(35))
+    assert abs(rho - 4 * 3.5 * 2.0 / (4 * math.pi ** 2)) < 1e-16
+
+
+# ---------------------------------------------------------------------------
+# Independent brute force on tiny inputs (Sec. II Eq. (1) with the paper's own
+# spinor normalisation 1/(2 E_out 2 E_in), Sec. III Eqs. (9), (11)-(12))
+
+
+def brute_force(Efun, t_i, t_f, grid, N, scheme):
+    dt = (t_f - t_i) / N
+    tm = t_i + (np.arange(N) + 0.5) * dt
+    A_mid = np.array([-si.quad(Efun, t_i, t, limit=200, epsabs=1e-15, epsrel=1e-14)[0] for t in tm])
+    A_in = 0.0
+    A_out = -si.quad(Efun, t_i, t_f, limit=400, epsabs=1e-15, epsrel=1e-14)[0]
+    nx, ny = grid["nx"], grid["ny"]
+    (x0, x1), (y0, y1) = grid["px"], grid["py"]
+    dx, dy = (x1 - x0) / nx, (y1 - y0) / ny
+    n = np.zeros((ny, nx))
+    for j in range(ny):
+        for i in range(nx):
+            px, py = x0 + i * dx, y0 + j * dy
+            Pin, Pout = np.array([px + A_in, py]), np.array([px + A_out, py])
+            Ein, Eout = np.hypot(*Pin), np.hypot(*Pout)
+            if Ein == 0 or Eout == 0:
+                continue
+            v = np.array([-Pin[0] + 1j * Pin[1], Ein]) / np.sqrt(Ein)      # Eq. (3), v_K+(t_i, -p)
+            u = np.array([Eout, Pout[0] + 1j * Pout[1]]) / np.sqrt(Eout)   # Eq. (3), u_K+(t_f, p)
+            U = I2.copy()
+            for k in range(N):
+                Px = px + A_mid[k]
+                if scheme == "midpoint":
+                    Uk = sl.expm(-1j * dt * (SX * Px + SY * py))
+                else:
+                    h = sl.expm(-0.5j * dt * py * SY)
+                    Uk = h @ sl.expm(-1j * dt * Px * SX) @ h
+                U = Uk @ U
+            n[j, i] = abs(np.vdot(u, U @ v)) ** 2 / (2 * Eout * 2 * Ein)
+    rho = 4.0 * dx * dy / (2 * math.pi) ** 2 * n.sum()
+    return n.ravel(), rho
+
+
+@pytest.mark.parametrize("scheme", ["strang", "midpoint"])
+def test_brute_force_tiny_grid(scheme):
+    """Whole pipeline (grid, midpoint field, spinors, steps, projection, density) against an
+    independent complex-matrix computation on a small asymmetric grid."""
+    Efun, T = sin2_E(0.4, 0.5, 2)
+    f = wl.sin2(0.4, 0.5, 2)
+    g = {"nx": 5, "ny": 4, "px": (-1.5, 2.5), "py": (-1.0, 1.6)}
+    N = 48
+    n_ref, rho_ref = brute_force(Efun, 0.0, T, g, N, scheme)
+    n, nd, masked = oracle.solve_grid(f, g, N, scheme)
+    assert masked == 0
+    assert np.max(np.abs(n - n_ref)) < 1e-13
+    assert abs(oracle.density(g, n) - rho_ref) < 1e-14 * abs(rho_ref) + 1e-16
+    assert n.max() > 1e-2  # non-trivial case
+
+
+def test_masked_point_at_zero_momentum():
+    """E_in = 0 (p = 0 with A_in = 0) is masked and gets n = 0."""
+    g = {"nx": 4, "ny": 4, "px": (-2.0, 2.0), "py": (-2.0, 2.0)}
+    n, nd, masked = oracle.solve_grid(F1, g, 200, "strang")
+    assert masked == 1
+    assert n[2 * 4 + 2] == 0.0
+
+
+# ---------------------------------------------------------------------------
+# Exact special cases and invariants on config 1 (64x64, [-2,2]^2, N = 4000)
+
+
+@pytest.fixture(scope="module")
+def cfg1_full():
+    out = {}
+    for s in ("strang", "midpoint"):
+        out[s] = oracle.solve_grid(F1, G1, CFG1["n_steps"], s)
+    return out
+
+
+@pytest.mark.parametrize("scheme", ["strang", "midpoint"])
+def test_py_zero_line_exactly_zero(cfg1_full, scheme):
+    """p_y = 0: the Hamiltonian sigma_x P_x(t) commutes with itself at all times, so the
+    sigma_x eigenstate is kept and n = 0 exactly (pin Q1)."""
+    n, nd, masked = cfg1_full[scheme]
+    row = n.reshape(64, 64)[32]  # p_y = -2 + 32 * 4/64 = 0
+    assert oracle.grid_p(-2.0, 2.0, 64, 32) == 0.0
+    assert np.all(row == 0.0)
+    assert masked == 1
+
+
+@pytest.mark.parametrize("scheme", ["strang", "midpoint"])
+def test_norm_conservation(cfg1_full, scheme):
+    """Every split step is unitary (Sec. III), so |psi|^2 stays 1 to rounding (pin Q2)."""
+    n, nd, masked = cfg1_full[scheme]
+    assert np.max(np.abs(nd)) <= 1e-13
+
+
+@pytest.mark.parametrize("scheme", ["strang", "midpoint"])
+def test_mirror_symmetry(cfg1_full, scheme):
+    """sigma_x H(p_y) sigma_x = H(-p_y) and sigma_x maps v_in, u_out of p_y to those of -p_y
+    up to phases: n(p_x, p_y) = n(p_x, -p_y) (pin Q9)."""
+    n = cfg1_full[scheme][0].reshape(64, 64)
+    mirrored = n[1:][::-1]  # row j -> row 64 - j
+    assert np.max(np.abs(n[1:] - mirrored)) <= 1e-13
+
+
+def test_valley_k_minus_identity():
+    """K-: H = -sigma.P with the K- spinors gives the same n as K+ (sigma_z maps one onto the other)."""
+    idx = wl.subsample_indices(64, 16)
+    for s in ("strang", "midpoint"):
+        a = oracle.solve_grid(F1, G1, 4000, s, valley=1, idx=idx)[0]
+        b = oracle.solve_grid(F1, G1, 4000, s, valley=-1, idx=idx)[0]
+        assert np.max(np.abs(a - b)) <= 1e-14
+
+
+def test_config1_density_in_range(cfg1_full):
+    """Both schemes give the same total density to O(dt^2) on config 1."""
+    rs = oracle.density(G1, cfg1_full["strang"][0])
+    rm = oracle.density(G1, cfg1_full["midpoint"][0])
+    assert abs(rs - rm) / rs < 1e-4
+    assert 0.0 < rs < 1.0
+
+
+# ---------------------------------------------------------------------------
+# Convergence: second order in dt (Sec. III: local error O(dt^3))
+
+
+@pytest.mark.parametrize("scheme", ["strang", "midpoint"])
+def test_second_order_convergence(scheme):
+    """max |n_N - n_{N/2}| falls by 4 per halving of dt (pin Q3)."""
+    idx = wl.subsample_indices(64, 8)
+    ns = [oracle.solve_grid(F1, G1, N, scheme, idx=idx)[0] for N in (2000, 4000, 8000, 16000)]
+    d = [np.max(np.abs(ns[i + 1] - ns[i])) for i in range(3)]
+    for a, b in zip(d[:-1], d[1:]):
+        assert 3.8 < a / b < 4.2, d
+
+
+def test_cross_scheme_difference_is_second_order():
+    """Strang and midpoint discretise the same equation: their difference falls by 4 per halving (pin Q8)."""
+    idx = wl.subsample_indices(64, 8)
+    d = []
+    for N in (2000, 4000, 8000):
+        a = oracle.solve_grid(F1, G1, N, "strang", idx=idx)[0]
+        b = oracle.solve_grid(F1, G1, N, "midpoint", idx=idx)[0]
+        d.append(np.max(np.abs(a - b)))
+    assert 3.8 < d[0] / d[1] < 4.2 and 3.8 < d[1] / d[2] < 4.2, d
+
+
+# ---------------------------------------------------------------------------
+# Continuum pins
+
+
+def test_continuum_dop853_richardson():
+    """Richardson extrapolation of the oracle (N, 2N) agrees with a high-accuracy DOP853
+    integration of i dpsi/dt = sigma.(p + A) psi, with A itself integrated from E (pin Q7)."""
+    Efun, T = sin2_E(0.1, 0.5, 8)
+
+    def rhs(t, y):
+        psi = y[0:2] + 1j * y[2:4]
+        A = y[4]
+        d = -1j * ((SX * (px + A) + SY * py) @ psi)
+        return [d[0].real, d[1].real, d[0].imag, d[1].imag, -Efun(t)]
+
+    for px, py in [(0.25, 0.125), (-0.5, 0.3125), (0.0625, -0.0625)]:
+        E = math.hypot(px, py)
+        v = np.array([-px + 1j * py, E]) / (math.sqrt(2) * E)
+        sol = si.solve_ivp(rhs, (0, T), [v[0].real, v[1].real, v[0].imag, v[1].imag, 0.0], method="DOP853",
+                           rtol=1e-13, atol=1e-15)
+        y = sol.y[:, -1]
+        psi = y[0:2] + 1j * y[2:4]
+        Px = px + y[4]
+        Eo = math.hypot(Px, py)
+        u = np.array([Eo, Px + 1j * py]) / (math.sqrt(2) * Eo)
+        n_c = abs(np.vdot(u, psi)) ** 2
+        for s in ("strang", "midpoint"):
+            n1 = oracle.solve_points(F1, [px], [py], 16000, s)[0][0]
+            n2 = oracle.solve_points(F1, [px], [py], 32000, s)[0][0]
+            n_r = (4 * n2 - n1) / 3
+            assert abs(n_r - n_c) <= 1e-9 * max(n_c, 1e-3), (s, px, py, n_r, n_c)
+
+
+def test_landau_zener_constant_field():
+    """Constant field E0 = 0.2 on [0, 200]: P_x sweeps through 0 once for 0 < p_x < 40; far from the
+    turn-on the pair density is the Landau-Zener value exp(-pi p_y^2 / E0) (pin Q5).  p_x < 0 never
+    crosses, which fixes the sign of A = -int E."""
+    f = wl.constant(0.2, 200.0)
+    N = 40000
+    pxs = np.array([2.0, 2.5, 3.0, 3.5, 3.9375])
+    pys = np.array([0.0625, 0.25, 0.5])
+    PX, PY = np.meshgrid(pxs, pys)
+    n = oracle.solve_points(f, PX.ravel(), PY.ravel(), N, "strang")[0].reshape(PX.shape)
+    lz = np.exp(-math.pi * PY ** 2 / 0.2)
+    dev = np.abs(n - lz).max(axis=0)  # per p_x
+    assert dev.max() <= 2e-3, dev
+    assert dev[-1] < dev[0]  # deviation falls as the crossing moves away from the turn-on
+    n_neg = oracle.solve_points(f, [-1.0], [0.25], N, "strang")[0][0]
+    assert n_neg < 1e-3
+    nm = oracle.solve_points(f, PX.ravel(), PY.ravel(), N, "midpoint")[0].reshape(PX.shape)
+    assert np.abs(nm - lz).max() <= 2e-3
+
+
+def test_weak_field_first_order_perturbation():
+    """Weak field: first-order perturbation theory in V = sigma_x A gives
+    n = p_y^2 / (4 |p|^4) |int E(t) e^{2i|p|t} dt|^2 (A(0) = A(T) = 0), with relative
+    corrections O(E0) (pin Q6)."""
+    E0 = 1e-4
+    Efun, T = sin2_E(E0, 0.5, 8)
+    f = wl.sin2(E0, 0.5, 8)
+    pts = [(0.25, 0.0625), (0.1875, 0.125), (0.125, 0.1875), (-0.25, 0.125)]
+    n = oracle.solve_points(f, [p[0] for p in pts], [p[1] for p in pts], 16000, "strang")[0]
+    for (px, py), nn in zip(pts, n):
+        p = math.hypot(px, py)
+        w = 2 * p
+        c = si.quad(Efun, 0, T, weight="cos", wvar=w, limit=400)[0]
+        s = si.quad(Efun, 0, T, weight="sin", wvar=w, limit=400)[0]
+        n_pt = py ** 2 / (4 * p ** 4) * (c * c + s * s)
+        assert abs(nn / n_pt - 1) <= 5e-3, (px, py, nn, n_pt)
