@@ -1,0 +1,188 @@
+/*
+ * pd.h -- C ABI of libpd, the gfx950 (MI355X) solver for electron-hole pair
+ * production in graphene by split-operator propagation of the massless 2D
+ * Dirac equation in momentum space (Fillion-Gourdeau et al., arXiv:1607.03062).
+ *
+ * What a solve computes (Sec. II, Eq. (1); Sec. III, Eqs. (9)-(13)):
+ *   for every point p of a uniform momentum grid, the negative-energy state
+ *   v_in(p) of sigma.(p + A(t_i)) is advanced by N short-time steps of the
+ *   equation i d/dt psi = sigma.(p + A(t)) psi (Sec. II, Eq. (2), valley K+,
+ *   hbar = v_F = e = 1), then projected on the positive-energy state
+ *   u_out(p) of sigma.(p + A(t_f)):  n(p) = |u_out^dagger psi(t_f)|^2  (unit
+ *   spinors, so 0 <= n <= 1), and the pair density is
+ *   rho = 4 * dx * dy / (2 pi)^2 * sum_p n(p)  (rectangle rule on the grid;
+ *   the factor 4 counts spin and valley).
+ *
+ * Conventions shared by every entry point:
+ *   - Grid: p_x[i] = px_min + i * (px_max - px_min) / nx, i < nx (same for y);
+ *     point index k = j * nx + i (x fastest); n(p) is laid out [ny][nx].
+ *   - Steps: dt = (t_f - t_i) / N; step k (0 <= k < N) uses the vector
+ *     potential at its midpoint t_i + (k + 1/2) dt (Sec. III, Eqs. (11)-(12)).
+ *   - A point where |p + A(t_i)| = 0 or |p + A(t_f)| = 0 has no defined
+ *     adiabatic spinor; it gets n = 0 and is counted in pd_info.n_masked.
+ *   - Every call returns a pd_status; nothing crosses the ABI as an exception.
+ *     The message of the last failure on the calling thread is returned by
+ *     pd_last_error().
+ *   - Device pointers are HIP device pointers of the device that was current
+ *     when the field was first set; a stream is a hipStream_t passed as void*
+ *     (NULL = the default stream).  All GPU work of a call is enqueued on its
+ *     stream.
+ *   - A handle is not thread-safe: calls on one handle must not overlap.
+ */
+#ifndef PD_H_
+#define PD_H_
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pd_grid_s* pd_grid;
+
+typedef enum {
+  PD_OK = 0,
+  PD_ERR_INVALID = 1,     /* an argument is out of range, or dt * E_max > pi */
+  PD_ERR_STATE = 2,       /* call out of order (e.g. pd_density before the last step) */
+  PD_ERR_NOMEM = 3,       /* a device or host allocation failed */
+  PD_ERR_DEVICE = 4,      /* a HIP call failed (no device, launch failure, ...) */
+  PD_ERR_UNSUPPORTED = 5  /* a valid request this build does not implement */
+} pd_status;
+
+typedef enum {
+  PD_FP64 = 0, /* every step in FP64 */
+  PD_FP32 = 1  /* precision form: FP32 state and rotations; FP64 time, field table,
+                  rotation angles, projection and density sum; the state is
+                  renormalised every 1024 absolute steps (the exact step is unitary,
+                  Sec. III) */
+} pd_precision;
+
+typedef enum {
+  /* exp(-i dt py sy/2) exp(-i dt (px + A) sx) exp(-i dt py sy/2): the midpoint
+     Hamiltonian of Sec. III split into its sigma_y and sigma_x parts */
+  PD_SCHEME_STRANG = 0,
+  /* the paper's step, exp(-i dt sigma.P(t_{k+1/2})) in the closed 2x2 form of
+     Sec. III, Eq. (13) */
+  PD_SCHEME_MIDPOINT = 1
+} pd_scheme;
+
+typedef enum {
+  PD_FIELD_SIN2 = 0,     /* E(t) = E0 sin^2(pi t/T) sin(omega t), T = cycles 2 pi/omega, t in [0, T] */
+  PD_FIELD_CONSTANT = 1, /* E(t) = E0 on [0, t_end] */
+  PD_FIELD_TABLE = 2,    /* caller's A at the N step midpoints, with t_i, t_f, A_in, A_out */
+  PD_FIELD_PULSE = 3     /* the rise / flat / fall laser pulse of Sec. IV, Eq. (14), on [0, duration]:
+                            E0 sin^2(omega_rise t) cos(omega t + phi) for t < pi/(2 omega_rise),
+                            E0 cos^2(omega_fall (t - duration + pi/(2 omega_fall))) cos(omega t + phi)
+                            over the last pi/(2 omega_fall), E0 cos(omega t + phi) between */
+} pd_field_kind;
+
+/* A homogeneous field along x in the gauge A_0 = 0, E = -dA/dt
+   (Sec. II, after Eq. (2)); A(t) = -int_{t_i}^{t} E.  Only the members of the
+   chosen kind are read.  The struct and A_mid are copied during the call. */
+typedef struct {
+  int kind;                 /* pd_field_kind */
+  double E0, omega;         /* SIN2, PULSE */
+  int cycles;               /* SIN2: >= 2 */
+  double t_end;             /* CONSTANT: > 0 */
+  const double* A_mid;      /* TABLE: host array of n_table = N values A(t_i + (k + 1/2) dt) */
+  long long n_table;        /* TABLE */
+  double t_i, t_f;          /* TABLE: t_f > t_i */
+  double A_in, A_out;       /* TABLE: A(t_i), A(t_f) */
+  double phi;               /* PULSE: carrier phase */
+  double omega_rise;        /* PULSE: > 0 */
+  double omega_fall;        /* PULSE: > 0 */
+  double duration;          /* PULSE: >= pi/(2 omega_rise) + pi/(2 omega_fall) */
+} pd_field;
+
+typedef struct {
+  long long n_points;       /* nx * ny */
+  long long n_steps;        /* N */
+  long long steps_done;     /* steps applied so far */
+  long long n_masked;       /* points with |p + A_in| = 0 or |p + A_out| = 0 */
+  double dt, t_i, t_f, A_in, A_out;
+  double E_max;             /* max over grid and step midpoints of |p + A| (also A_in, A_out) */
+  double A_min, A_max;      /* range of A over the midpoints and the end points */
+  int precision;            /* pd_precision */
+  int scheme;               /* pd_scheme */
+  int points_per_lane;      /* launch shape in use */
+  int block_threads;
+  size_t device_bytes;      /* device memory the handle owns */
+} pd_info;
+
+/* Create a solver on an nx x ny node grid (1 <= nx, ny <= 65536; finite ranges
+   with max > min).  Allocates nothing on the device.  *out receives the handle;
+   it is NULL on failure. */
+pd_status pd_create_grid(int nx, int ny, double px_min, double px_max, double py_min, double py_max,
+                         int precision, int scheme, pd_grid* out);
+
+/* Validate a field and step count without touching the device: fills *out
+   (dt, E_max, A range, n_masked ...) and returns PD_ERR_INVALID if the step
+   would violate dt * E_max <= pi (Sec. III, last paragraph) or an argument is
+   out of range.  out may be NULL. */
+pd_status pd_check_field(pd_grid g, const pd_field* f, long long n_steps, pd_info* out);
+
+/* Host-only query of the field sampling used by a solve: writes the n_steps
+   values A(t_i + (k + 1/2) dt) to the host array A_mid (may be NULL) and the
+   end values to *t_i, *t_f, *A_in, *A_out (each may be NULL).  No device work. */
+pd_status pd_sample_field(const pd_field* f, long long n_steps, double* A_mid, double* t_i, double* t_f,
+                          double* A_in, double* A_out);
+
+/* Set the field and the number of steps N >= 1: builds the per-step FP64
+   table of the field on the host (A at the step midpoints, Sec. III,
+   Eqs. (11)-(12)), uploads it with a blocking copy, allocates the handle's
+   device buffers on first use and resets the solve to t_i (steps_done = 0).
+   Same validation as pd_check_field. */
+pd_status pd_set_field(pd_grid g, const pd_field* f, long long n_steps);
+
+/* Restart the solve at t_i (steps_done = 0) with the field already set; the
+   device table is kept.  PD_ERR_STATE before pd_set_field. */
+pd_status pd_rewind(pd_grid g);
+
+/* Advance up to max_steps steps (max_steps < 0: all remaining).  Enqueued on
+   stream, returns without waiting.  A call that starts at step 0 and runs to N
+   keeps every spinor in registers; otherwise the state is kept in device
+   memory between calls (the handle's own buffer, or the one given to
+   pd_bind_state).  The call that reaches step N also projects on u_out and
+   stores n(p) in the handle's device buffer.  PD_ERR_STATE before
+   pd_set_field or after the last step. */
+pd_status pd_propagate(pd_grid g, long long max_steps, void* stream);
+
+/* After the last step: sums n(p) into rho with a fixed-order reduction (the
+   result does not depend on the launch shape), optionally copies n(p) to
+   n_out (n_points doubles; device memory if n_out_on_device, else host
+   memory), and writes rho to the host double *rho_out (may be NULL).  When
+   rho_out or a host n_out is given the call waits for stream. */
+pd_status pd_density(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, void* stream);
+
+/* Bytes of device state a chunked solve keeps between pd_propagate calls
+   (3 FP64 or FP32 values per point for PD_SCHEME_STRANG, 4 for
+   PD_SCHEME_MIDPOINT). */
+size_t pd_state_bytes(pd_grid g);
+
+/* Use caller-owned device memory (at least pd_state_bytes, 256-byte aligned)
+   for the chunked state instead of the handle's own buffer.  The caller keeps
+   it alive until the handle is destroyed or another buffer is bound.
+   dev_ptr = NULL returns to the handle's own buffer. */
+pd_status pd_bind_state(pd_grid g, void* dev_ptr, size_t bytes);
+
+/* Override the launch shape: points_per_lane in {1, 2, 4}, block_threads in
+   {64, 128, 256}; 0 keeps the current value.  Results do not depend on the
+   launch shape (bit for bit). */
+pd_status pd_set_launch(pd_grid g, int points_per_lane, int block_threads);
+
+pd_status pd_get_info(pd_grid g, pd_info* out);
+
+/* Release the handle and the device memory it owns.  NULL is a no-op. */
+void pd_destroy_grid(pd_grid g);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* pd_last_error(void);
+
+/* Library version string. */
+const char* pd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PD_H_ */

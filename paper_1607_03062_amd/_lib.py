@@ -1,0 +1,263 @@
+"""ctypes binding of libpd (argument marshalling only: every step of a solve
+runs in the library's HIP kernels).  Names follow include/pd.h."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpd.so")
+
+PD_OK, PD_ERR_INVALID, PD_ERR_STATE, PD_ERR_NOMEM, PD_ERR_DEVICE, PD_ERR_UNSUPPORTED = range(6)
+PD_FP64, PD_FP32 = 0, 1
+PD_SCHEME_STRANG, PD_SCHEME_MIDPOINT = 0, 1
+PD_FIELD_SIN2, PD_FIELD_CONSTANT, PD_FIELD_TABLE, PD_FIELD_PULSE = 0, 1, 2, 3
+
+PRECISIONS = {"fp64": PD_FP64, "fp32": PD_FP32}
+SCHEMES = {"strang": PD_SCHEME_STRANG, "midpoint": PD_SCHEME_MIDPOINT}
+FIELD_KINDS = {"sin2": PD_FIELD_SIN2, "constant": PD_FIELD_CONSTANT, "table": PD_FIELD_TABLE,
+               "pulse": PD_FIELD_PULSE}
+STATUS_NAMES = {0: "PD_OK", 1: "PD_ERR_INVALID", 2: "PD_ERR_STATE", 3: "PD_ERR_NOMEM", 4: "PD_ERR_DEVICE",
+                5: "PD_ERR_UNSUPPORTED"}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+class pd_field(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int),
+        ("E0", ctypes.c_double),
+        ("omega", ctypes.c_double),
+        ("cycles", ctypes.c_int),
+        ("t_end", ctypes.c_double),
+        ("A_mid", _dp),
+        ("n_table", ctypes.c_longlong),
+        ("t_i", ctypes.c_double),
+        ("t_f", ctypes.c_double),
+        ("A_in", ctypes.c_double),
+        ("A_out", ctypes.c_double),
+        ("phi", ctypes.c_double),
+        ("omega_rise", ctypes.c_double),
+        ("omega_fall", ctypes.c_double),
+        ("duration", ctypes.c_double),
+    ]
+
+
+class pd_info(ctypes.Structure):
+    _fields_ = [
+        ("n_points", ctypes.c_longlong),
+        ("n_steps", ctypes.c_longlong),
+        ("steps_done", ctypes.c_longlong),
+        ("n_masked", ctypes.c_longlong),
+        ("dt", ctypes.c_double),
+        ("t_i", ctypes.c_double),
+        ("t_f", ctypes.c_double),
+        ("A_in", ctypes.c_double),
+        ("A_out", ctypes.c_double),
+        ("E_max", ctypes.c_double),
+        ("A_min", ctypes.c_double),
+        ("A_max", ctypes.c_double),
+        ("precision", ctypes.c_int),
+        ("scheme", ctypes.c_int),
+        ("points_per_lane", ctypes.c_int),
+        ("block_threads", ctypes.c_int),
+        ("device_bytes", ctypes.c_size_t),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class PDError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        self.status = status
+        self.message = message
+        super().__init__("%s failed with %s: %s" % (where, STATUS_NAMES.get(status, status), message))
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point of include/pd.h
+SIGNATURES = [
+    ("pd_create_grid", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(_vp)]),
+    ("pd_check_field", ctypes.c_int, [_vp, ctypes.POINTER(pd_field), ctypes.c_longlong, ctypes.POINTER(pd_info)]),
+    ("pd_sample_field", ctypes.c_int, [ctypes.POINTER(pd_field), ctypes.c_longlong, _dp, _dp, _dp, _dp, _dp]),
+    ("pd_set_field", ctypes.c_int, [_vp, ctypes.POINTER(pd_field), ctypes.c_longlong]),
+    ("pd_rewind", ctypes.c_int, [_vp]),
+    ("pd_propagate", ctypes.c_int, [_vp, ctypes.c_longlong, _vp]),
+    ("pd_density", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _vp]),
+    ("pd_state_bytes", ctypes.c_size_t, [_vp]),
+    ("pd_bind_state", ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    ("pd_set_launch", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    ("pd_get_info", ctypes.c_int, [_vp, ctypes.POINTER(pd_info)]),
+    ("pd_destroy_grid", None, [_vp]),
+    ("pd_last_error", ctypes.c_char_p, []),
+    ("pd_version", ctypes.c_char_p, []),
+]
+
+
+def load() -> ctypes.CDLL:
+    """Load the in-tree libpd.so.  Raises if it has not been built: there is no
+    fallback path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libpd.so is not built (%s); run `python -m paper_1607_03062_amd.build` "
+                              "or __graft_entry__.build()" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(status: int, where: str):
+    if status != PD_OK:
+        raise PDError(status, where, load().pd_last_error().decode())
+
+
+def stream_handle(stream) -> int | None:
+    """hipStream_t of a torch stream, an int handle, or None (default stream)."""
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def make_field(field: dict, n_steps: int):
+    """pd_field from a field dict; returns (struct, keep-alive)."""
+    f = pd_field()
+    keep = None
+    kind = field["kind"]
+    f.kind = FIELD_KINDS[kind]
+    f.E0 = float(field.get("E0", 0.0))
+    f.omega = float(field.get("omega", 0.0))
+    f.cycles = int(field.get("cycles", 0))
+    f.t_end = float(field.get("t_end", 0.0))
+    if kind == "table":
+        keep = np.ascontiguousarray(field["A_mid"], dtype=np.float64)
+        f.A_mid = keep.ctypes.data_as(_dp)
+        f.n_table = keep.shape[0]
+        f.t_i, f.t_f = float(field["t_i"]), float(field["t_f"])
+        f.A_in, f.A_out = float(field["A_in"]), float(field["A_out"])
+    f.phi = float(field.get("phi", 0.0))
+    f.omega_rise = float(field.get("omega_rise", 0.0))
+    f.omega_fall = float(field.get("omega_fall", 0.0))
+    f.duration = float(field.get("duration", 0.0))
+    return f, keep
+
+
+def sample_field(field: dict, n_steps: int):
+    """Host-side field sampling of the library: (A at the step midpoints, t_i, t_f, A_in, A_out)."""
+    f, keep = make_field(field, n_steps)
+    A = np.zeros(int(n_steps))
+    vals = [ctypes.c_double() for _ in range(4)]
+    check(load().pd_sample_field(ctypes.byref(f), int(n_steps), A.ctypes.data_as(_dp),
+                                 *[ctypes.byref(v) for v in vals]), "pd_sample_field")
+    return (A,) + tuple(v.value for v in vals)
+
+
+def _ptr_of(buf):
+    """(address, on_device) of a torch tensor or numpy array."""
+    if hasattr(buf, "data_ptr"):
+        return int(buf.data_ptr()), 1 if buf.is_cuda else 0
+    return int(buf.ctypes.data), 0
+
+
+class Solver:
+    """One momentum grid and its solve (pd_grid handle)."""
+
+    def __init__(self, nx, ny, px, py, precision="fp64", scheme="strang"):
+        lib = load()
+        h = _vp()
+        check(lib.pd_create_grid(int(nx), int(ny), float(px[0]), float(px[1]), float(py[0]), float(py[1]),
+                                 PRECISIONS[precision], SCHEMES[scheme], ctypes.byref(h)), "pd_create_grid")
+        self._h = h
+        self.nx, self.ny = int(nx), int(ny)
+        self.precision, self.scheme = precision, scheme
+
+    @classmethod
+    def for_grid(cls, grid: dict, precision="fp64", scheme="strang"):
+        return cls(grid["nx"], grid["ny"], grid["px"], grid["py"], precision, scheme)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def check_field(self, field: dict, n_steps: int) -> dict:
+        f, keep = make_field(field, n_steps)
+        info = pd_info()
+        check(load().pd_check_field(self._h, ctypes.byref(f), int(n_steps), ctypes.byref(info)), "pd_check_field")
+        return info.as_dict()
+
+    def set_field(self, field: dict, n_steps: int):
+        f, keep = make_field(field, n_steps)
+        check(load().pd_set_field(self._h, ctypes.byref(f), int(n_steps)), "pd_set_field")
+        return self
+
+    def rewind(self):
+        check(load().pd_rewind(self._h), "pd_rewind")
+        return self
+
+    def propagate(self, max_steps: int = -1, stream=None):
+        check(load().pd_propagate(self._h, int(max_steps), stream_handle(stream)), "pd_propagate")
+        return self
+
+    def density(self, n_out=None, want_rho: bool = True, stream=None):
+        """Returns rho (float) or None; fills n_out (torch device tensor or numpy array) if given."""
+        ptr, dev = (None, 0) if n_out is None else _ptr_of(n_out)
+        rho = ctypes.c_double()
+        check(load().pd_density(self._h, ptr, dev, ctypes.byref(rho) if want_rho else None,
+                                stream_handle(stream)), "pd_density")
+        return rho.value if want_rho else None
+
+    def solve(self, stream=None, n_out=None):
+        self.propagate(-1, stream)
+        return self.density(n_out, True, stream)
+
+    def state_bytes(self) -> int:
+        return int(load().pd_state_bytes(self._h))
+
+    def bind_state(self, buf=None):
+        if buf is None:
+            check(load().pd_bind_state(self._h, None, 0), "pd_bind_state")
+        else:
+            ptr, dev = _ptr_of(buf)
+            nbytes = buf.numel() * buf.element_size() if hasattr(buf, "numel") else buf.nbytes
+            check(load().pd_bind_state(self._h, ptr, nbytes), "pd_bind_state")
+        return self
+
+    def set_launch(self, points_per_lane: int = 0, block_threads: int = 0):
+        check(load().pd_set_launch(self._h, int(points_per_lane), int(block_threads)), "pd_set_launch")
+        return self
+
+    def info(self) -> dict:
+        info = pd_info()
+        check(load().pd_get_info(self._h, ctypes.byref(info)), "pd_get_info")
+        return info.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pd_destroy_grid(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False

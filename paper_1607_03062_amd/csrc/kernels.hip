@@ -1,0 +1,478 @@
+// gfx950 kernels of libpd: split-operator propagation of one spinor per momentum
+// point, projection on the final positive-energy state, and the density sum.
+//
+// One lane per momentum point (points_per_lane of them, strided by the block
+// size so loads and stores stay coalesced).  The per-step field row is the same
+// for every lane: it is read with uniform (scalar-unit) loads from the table in
+// global memory, so the vector ALUs only see the rotation arithmetic.
+//
+// Strang scheme (Sec. III, Eqs. (11)-(12), with the midpoint Hamiltonian
+// sigma_x P_x + sigma_y p_y split into its two parts):
+//   U_k = exp(-i dt py sy / 2) exp(-i dt (px + A_k) sx) exp(-i dt py sy / 2).
+// The kernel propagates the Bloch vector r of the pure state, psi psi^dagger =
+// (1 + r.sigma) / 2, which carries everything n(p) depends on (the global
+// phase of psi is unobservable): exp(-i a sx) rotates r by 2a about x and
+// exp(-i b sy) by 2b about y.  Since exp(-i dt (px + A_k) sx) =
+// exp(-i dt px sx) exp(-i dt A_k sx), every step is three plane rotations:
+// by 2 dt A_k about x (table row, same for all lanes), by 2 dt px about x and
+// by 2 dt py about y (per-point constants computed once); the half steps of
+// neighbouring steps are merged.  Each rotation costs four FMAs.
+// The projection on u_out is n = |u_out^dagger psi|^2 = (1 + r . r_u) / 2 with
+// r_u = P_out / |P_out| the Bloch vector of u_out (Sec. II, Eqs. (1), (3)).
+//
+// Midpoint scheme (Sec. III, Eq. (13)): per step the closed 2x2 form
+//   U = cos(dt E) I - i sigma.P sin(dt E) / E,  P = p + A_k,
+// acting on the spinor (a1 + i b1, a2 + i b2); cos - 1 and sin(x)/x are even
+// Taylor series in x = (dt E)^2 of an order chosen by the host.
+#include <hip/hip_runtime.h>
+
+#include "pd_internal.h"
+
+namespace pdx {
+namespace {
+
+constexpr long long kRenormEvery = 1024;  // FP32 form: renormalise after every 1024th step
+
+template <typename R>
+struct Row {
+  R h, s;
+};
+
+// Plane rotation of (u, v) by an angle with h = cos - 1, s = sin:
+//   u' = u + h u - s v,  v' = v + h v + s u.
+__device__ __forceinline__ void rotate(double& u, double& v, double h, double s) {
+  double nu = fma(h, u, fma(-s, v, u));
+  double nv = fma(h, v, fma(s, u, v));
+  u = nu;
+  v = nv;
+}
+
+// FP32 form: the small increment is formed first and added once, so the state
+// sees a single rounding per component per rotation.
+__device__ __forceinline__ void rotate(float& u, float& v, float h, float s) {
+  float du = fmaf(h, u, -(s * v));
+  float dv = fmaf(h, v, s * u);
+  u = u + du;
+  v = v + dv;
+}
+
+struct PointCoords {
+  double px, py;
+};
+
+__device__ __forceinline__ PointCoords coords(const SolveParams& p, long long idx) {
+  long long j = idx / p.nx;
+  long long i = idx - j * p.nx;
+  PointCoords c;
+  c.px = p.px_min + (double)i * p.dx;
+  c.py = p.py_min + (double)j * p.dy;
+  return c;
+}
+
+template <typename R, int PPL>
+__global__ void __launch_bounds__(256) strang_kernel(const SolveParams p) {
+  const long long base = (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x;
+  R x[PPL], y[PPL], z[PPL];
+  R hA[PPL], sA[PPL], hT[PPL], sT[PPL];  // rotations by 2 dt px about x and 2 dt py about y
+
+#pragma unroll
+  for (int q = 0; q < PPL; ++q) {
+    long long idx = base + (long long)q * blockDim.x;
+    if (idx >= p.npts) idx = p.npts - 1;  // tail lanes recompute a valid point and store nothing
+    PointCoords c = coords(p, idx);
+    double sa, ca, sb, cb;
+    sincos(p.dt * c.px, &sa, &ca);
+    sincos(p.dt * c.py, &sb, &cb);
+    hA[q] = (R)(-2.0 * sa * sa);
+    sA[q] = (R)(2.0 * sa * ca);
+    hT[q] = (R)(-2.0 * sb * sb);
+    sT[q] = (R)(2.0 * sb * cb);
+    if (p.load_state) {
+      const R* st = static_cast<const R*>(p.state);
+      x[q] = st[idx];
+      y[q] = st[p.npts + idx];
+      z[q] = st[2 * p.npts + idx];
+    } else {
+      // v_in: negative-energy eigenvector of sigma.P_in, Bloch vector -P_in/|P_in|
+      double Px = c.px + p.A_in;
+      double E = sqrt(Px * Px + c.py * c.py);
+      double rx = 0.0, ry = 0.0;
+      if (E > 0.0) {
+        rx = -Px / E;
+        ry = -c.py / E;
+      }
+      x[q] = (R)rx;
+      y[q] = (R)ry;
+      z[q] = (R)0;
+      // first half step exp(-i dt py sy / 2): rotation by dt py about y
+      double sh = sin(0.5 * p.dt * c.py);
+      R hH = (R)(-2.0 * sh * sh), sH = (R)sb;
+      rotate(z[q], x[q], hH, sH);
+    }
+  }
+
+  const Row<R>* __restrict__ tab = static_cast<const Row<R>*>(p.table);
+  long long k = p.k_begin;
+  const long long k_full = p.k_end < p.n_steps ? p.k_end : p.n_steps - 1;
+  while (k < k_full) {
+    long long seg = k_full;
+    if (sizeof(R) == 4) {
+      long long next = (k / kRenormEvery + 1) * kRenormEvery;
+      seg = next < k_full ? next : k_full;
+    }
+#pragma unroll 8
+    for (; k < seg; ++k) {
+      const Row<R> r = tab[k];
+#pragma unroll
+      for (int q = 0; q < PPL; ++q) {
+        rotate(y[q], z[q], r.h, r.s);
+        rotate(y[q], z[q], hA[q], sA[q]);
+        rotate(z[q], x[q], hT[q], sT[q]);
+      }
+    }
+    if (sizeof(R) == 4 && (k % kRenormEvery) == 0) {
+#pragma unroll
+      for (int q = 0; q < PPL; ++q) {
+        double X = x[q], Y = y[q], Z = z[q];
+        double nr = sqrt(X * X + Y * Y + Z * Z);
+        if (nr > 0.0) {
+          x[q] = (R)(X / nr);
+          y[q] = (R)(Y / nr);
+          z[q] = (R)(Z / nr);
+        }
+      }
+    }
+  }
+
+  if (p.k_end == p.n_steps) {
+    // last step: full sigma_x factor, then the closing half step about y
+    const Row<R> r = tab[p.n_steps - 1];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      long long idx = base + (long long)q * blockDim.x;
+      bool valid = idx < p.npts;
+      if (!valid) idx = p.npts - 1;
+      PointCoords c = coords(p, idx);
+      double sh = sin(0.5 * p.dt * c.py);
+      R hH = (R)(-2.0 * sh * sh), sH = (R)sin(p.dt * c.py);
+      rotate(y[q], z[q], r.h, r.s);
+      rotate(y[q], z[q], hA[q], sA[q]);
+      rotate(z[q], x[q], hH, sH);
+      // projection on u_out: n = (E_out + P_out . r) / (2 E_out)
+      double Pxi = c.px + p.A_in, Pxo = c.px + p.A_out;
+      double Ei = sqrt(Pxi * Pxi + c.py * c.py), Eo = sqrt(Pxo * Pxo + c.py * c.py);
+      double X = x[q], Y = y[q];
+      if (sizeof(R) == 4) {
+        double Z = z[q];
+        double nr = sqrt(X * X + Y * Y + Z * Z);
+        if (nr > 0.0) {
+          X = X / nr;
+          Y = Y / nr;
+        }
+      }
+      double n = 0.0;
+      if (Ei > 0.0 && Eo > 0.0) {
+        double dot = Pxo * X + c.py * Y;
+        n = (Eo + dot) / (2.0 * Eo);
+      }
+      if (valid) p.n_out[idx] = n;
+    }
+  } else if (p.store_state) {
+    R* st = static_cast<R*>(p.state);
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      long long idx = base + (long long)q * blockDim.x;
+      if (idx < p.npts) {
+        st[idx] = x[q];
+        st[p.npts + idx] = y[q];
+        st[2 * p.npts + idx] = z[q];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Midpoint scheme: spinor state, Taylor coefficients per point and step.
+
+template <int J>
+struct Taylor {
+  // cos(sqrt x) - 1 = sum_{j>=1} (-x)^j / (2j)!;  sin(sqrt x)/sqrt x = sum_{j>=0} (-x)^j / (2j+1)!
+  __device__ __forceinline__ static double h(double x) {
+    double acc = coef_h(J);
+#pragma unroll
+    for (int j = J - 1; j >= 1; --j) acc = fma(acc, x, coef_h(j));
+    return acc * x;
+  }
+  __device__ __forceinline__ static double s(double x) {
+    double acc = coef_s(J);
+#pragma unroll
+    for (int j = J - 1; j >= 0; --j) acc = fma(acc, x, coef_s(j));
+    return acc;
+  }
+  __device__ __forceinline__ static float h(float x) {
+    float acc = (float)coef_h(J);
+#pragma unroll
+    for (int j = J - 1; j >= 1; --j) acc = fmaf(acc, x, (float)coef_h(j));
+    return acc * x;
+  }
+  __device__ __forceinline__ static float s(float x) {
+    float acc = (float)coef_s(J);
+#pragma unroll
+    for (int j = J - 1; j >= 0; --j) acc = fmaf(acc, x, (float)coef_s(j));
+    return acc;
+  }
+  // (-1)^j / (2j)!  and  (-1)^j / (2j+1)!, folded by the compiler
+  __device__ __forceinline__ static constexpr double coef_h(int j) {
+    double f = 1.0;
+    for (int m = 2; m <= 2 * j; ++m) f *= m;
+    return (j % 2 ? -1.0 : 1.0) / f;
+  }
+  __device__ __forceinline__ static constexpr double coef_s(int j) {
+    double f = 1.0;
+    for (int m = 2; m <= 2 * j + 1; ++m) f *= m;
+    return (j % 2 ? -1.0 : 1.0) / f;
+  }
+};
+
+// psi1' = c psi1 + (-i al - be) psi2 ;  psi2' = c psi2 + (be - i al) psi1, with c = 1 + h.
+__device__ __forceinline__ void midpoint_update(double& a1, double& b1, double& a2, double& b2, double h, double al,
+                                                double be) {
+  double na1 = fma(h, a1, fma(-be, a2, fma(al, b2, a1)));
+  double nb1 = fma(h, b1, fma(-be, b2, fma(-al, a2, b1)));
+  double na2 = fma(h, a2, fma(be, a1, fma(al, b1, a2)));
+  double nb2 = fma(h, b2, fma(be, b1, fma(-al, a1, b2)));
+  a1 = na1;
+  b1 = nb1;
+  a2 = na2;
+  b2 = nb2;
+}
+
+__device__ __forceinline__ void midpoint_update(float& a1, float& b1, float& a2, float& b2, float h, float al,
+                                                float be) {
+  float da1 = fmaf(h, a1, fmaf(-be, a2, al * b2));
+  float db1 = fmaf(h, b1, fmaf(-be, b2, -(al * a2)));
+  float da2 = fmaf(h, a2, fmaf(be, a1, al * b1));
+  float db2 = fmaf(h, b2, fmaf(be, b1, -(al * a1)));
+  a1 += da1;
+  b1 += db1;
+  a2 += da2;
+  b2 += db2;
+}
+
+template <typename R, int J, int PPL>
+__global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
+  const long long base = (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x;
+  R a1[PPL], b1[PPL], a2[PPL], b2[PPL];
+  double X0[PPL], Y[PPL], Y2[PPL];
+#pragma unroll
+  for (int q = 0; q < PPL; ++q) {
+    long long idx = base + (long long)q * blockDim.x;
+    if (idx >= p.npts) idx = p.npts - 1;
+    PointCoords c = coords(p, idx);
+    X0[q] = p.dt * c.px;
+    Y[q] = p.dt * c.py;
+    Y2[q] = Y[q] * Y[q];
+    if (p.load_state) {
+      const R* st = static_cast<const R*>(p.state);
+      a1[q] = st[idx];
+      b1[q] = st[p.npts + idx];
+      a2[q] = st[2 * p.npts + idx];
+      b2[q] = st[3 * p.npts + idx];
+    } else {
+      // v_in = (-Px + i py, E) / (sqrt(2) E)   (Sec. II, Eq. (3), unit norm)
+      double Px = c.px + p.A_in;
+      double E = sqrt(Px * Px + c.py * c.py);
+      double d = 1.4142135623730951 * E;
+      bool ok = E > 0.0;
+      a1[q] = ok ? (R)(-Px / d) : (R)0;
+      b1[q] = ok ? (R)(c.py / d) : (R)0;
+      a2[q] = ok ? (R)(E / d) : (R)0;
+      b2[q] = (R)0;
+    }
+  }
+  const double* __restrict__ tab = static_cast<const double*>(p.table);
+  long long k = p.k_begin;
+  while (k < p.k_end) {
+    long long seg = p.k_end;
+    if (sizeof(R) == 4) {
+      long long next = (k / kRenormEvery + 1) * kRenormEvery;
+      seg = next < p.k_end ? next : p.k_end;
+    }
+#pragma unroll 4
+    for (; k < seg; ++k) {
+      const double d = tab[k];
+#pragma unroll
+      for (int q = 0; q < PPL; ++q) {
+        double X = X0[q] + d;           // dt (px + A_k), FP64 in both forms
+        double x = fma(X, X, Y2[q]);    // (dt E)^2
+        R xr = (R)x;
+        R h = Taylor<J>::h(xr);
+        R sp = Taylor<J>::s(xr);        // sin(dt E) / (dt E)
+        R al = sp * (R)X, be = sp * (R)Y[q];
+        midpoint_update(a1[q], b1[q], a2[q], b2[q], h, al, be);
+      }
+    }
+    if (sizeof(R) == 4 && (k % kRenormEvery) == 0 && k < p.n_steps) {
+#pragma unroll
+      for (int q = 0; q < PPL; ++q) {
+        double A1 = a1[q], B1 = b1[q], A2 = a2[q], B2 = b2[q];
+        double nr = sqrt(A1 * A1 + B1 * B1 + A2 * A2 + B2 * B2);
+        if (nr > 0.0) {
+          a1[q] = (R)(A1 / nr);
+          b1[q] = (R)(B1 / nr);
+          a2[q] = (R)(A2 / nr);
+          b2[q] = (R)(B2 / nr);
+        }
+      }
+    }
+  }
+  if (p.k_end == p.n_steps) {
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      long long idx = base + (long long)q * blockDim.x;
+      bool valid = idx < p.npts;
+      if (!valid) idx = p.npts - 1;
+      PointCoords c = coords(p, idx);
+      double Pxi = c.px + p.A_in, Pxo = c.px + p.A_out;
+      double Ei = sqrt(Pxi * Pxi + c.py * c.py), Eo = sqrt(Pxo * Pxo + c.py * c.py);
+      double A1 = a1[q], B1 = b1[q], A2 = a2[q], B2 = b2[q];
+      double n = 0.0;
+      if (Ei > 0.0 && Eo > 0.0) {
+        // u_out = (E, Px + i py) / (sqrt(2) E):  sqrt(2) E amp = (E a1 + Px a2 + py b2) + i (E b1 + Px b2 - py a2)
+        double re = (Eo * A1 + Pxo * A2) + c.py * B2;
+        double im = (Eo * B1 + Pxo * B2) - c.py * A2;
+        n = (re * re + im * im) / (2.0 * Eo * Eo);
+        if (sizeof(R) == 4) n = n / (A1 * A1 + B1 * B1 + A2 * A2 + B2 * B2);
+      }
+      if (valid) p.n_out[idx] = n;
+    }
+  } else if (p.store_state) {
+    R* st = static_cast<R*>(p.state);
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      long long idx = base + (long long)q * blockDim.x;
+      if (idx < p.npts) {
+        st[idx] = a1[q];
+        st[p.npts + idx] = b1[q];
+        st[2 * p.npts + idx] = a2[q];
+        st[3 * p.npts + idx] = b2[q];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Density: rho = scale * sum n, in a fixed order that depends only on npts.
+
+constexpr int kRedThreads = 256;
+constexpr int kRedPerThread = 8;
+constexpr long long kRedTile = (long long)kRedThreads * kRedPerThread;
+
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double wave_part[kRedThreads / 64];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) wave_part[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < kRedThreads / 64; ++w) s += wave_part[w];
+  }
+  return s;
+}
+
+__global__ void __launch_bounds__(kRedThreads) density_tiles(const double* __restrict__ n, long long npts,
+                                                             double* __restrict__ partial) {
+  const long long base = (long long)blockIdx.x * kRedTile + threadIdx.x;
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < kRedPerThread; ++q) {
+    long long i = base + (long long)q * kRedThreads;
+    if (i < npts) s += n[i];
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kRedThreads) density_finish(const double* __restrict__ partial, long long count,
+                                                              double scale, double* __restrict__ rho) {
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < count; i += kRedThreads) s += partial[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) *rho = scale * s;
+}
+
+template <typename R, int PPL>
+hipError_t launch_strang(int block, const SolveParams& p, hipStream_t stream) {
+  long long per_block = (long long)block * PPL;
+  long long blocks = (p.npts + per_block - 1) / per_block;
+  hipLaunchKernelGGL((strang_kernel<R, PPL>), dim3((unsigned)blocks), dim3(block), 0, stream, p);
+  return hipGetLastError();
+}
+
+template <typename R, int J, int PPL>
+hipError_t launch_midpoint(int block, const SolveParams& p, hipStream_t stream) {
+  long long per_block = (long long)block * PPL;
+  long long blocks = (p.npts + per_block - 1) / per_block;
+  hipLaunchKernelGGL((midpoint_kernel<R, J, PPL>), dim3((unsigned)blocks), dim3(block), 0, stream, p);
+  return hipGetLastError();
+}
+
+template <typename R, int J>
+hipError_t midpoint_ppl(int ppl, int block, const SolveParams& p, hipStream_t stream) {
+  switch (ppl) {
+    case 1: return launch_midpoint<R, J, 1>(block, p, stream);
+    case 2: return launch_midpoint<R, J, 2>(block, p, stream);
+    default: return launch_midpoint<R, J, 4>(block, p, stream);
+  }
+}
+
+}  // namespace
+
+size_t state_values_per_point(int scheme) { return scheme == PD_SCHEME_MIDPOINT ? 4 : 3; }
+
+long long density_partials(long long npts) { return (npts + kRedTile - 1) / kRedTile; }
+
+hipError_t launch_propagate(int scheme, int precision, int ppl, int block, int taylor, const SolveParams& p,
+                            hipStream_t stream) {
+  if (scheme == PD_SCHEME_STRANG) {
+    if (precision == PD_FP32) {
+      switch (ppl) {
+        case 1: return launch_strang<float, 1>(block, p, stream);
+        case 2: return launch_strang<float, 2>(block, p, stream);
+        default: return launch_strang<float, 4>(block, p, stream);
+      }
+    }
+    switch (ppl) {
+      case 1: return launch_strang<double, 1>(block, p, stream);
+      case 2: return launch_strang<double, 2>(block, p, stream);
+      default: return launch_strang<double, 4>(block, p, stream);
+    }
+  }
+  if (precision == PD_FP32) {
+    switch (taylor) {
+      case 3: return midpoint_ppl<float, 3>(ppl, block, p, stream);
+      case 5: return midpoint_ppl<float, 5>(ppl, block, p, stream);
+      default: return midpoint_ppl<float, 9>(ppl, block, p, stream);
+    }
+  }
+  switch (taylor) {
+    case 5: return midpoint_ppl<double, 5>(ppl, block, p, stream);
+    case 8: return midpoint_ppl<double, 8>(ppl, block, p, stream);
+    default: return midpoint_ppl<double, 14>(ppl, block, p, stream);
+  }
+}
+
+hipError_t launch_density(const double* n, long long npts, double scale, double* partial, double* rho,
+                          hipStream_t stream) {
+  long long tiles = density_partials(npts);
+  hipLaunchKernelGGL(density_tiles, dim3((unsigned)tiles), dim3(kRedThreads), 0, stream, n, npts, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(density_finish, dim3(1), dim3(kRedThreads), 0, stream, partial, tiles, scale, rho);
+  return hipGetLastError();
+}
+
+}  // namespace pdx

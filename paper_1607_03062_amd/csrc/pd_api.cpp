@@ -1,0 +1,398 @@
+// C ABI of libpd (declared and documented in include/pd.h).
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pd.h"
+#include "pd_internal.h"
+
+using namespace pdx;
+
+namespace {
+
+thread_local std::string g_error;
+
+pd_status fail(pd_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return s;
+}
+
+pd_status ok() { return PD_OK; }
+
+constexpr double kPi = 3.14159265358979323846;
+
+}  // namespace
+
+struct pd_grid_s {
+  Grid grid;
+  int precision = PD_FP64;
+  int scheme = PD_SCHEME_STRANG;
+  int points_per_lane = 2;
+  int block_threads = 256;
+
+  bool field_set = false;
+  FieldTables field;
+  long long n_masked = 0;
+  long long steps_done = 0;
+  int taylor = 0;
+
+  int device = -1;
+  void* d_table = nullptr;
+  size_t table_bytes = 0;
+  double* d_n = nullptr;
+  double* d_partial = nullptr;
+  double* d_rho = nullptr;
+  void* d_state_own = nullptr;
+  void* d_state_bound = nullptr;
+  size_t state_bound_bytes = 0;
+
+  size_t device_bytes() const {
+    size_t b = table_bytes;
+    if (d_n) b += (size_t)grid.points() * sizeof(double);
+    if (d_partial) b += (size_t)density_partials(grid.points()) * sizeof(double) + sizeof(double);
+    if (d_state_own) b += state_bytes();
+    return b;
+  }
+  size_t state_bytes() const {
+    size_t v = precision == PD_FP32 ? sizeof(float) : sizeof(double);
+    return (size_t)grid.points() * state_values_per_point(scheme) * v;
+  }
+};
+
+namespace {
+
+// Makes the handle's device current for the duration of a call.
+struct DeviceScope {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceScope(int dev) {
+    if (dev < 0) return;
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceScope() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+pd_status hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) return fail(PD_ERR_NOMEM, "%s: %s", what, hipGetErrorString(e));
+  return fail(PD_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void release(void*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+template <typename T>
+void release(T*& p) {
+  void* v = p;
+  release(v);
+  p = nullptr;
+}
+
+pd_status prepare_field(pd_grid g, const pd_field* f, long long n_steps, FieldTables* t, long long* masked,
+                        int* taylor) {
+  if (!g) return fail(PD_ERR_INVALID, "null handle");
+  if (!f) return fail(PD_ERR_INVALID, "null field");
+  std::string err;
+  if (!sample_field(*f, n_steps, t, &err)) return fail(PD_ERR_INVALID, "%s", err.c_str());
+  field_extent(g->grid, t);
+  // Step-size condition of Sec. III (last paragraph): dt <= pi / max E.
+  if (t->dt * t->E_max > kPi)
+    return fail(PD_ERR_INVALID, "dt * E_max = %.6g exceeds pi (dt = %.6g, E_max = %.6g): use more steps",
+                t->dt * t->E_max, t->dt, t->E_max);
+  *masked = count_masked(g->grid, t->A_in, t->A_out);
+  *taylor = 0;
+  if (g->scheme == PD_SCHEME_MIDPOINT) {
+    double xm = t->dt * t->E_max;
+    *taylor = taylor_order(xm * xm, g->precision);
+    if (*taylor < 0) return fail(PD_ERR_UNSUPPORTED, "midpoint step too large for the compiled Taylor orders");
+  }
+  return ok();
+}
+
+void fill_info(pd_grid g, const FieldTables& t, long long masked, long long steps_done, pd_info* out) {
+  std::memset(out, 0, sizeof *out);
+  out->n_points = g->grid.points();
+  out->n_steps = t.n_steps;
+  out->steps_done = steps_done;
+  out->n_masked = masked;
+  out->dt = t.dt;
+  out->t_i = t.t_i;
+  out->t_f = t.t_f;
+  out->A_in = t.A_in;
+  out->A_out = t.A_out;
+  out->E_max = t.E_max;
+  out->A_min = t.A_min;
+  out->A_max = t.A_max;
+  out->precision = g->precision;
+  out->scheme = g->scheme;
+  out->points_per_lane = g->points_per_lane;
+  out->block_threads = g->block_threads;
+  out->device_bytes = g->device_bytes();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pd_last_error(void) { return g_error.c_str(); }
+
+const char* pd_version(void) { return "libpd 0.1.0 gfx950"; }
+
+pd_status pd_create_grid(int nx, int ny, double px_min, double px_max, double py_min, double py_max, int precision,
+                         int scheme, pd_grid* out) {
+  if (!out) return fail(PD_ERR_INVALID, "null output handle pointer");
+  *out = nullptr;
+  if (nx < 1 || ny < 1 || nx > 65536 || ny > 65536) return fail(PD_ERR_INVALID, "nx, ny must be in [1, 65536]");
+  if (!std::isfinite(px_min) || !std::isfinite(px_max) || !std::isfinite(py_min) || !std::isfinite(py_max) ||
+      !(px_max > px_min) || !(py_max > py_min))
+    return fail(PD_ERR_INVALID, "momentum ranges must be finite with max > min");
+  if (precision != PD_FP64 && precision != PD_FP32) return fail(PD_ERR_INVALID, "unknown precision %d", precision);
+  if (scheme != PD_SCHEME_STRANG && scheme != PD_SCHEME_MIDPOINT)
+    return fail(PD_ERR_INVALID, "unknown scheme %d", scheme);
+  pd_grid g = new (std::nothrow) pd_grid_s();
+  if (!g) return fail(PD_ERR_NOMEM, "host allocation failed");
+  g->grid.nx = nx;
+  g->grid.ny = ny;
+  g->grid.px_min = px_min;
+  g->grid.px_max = px_max;
+  g->grid.py_min = py_min;
+  g->grid.py_max = py_max;
+  g->grid.dx = (px_max - px_min) / (double)nx;
+  g->grid.dy = (py_max - py_min) / (double)ny;
+  g->precision = precision;
+  g->scheme = scheme;
+  g->points_per_lane = 2;
+  g->block_threads = 256;
+  *out = g;
+  return ok();
+}
+
+pd_status pd_check_field(pd_grid g, const pd_field* f, long long n_steps, pd_info* out) {
+  FieldTables t;
+  long long masked = 0;
+  int taylor = 0;
+  pd_status s = prepare_field(g, f, n_steps, &t, &masked, &taylor);
+  if (out && g && (s == PD_OK || !t.A_mid.empty())) fill_info(g, t, masked, 0, out);
+  return s;
+}
+
+pd_status pd_sample_field(const pd_field* f, long long n_steps, double* A_mid, double* t_i, double* t_f,
+                          double* A_in, double* A_out) {
+  if (!f) return fail(PD_ERR_INVALID, "null field");
+  FieldTables t;
+  std::string err;
+  if (!sample_field(*f, n_steps, &t, &err)) return fail(PD_ERR_INVALID, "%s", err.c_str());
+  if (A_mid) std::memcpy(A_mid, t.A_mid.data(), (size_t)n_steps * sizeof(double));
+  if (t_i) *t_i = t.t_i;
+  if (t_f) *t_f = t.t_f;
+  if (A_in) *A_in = t.A_in;
+  if (A_out) *A_out = t.A_out;
+  return ok();
+}
+
+pd_status pd_set_field(pd_grid g, const pd_field* f, long long n_steps) {
+  FieldTables t;
+  long long masked = 0;
+  int taylor = 0;
+  pd_status s = prepare_field(g, f, n_steps, &t, &masked, &taylor);
+  if (s != PD_OK) return s;
+  std::vector<unsigned char> rows;
+  build_step_table(t, g->scheme, g->precision, &rows);
+
+  if (g->device < 0) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    g->device = dev;
+  }
+  DeviceScope scope(g->device);
+  if (!scope.ok) return fail(PD_ERR_DEVICE, "cannot select device %d", g->device);
+  hipError_t e;
+  if (g->d_table) {
+    // Work of an earlier solve may still read the table or the state.
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  }
+  g->field_set = false;
+  if (rows.size() != g->table_bytes) {
+    release(g->d_table);
+    g->table_bytes = 0;
+    e = hipMalloc(&g->d_table, rows.size());
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(field table)");
+    g->table_bytes = rows.size();
+  }
+  e = hipMemcpy(g->d_table, rows.data(), rows.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(field table)");
+  long long npts = g->grid.points();
+  if (!g->d_n) {
+    e = hipMalloc(&g->d_n, (size_t)npts * sizeof(double));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(n)");
+  }
+  if (!g->d_partial) {
+    e = hipMalloc(&g->d_partial, (size_t)density_partials(npts) * sizeof(double));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(partials)");
+    e = hipMalloc(&g->d_rho, sizeof(double));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(rho)");
+  }
+  g->field = std::move(t);
+  g->n_masked = masked;
+  g->taylor = taylor;
+  g->steps_done = 0;
+  g->field_set = true;
+  return ok();
+}
+
+size_t pd_state_bytes(pd_grid g) { return g ? g->state_bytes() : 0; }
+
+pd_status pd_bind_state(pd_grid g, void* dev_ptr, size_t bytes) {
+  if (!g) return fail(PD_ERR_INVALID, "null handle");
+  if (dev_ptr) {
+    if (bytes < g->state_bytes())
+      return fail(PD_ERR_INVALID, "state buffer of %zu bytes is smaller than the %zu needed", bytes,
+                  g->state_bytes());
+    if (reinterpret_cast<uintptr_t>(dev_ptr) % 256 != 0) return fail(PD_ERR_INVALID, "state buffer not 256-byte aligned");
+  }
+  if (g->field_set && g->steps_done > 0 && g->steps_done < g->field.n_steps)
+    return fail(PD_ERR_STATE, "cannot rebind the state in the middle of a solve");
+  g->d_state_bound = dev_ptr;
+  g->state_bound_bytes = dev_ptr ? bytes : 0;
+  return ok();
+}
+
+pd_status pd_set_launch(pd_grid g, int points_per_lane, int block_threads) {
+  if (!g) return fail(PD_ERR_INVALID, "null handle");
+  if (points_per_lane != 0 && points_per_lane != 1 && points_per_lane != 2 && points_per_lane != 4)
+    return fail(PD_ERR_INVALID, "points_per_lane must be 1, 2 or 4");
+  if (block_threads != 0 && block_threads != 64 && block_threads != 128 && block_threads != 256)
+    return fail(PD_ERR_INVALID, "block_threads must be 64, 128 or 256");
+  if (points_per_lane) g->points_per_lane = points_per_lane;
+  if (block_threads) g->block_threads = block_threads;
+  return ok();
+}
+
+pd_status pd_rewind(pd_grid g) {
+  if (!g) return fail(PD_ERR_INVALID, "null handle");
+  if (!g->field_set) return fail(PD_ERR_STATE, "pd_rewind before pd_set_field");
+  g->steps_done = 0;
+  return ok();
+}
+
+pd_status pd_propagate(pd_grid g, long long max_steps, void* stream) {
+  if (!g) return fail(PD_ERR_INVALID, "null handle");
+  if (!g->field_set) return fail(PD_ERR_STATE, "pd_propagate before pd_set_field");
+  const long long N = g->field.n_steps;
+  long long left = N - g->steps_done;
+  if (left == 0) return fail(PD_ERR_STATE, "solve already complete (%lld steps)", N);
+  long long m = (max_steps < 0 || max_steps > left) ? left : max_steps;
+  if (m == 0) return ok();
+  DeviceScope scope(g->device);
+  if (!scope.ok) return fail(PD_ERR_DEVICE, "cannot select device %d", g->device);
+
+  SolveParams p{};
+  p.npts = g->grid.points();
+  p.nx = g->grid.nx;
+  p.px_min = g->grid.px_min;
+  p.dx = g->grid.dx;
+  p.py_min = g->grid.py_min;
+  p.dy = g->grid.dy;
+  p.A_in = g->field.A_in;
+  p.A_out = g->field.A_out;
+  p.dt = g->field.dt;
+  p.n_steps = N;
+  p.k_begin = g->steps_done;
+  p.k_end = g->steps_done + m;
+  p.table = g->d_table;
+  p.n_out = g->d_n;
+  p.load_state = p.k_begin > 0;
+  p.store_state = p.k_end < N;
+  if (p.load_state || p.store_state) {
+    void* st = g->d_state_bound;
+    if (!st) {
+      if (!g->d_state_own) {
+        hipError_t e = hipMalloc(&g->d_state_own, g->state_bytes());
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(state)");
+      }
+      st = g->d_state_own;
+    }
+    p.state = st;
+  }
+  hipError_t e = launch_propagate(g->scheme, g->precision, g->points_per_lane, g->block_threads, g->taylor, p,
+                                  static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "propagate launch");
+  g->steps_done = p.k_end;
+  return ok();
+}
+
+pd_status pd_density(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, void* stream) {
+  if (!g) return fail(PD_ERR_INVALID, "null handle");
+  if (!g->field_set || g->steps_done != g->field.n_steps)
+    return fail(PD_ERR_STATE, "pd_density before the last step (%lld of %lld done)", g->steps_done,
+                g->field_set ? g->field.n_steps : 0LL);
+  DeviceScope scope(g->device);
+  if (!scope.ok) return fail(PD_ERR_DEVICE, "cannot select device %d", g->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long npts = g->grid.points();
+  const double scale = 4.0 * g->grid.dx * g->grid.dy / (4.0 * kPi * kPi);
+  hipError_t e = launch_density(g->d_n, npts, scale, g->d_partial, g->d_rho, s);
+  if (e != hipSuccess) return hip_fail(e, "density launch");
+  bool wait = false;
+  if (n_out) {
+    e = hipMemcpyAsync(n_out, g->d_n, (size_t)npts * sizeof(double),
+                       n_out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "copy of n(p)");
+    wait = !n_out_on_device;
+  }
+  double rho = 0.0;
+  if (rho_out) {
+    e = hipMemcpyAsync(&rho, g->d_rho, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "copy of rho");
+    wait = true;
+  }
+  if (wait) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  }
+  if (rho_out) *rho_out = rho;
+  return ok();
+}
+
+pd_status pd_get_info(pd_grid g, pd_info* out) {
+  if (!g || !out) return fail(PD_ERR_INVALID, "null argument");
+  if (!g->field_set) {
+    FieldTables empty;
+    fill_info(g, empty, 0, 0, out);
+    return ok();
+  }
+  fill_info(g, g->field, g->n_masked, g->steps_done, out);
+  return ok();
+}
+
+void pd_destroy_grid(pd_grid g) {
+  if (!g) return;
+  if (g->device >= 0) {
+    DeviceScope scope(g->device);
+    release(g->d_table);
+    release(g->d_n);
+    release(g->d_partial);
+    release(g->d_rho);
+    release(g->d_state_own);
+  }
+  delete g;
+}
+
+}  // extern "C"

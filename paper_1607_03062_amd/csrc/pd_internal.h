@@ -1,0 +1,70 @@
+// Internal declarations shared by the host side of libpd and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <string>
+#include <vector>
+
+#include "pd.h"
+
+namespace pdx {
+
+// Host-side description of a field sampled for one solve.
+struct FieldTables {
+  double t_i = 0, t_f = 0, dt = 0;
+  double A_in = 0, A_out = 0, A_min = 0, A_max = 0;
+  double E_max = 0;
+  long long n_steps = 0;
+  std::vector<double> A_mid;  // A(t_i + (k + 1/2) dt), k < n_steps
+};
+
+struct Grid {
+  int nx = 0, ny = 0;
+  double px_min = 0, px_max = 0, py_min = 0, py_max = 0;
+  double dx = 0, dy = 0;
+  // Node coordinates; the kernels evaluate the same expressions (no contraction).
+  double px(int i) const { return px_min + (double)i * dx; }
+  double py(int j) const { return py_min + (double)j * dy; }
+  long long points() const { return (long long)nx * (long long)ny; }
+};
+
+// field.cpp
+bool sample_field(const pd_field& f, long long n_steps, FieldTables* out, std::string* err);
+void field_extent(const Grid& g, FieldTables* t);      // E_max over the grid
+long long count_masked(const Grid& g, double A_in, double A_out);
+
+// Per-step rows of the field table, as the kernels read them.
+//   Strang, FP64: {h, s} of the angle 2 dt A_k  (h = cos - 1, s = sin), 16 bytes
+//   Strang, FP32: the same rounded to float, 8 bytes
+//   Midpoint:     dt * A_k in FP64, 8 bytes
+size_t table_row_bytes(int scheme, int precision);
+void build_step_table(const FieldTables& t, int scheme, int precision, std::vector<unsigned char>* rows);
+
+// Smallest Taylor order (terms of cos - 1 and of sin(x)/x in x = (dt E)^2) whose
+// truncation stays below the precision's rounding for x <= x_max.
+int taylor_order(double x_max, int precision);
+
+// Parameters of one propagation launch (passed by value to the kernels).
+struct SolveParams {
+  long long npts;
+  int nx;
+  double px_min, dx, py_min, dy;
+  double A_in, A_out, dt;
+  long long n_steps, k_begin, k_end;
+  const void* table;
+  void* state;       // chunk state, structure of arrays; nullptr if not used
+  double* n_out;     // written by the launch that reaches n_steps
+  int load_state;    // 1: resume from state; 0: start from v_in
+  int store_state;   // 1: keep the state after k_end
+};
+
+// kernels.hip
+hipError_t launch_propagate(int scheme, int precision, int points_per_lane, int block_threads, int taylor,
+                            const SolveParams& p, hipStream_t stream);
+hipError_t launch_density(const double* n, long long npts, double scale, double* partial, double* rho,
+                          hipStream_t stream);
+long long density_partials(long long npts);
+size_t state_values_per_point(int scheme);
+
+}  // namespace pdx

@@ -31,8 +31,29 @@ def config1_values():
     return out
 
 
+def full_grid_values(c, n_samples=512, seed=7):
+    """rho over the full grid and n at seeded sample points (FP64 Strang oracle)."""
+    n, nd, masked = oracle.solve_grid(c["field"], c["grid"], c["n_steps"], "strang")
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(n.shape[0], size=n_samples, replace=False))
+    return {"config": c["name"], "n_steps": c["n_steps"], "rho": oracle.density(c["grid"], n),
+            "rho_kahan": oracle.density(c["grid"], n, kahan=True), "n_masked": masked,
+            "n_max": float(n.max()), "max_norm_dev": float(np.abs(nd).max()),
+            "samples": {str(int(i)): float(n[i]) for i in idx}}
+
+
 if __name__ == "__main__":
-    path = os.path.join(HERE, "oracle_config1.json")
-    with open(path, "w") as fh:
-        json.dump(config1_values(), fh, indent=1, sort_keys=True)
-    print("wrote", path)
+    which = sys.argv[1:] or ["config1"]
+    for w in which:
+        if w == "config1":
+            vals, name = config1_values(), "oracle_config1.json"
+        elif w == "config2a":
+            vals, name = full_grid_values(wl.config2a()), "oracle_config2a.json"
+        elif w == "config2b":
+            vals, name = full_grid_values(wl.config2b()), "oracle_config2b.json"
+        else:
+            raise SystemExit("unknown golden set %s" % w)
+        path = os.path.join(HERE, name)
+        with open(path, "w") as fh:
+            json.dump(vals, fh, indent=1, sort_keys=True)
+        print("wrote", path, flush=True)

@@ -1,0 +1,176 @@
+"""Host-side logic of libpd and its C ABI, without a GPU: the library loads and
+exports every entry point declared in include/pd.h, validates its arguments,
+samples the field like the oracle does, and reports device failures as
+status codes."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1607_03062_amd as pd
+from paper_1607_03062_amd import _lib
+from paper_1607_03062_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"^\s*(?:[A-Za-z_][\w\s\*]*?)\b(pd_\w+)\s*\(", text, flags=re.M))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pd.require_native()
+    names = declared_symbols()
+    assert {"pd_create_grid", "pd_set_field", "pd_propagate", "pd_density"} <= names
+    for n in sorted(names):
+        assert hasattr(lib, n), "libpd.so does not export %s" % n
+    # the Python binding covers every declared entry point
+    bound = {s[0] for s in _lib.SIGNATURES}
+    assert names <= bound, names - bound
+
+
+def test_version():
+    assert "gfx950" in pd.version()
+
+
+@pytest.mark.parametrize("args", [
+    (0, 4, -1, 1, -1, 1, 0, 0),
+    (4, 70000, -1, 1, -1, 1, 0, 0),
+    (4, 4, 1, 1, -1, 1, 0, 0),
+    (4, 4, -1, 1, 2, -2, 0, 0),
+    (4, 4, -1, float("nan"), -1, 1, 0, 0),
+    (4, 4, -1, float("inf"), -1, 1, 0, 0),
+    (4, 4, -1, 1, -1, 1, 7, 0),
+    (4, 4, -1, 1, -1, 1, 0, 9),
+])
+def test_create_grid_rejects_bad_arguments(args):
+    lib = pd.require_native()
+    h = ctypes.c_void_p(1)
+    st = lib.pd_create_grid(*args, ctypes.byref(h))
+    assert st == _lib.PD_ERR_INVALID
+    assert h.value is None
+    assert lib.pd_last_error().decode()
+
+
+def test_null_handles():
+    lib = pd.require_native()
+    assert lib.pd_propagate(None, -1, None) == _lib.PD_ERR_INVALID
+    assert lib.pd_density(None, None, 0, None, None) == _lib.PD_ERR_INVALID
+    assert lib.pd_state_bytes(None) == 0
+    lib.pd_destroy_grid(None)
+
+
+@pytest.mark.parametrize("kind", ["sin2", "constant", "pulse"])
+def test_field_sampling_matches_oracle(kind):
+    """The library's host-side A(t) at the step midpoints equals the oracle's (independent code)."""
+    if kind == "sin2":
+        f, N = wl.sin2(0.16772546041219238, 0.25, 20), 40000
+    elif kind == "constant":
+        f, N = wl.constant(0.2, 200.0), 40000
+    else:
+        f = {"kind": "pulse", "E0": 1.0, "omega": 0.4876, "phi": 0.7, "omega_rise": 0.0609,
+             "omega_fall": 0.0609, "duration": 70.9}
+        N = 7000
+    A, t_i, t_f, a_in, a_out = _lib.sample_field(f, N)
+    Ao, a_in_o, a_out_o, dt_o = oracle.field_table(f, N)
+    scale = max(1.0, np.abs(Ao).max())
+    assert np.max(np.abs(A - Ao)) <= 4e-16 * scale * 8
+    assert abs(a_in - a_in_o) <= 1e-16 and abs(a_out - a_out_o) <= 1e-15 * scale
+    assert abs((t_f - t_i) / N - dt_o) <= 1e-18
+
+
+def test_check_field_reports_step_bound_and_masking():
+    s = pd.Solver.for_grid(wl.config1()["grid"])
+    info = s.check_field(wl.config1()["field"], 4000)
+    assert info["n_masked"] == 1
+    assert abs(info["dt"] - 100.53096491487338 / 4000) < 1e-15
+    # E_max: corner of the grid box (-2, 2 - 1/16) x A range
+    A = oracle.field_table(wl.config1()["field"], 4000)[0]
+    X = max(abs(-2 + A.min()), abs(-2 + A.max()), abs(1.9375 + A.min()), abs(1.9375 + A.max()))
+    assert abs(info["E_max"] - math.hypot(X, 2.0)) < 1e-14
+    # Sec. III step condition dt * E_max <= pi
+    with pytest.raises(pd.PDError) as e:
+        s.check_field(wl.config1()["field"], 90)
+    assert e.value.status == _lib.PD_ERR_INVALID and "pi" in e.value.message
+    s.close()
+
+
+def test_masked_count_with_final_momentum_zero():
+    """Constant field E0 = 0.2 on [0, 200]: A_out = -40, so p = (40, 0) has E_out = 0."""
+    s = pd.Solver(81, 3, (0.0, 81.0), (-1.0, 2.0))  # p_x = 0, 1, ..., 80; p_y = -1, 0, 1
+    info = s.check_field(wl.constant(0.2, 200.0), 40000)
+    assert info["n_masked"] == 2  # p = (0, 0) and p = (40, 0)
+    s.close()
+
+
+@pytest.mark.parametrize("field,msg", [
+    ({"kind": "sin2", "E0": 0.1, "omega": 0.5, "cycles": 1}, "cycles"),
+    ({"kind": "sin2", "E0": float("nan"), "omega": 0.5, "cycles": 8}, "finite"),
+    ({"kind": "constant", "E0": 0.1, "t_end": -1.0}, "t_end"),
+    ({"kind": "pulse", "E0": 1.0, "omega": 0.5, "phi": 0, "omega_rise": 0.06, "omega_fall": 0.06,
+      "duration": 10.0}, "shorter"),
+])
+def test_bad_fields(field, msg):
+    s = pd.Solver(8, 8, (-1, 1), (-1, 1))
+    with pytest.raises(pd.PDError) as e:
+        s.check_field(field, 1000)
+    assert e.value.status == _lib.PD_ERR_INVALID and msg in e.value.message
+    s.close()
+
+
+def test_table_field_length_checked():
+    s = pd.Solver(8, 8, (-1, 1), (-1, 1))
+    f = {"kind": "table", "A_mid": np.zeros(10), "t_i": 0.0, "t_f": 1.0, "A_in": 0.0, "A_out": 0.0}
+    with pytest.raises(pd.PDError):
+        s.check_field(f, 11)
+    assert s.check_field(f, 10)["n_steps"] == 10
+    s.close()
+
+
+def test_state_errors_without_device():
+    s = pd.Solver(8, 8, (-1, 1), (-1, 1))
+    with pytest.raises(pd.PDError) as e:
+        s.propagate()
+    assert e.value.status == _lib.PD_ERR_STATE
+    with pytest.raises(pd.PDError) as e:
+        s.density()
+    assert e.value.status == _lib.PD_ERR_STATE
+    with pytest.raises(pd.PDError):
+        s.set_launch(3, 0)
+    with pytest.raises(pd.PDError):
+        s.set_launch(0, 512)
+    s.set_launch(4, 64)
+    assert s.info()["points_per_lane"] == 4 and s.info()["block_threads"] == 64
+    s.close()
+
+
+def test_device_failure_is_a_status_not_a_crash():
+    """Without a GPU the first device call fails with PD_ERR_DEVICE and a message."""
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    s = pd.Solver(8, 8, (-1, 1), (-1, 1))
+    with pytest.raises(pd.PDError) as e:
+        s.set_field(wl.sin2(0.1, 0.5, 8), 4000)
+    assert e.value.status == _lib.PD_ERR_DEVICE
+    s.close()
+
+
+def test_state_bytes():
+    s = pd.Solver(10, 7, (-1, 1), (-1, 1), "fp64", "strang")
+    assert s.state_bytes() == 70 * 3 * 8
+    s.close()
+    s = pd.Solver(10, 7, (-1, 1), (-1, 1), "fp32", "midpoint")
+    assert s.state_bytes() == 70 * 4 * 4
+    s.close()

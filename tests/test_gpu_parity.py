@@ -1,0 +1,283 @@
+"""GPU path (HIP kernels behind the C ABI) against the FP64 CPU oracle.
+
+Tolerances:
+  FP64 forms: |n_gpu - n_oracle| <= 1e-12 per point and |rho_gpu / rho_oracle - 1| <= 1e-12.
+    Both sides are FP64 with rounding ~1e-16 per operation; the error after N
+    unitary steps grows like sqrt(N) ulps (about 1e-14 at N = 80000), and the
+    GPU's factorised rotations add no truncation, so 1e-12 leaves two decades.
+  FP32 precision form: |n_gpu - n_oracle| <= 1e-5 per point (the bar set for
+    the FP32 form; FP32 rounding of the state random-walks to ~1e-6 after 80000 steps).
+  p_y = 0 lines: exactly 0.0 on both sides (the sigma_x eigenstate is kept).
+  Launch shape, chunking and repeats: bit-identical n and rho.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1607_03062_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+FP64_N_ABS = 1e-12
+FP64_RHO_REL = 1e-12
+FP32_N_ABS = 1e-5
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def run(pd, grid, field, N, precision="fp64", scheme="strang", ppl=0, block=0, chunks=None, bind=None):
+    print("gpu solve: grid %dx%d N=%d %s %s ppl=%s block=%s chunks=%s" % (
+        grid["nx"], grid["ny"], N, precision, scheme, ppl, block, chunks), flush=True)
+    s = pd.Solver.for_grid(grid, precision, scheme)
+    s.set_launch(ppl, block)
+    s.set_field(field, N)
+    if bind is not None:
+        s.bind_state(bind)
+    if chunks:
+        for c in chunks:
+            s.propagate(c)
+    else:
+        s.propagate(-1)
+    n = np.empty(grid["nx"] * grid["ny"])
+    rho = s.density(n_out=n)
+    info = s.info()
+    s.close()
+    return n, rho, info
+
+
+RAGGED = {"nx": 37, "ny": 53, "px": (-1.3, 2.1), "py": (-0.9, 1.7)}
+RAGGED_FIELD = wl.sin2(0.3, 0.6, 3)
+
+
+@pytest.fixture(scope="module")
+def cfg1_oracle():
+    c = wl.config1()
+    return {s: oracle.solve_grid(c["field"], c["grid"], c["n_steps"], s) for s in ("strang", "midpoint")}
+
+
+@pytest.mark.parametrize("scheme", ["strang", "midpoint"])
+def test_config1_fp64_full_grid(gpu, cfg1_oracle, scheme):
+    c = wl.config1()
+    n, rho, info = run(gpu, c["grid"], c["field"], c["n_steps"], "fp64", scheme)
+    n_o, nd, masked = cfg1_oracle[scheme]
+    rho_o = oracle.density(c["grid"], n_o)
+    assert np.max(np.abs(n - n_o)) <= FP64_N_ABS
+    assert abs(rho / rho_o - 1) <= FP64_RHO_REL
+    assert info["n_masked"] == masked == 1
+    row = n.reshape(64, 64)[32]  # p_y = 0
+    assert np.all(row == 0.0)
+
+
+@pytest.mark.parametrize("scheme", ["strang", "midpoint"])
+def test_config1_fp32_form(gpu, cfg1_oracle, scheme):
+    c = wl.config1()
+    n, rho, info = run(gpu, c["grid"], c["field"], c["n_steps"], "fp32", scheme)
+    n_o = cfg1_oracle[scheme][0]
+    assert np.max(np.abs(n - n_o)) <= FP32_N_ABS
+    assert np.all(n.reshape(64, 64)[32] == 0.0)
+    assert abs(rho / oracle.density(c["grid"], n_o) - 1) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("scheme", ["strang", "midpoint"])
+def test_ragged_grid_every_launch_shape(gpu, precision, scheme):
+    """37 x 53 points (not a multiple of any tile), 777 steps: every launch shape gives the
+    same bits, and the oracle's values."""
+    N = 777
+    n_o = oracle.solve_grid(RAGGED_FIELD, RAGGED, N, scheme)[0]
+    ref = None
+    for ppl in (1, 2, 4):
+        for block in (64, 256):
+            n, rho, _ = run(gpu, RAGGED, RAGGED_FIELD, N, precision, scheme, ppl, block)
+            if ref is None:
+                ref = (n, rho)
+                tol = FP64_N_ABS if precision == "fp64" else FP32_N_ABS
+                assert np.max(np.abs(n - n_o)) <= tol
+            else:
+                assert np.array_equal(n, ref[0]) and rho == ref[1], (ppl, block)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("scheme", ["strang", "midpoint"])
+def test_chunked_equals_single_launch(gpu, precision, scheme):
+    """Propagation split into chunks that cross the FP32 renormalisation boundaries
+    (every 1024 steps) reproduces the single launch bit for bit, with the handle's
+    own state buffer and with a caller-owned torch buffer."""
+    import torch
+
+    N = 5000
+    chunks = [1, 1023, 1, 2047, 1, 900, 1027]
+    single = run(gpu, RAGGED, RAGGED_FIELD, N, precision, scheme)
+    chunked = run(gpu, RAGGED, RAGGED_FIELD, N, precision, scheme, chunks=chunks)
+    assert np.array_equal(single[0], chunked[0]) and single[1] == chunked[1]
+    nbytes = RAGGED["nx"] * RAGGED["ny"] * (3 if scheme == "strang" else 4) * (8 if precision == "fp64" else 4)
+    buf = torch.empty(nbytes // 4 + 64, dtype=torch.float32, device="cuda")
+    bound = run(gpu, RAGGED, RAGGED_FIELD, N, precision, scheme, chunks=[2500, 2500], bind=buf)
+    assert np.array_equal(single[0], bound[0])
+
+
+def test_degenerate_inputs(gpu):
+    # one point, one step
+    g1 = {"nx": 1, "ny": 1, "px": (0.3, 0.4), "py": (0.2, 0.3)}
+    f = wl.sin2(0.1, 0.5, 8)
+    n, rho, info = run(gpu, g1, f, 400)
+    n_o = oracle.solve_grid(f, g1, 400)[0]
+    assert abs(n[0] - n_o[0]) <= FP64_N_ABS
+    # a grid made of the masked point only
+    g0 = {"nx": 1, "ny": 1, "px": (0.0, 1.0), "py": (0.0, 1.0)}
+    n, rho, info = run(gpu, g0, f, 400)
+    assert n[0] == 0.0 and rho == 0.0 and info["n_masked"] == 1
+    # a single step on config 1's grid (constant field over a short time)
+    c = wl.config1()
+    short = wl.constant(0.2, 0.5)
+    for scheme in ("strang", "midpoint"):
+        n, rho, info = run(gpu, c["grid"], short, 1, "fp64", scheme)
+        n_o = oracle.solve_grid(short, c["grid"], 1, scheme)[0]
+        assert np.max(np.abs(n - n_o)) <= FP64_N_ABS
+    # E_out = 0 inside the grid (constant field, A_out = -40): masked, n = 0
+    gm = {"nx": 81, "ny": 3, "px": (0.0, 81.0), "py": (-1.0, 2.0)}
+    for scheme in ("strang", "midpoint"):
+        n, rho, info = run(gpu, gm, wl.constant(0.2, 200.0), 40000, "fp64", scheme)
+        assert info["n_masked"] == 2
+        assert n[81 + 0] == 0.0 and n[81 + 40] == 0.0
+        idx = np.array([81 * 2 + 3, 81 * 0 + 30])
+        n_o = oracle.solve_grid(wl.constant(0.2, 200.0), gm, 40000, scheme, idx=idx)[0]
+        assert np.max(np.abs(n[idx] - n_o)) <= FP64_N_ABS
+
+
+def test_repeat_is_bitwise(gpu):
+    c = wl.config1()
+    a = run(gpu, c["grid"], c["field"], c["n_steps"])
+    b = run(gpu, c["grid"], c["field"], c["n_steps"])
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+
+
+def test_density_reduction(gpu):
+    c = wl.config1()
+    n, rho, info = run(gpu, RAGGED, RAGGED_FIELD, 777)
+    dx = (RAGGED["px"][1] - RAGGED["px"][0]) / RAGGED["nx"]
+    dy = (RAGGED["py"][1] - RAGGED["py"][0]) / RAGGED["ny"]
+    exact = 4 * dx * dy / (4 * math.pi ** 2) * math.fsum(n)
+    assert abs(rho / exact - 1) <= 1e-14
+
+
+def test_torch_stream_and_device_output(gpu):
+    import torch
+
+    c = wl.config1()
+    ref = run(gpu, c["grid"], c["field"], c["n_steps"])
+    s = gpu.Solver.for_grid(c["grid"])
+    s.set_field(c["field"], c["n_steps"])
+    st = torch.cuda.Stream()
+    out = torch.empty(64 * 64, dtype=torch.float64, device="cuda")
+    s.propagate(-1, stream=st)
+    rho = s.density(n_out=out, stream=st)
+    st.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref[0]) and rho == ref[1]
+    s.close()
+
+
+def test_error_paths_on_device(gpu):
+    c = wl.config1()
+    s = gpu.Solver.for_grid(c["grid"])
+    s.set_field(c["field"], 100)
+    with pytest.raises(gpu.PDError) as e:
+        s.density()
+    assert e.value.status == 2
+    s.propagate(50)
+    with pytest.raises(gpu.PDError):
+        s.density()
+    s.propagate(-1)
+    with pytest.raises(gpu.PDError) as e:
+        s.propagate(-1)
+    assert e.value.status == 2
+    s.density()
+    import torch
+
+    small = torch.empty(16, dtype=torch.float64, device="cuda")
+    with pytest.raises(gpu.PDError) as e:
+        s.bind_state(small)
+    assert e.value.status == 1
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads, in the launch configuration the benchmark uses
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def test_config2a_full_size(gpu):
+    """1024^2 on [-4,4]^2, seeded E0, omega = 0.25, 20 cycles, 40000 steps, FP64: sampled points
+    against the oracle, exact p_y = 0 row, mirror symmetry, and rho against the oracle's full grid."""
+    c = wl.config2a()
+    n, rho, info = run(gpu, c["grid"], c["field"], c["n_steps"])
+    N = c["grid"]["nx"]
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(N * N, size=200, replace=False))
+    n_o = oracle.solve_grid(c["field"], c["grid"], c["n_steps"], idx=idx)[0]
+    assert np.max(np.abs(n[idx] - n_o)) <= FP64_N_ABS
+    m = n.reshape(N, N)
+    assert np.all(m[N // 2] == 0.0)
+    assert np.max(np.abs(m[1:] - m[1:][::-1])) <= 1e-13
+    gold = _golden("oracle_config2a.json")
+    if gold is not None:
+        assert abs(rho / gold["rho"] - 1) <= FP64_RHO_REL
+        ks = np.array([int(k) for k in gold["samples"]])
+        vs = np.array(list(gold["samples"].values()))
+        assert np.max(np.abs(n[ks] - vs)) <= FP64_N_ABS
+
+
+def test_config2b_constant_field_landau_zener(gpu):
+    """Constant field E0 = 0.2 on [0, 200], 1024^2, 40000 steps: for 2 <= p_x < 4 the density
+    is the Landau-Zener value exp(-pi p_y^2 / E0) within 2e-3; sampled points match the oracle."""
+    c = wl.config2b()
+    n, rho, info = run(gpu, c["grid"], c["field"], c["n_steps"])
+    N = c["grid"]["nx"]
+    m = n.reshape(N, N)
+    p = -4.0 + np.arange(N) * (8.0 / N)
+    cols = (p >= 2.0) & (p < 4.0)
+    lz = np.exp(-math.pi * p ** 2 / 0.2)
+    dev = np.abs(m[:, cols] - lz[:, None]).max()
+    assert dev <= 2e-3
+    rng = np.random.default_rng(12)
+    idx = np.sort(rng.choice(N * N, size=120, replace=False))
+    n_o = oracle.solve_grid(c["field"], c["grid"], c["n_steps"], idx=idx)[0]
+    assert np.max(np.abs(n[idx] - n_o)) <= FP64_N_ABS
+    gold = _golden("oracle_config2b.json")
+    if gold is not None:
+        assert abs(rho / gold["rho"] - 1) <= FP64_RHO_REL
+
+
+@pytest.fixture(scope="module")
+def cfg3_subsample_oracle():
+    c = wl.config3()
+    idx = wl.subsample_indices(2048, 64)
+    n_o = oracle.solve_grid(c["field"], c["grid"], c["n_steps"], idx=idx)[0]
+    return idx, n_o
+
+
+def test_config3_precision_form(gpu, cfg3_subsample_oracle):
+    """2048^2 on [-2,2]^2, 80000 steps, FP32 form: the 64 x 64 subsample (stride 32) within
+    1e-5 of the FP64 oracle per point; the FP64 form within 1e-12; total densities agree."""
+    idx, n_o = cfg3_subsample_oracle
+    c = wl.config3()
+    n32, rho32, _ = run(gpu, c["grid"], c["field"], c["n_steps"], "fp32")
+    err32 = np.max(np.abs(n32[idx] - n_o))
+    print("config3 fp32 max |dn| on subsample = %.3e" % err32)
+    assert err32 <= FP32_N_ABS
+    n64, rho64, _ = run(gpu, c["grid"], c["field"], c["n_steps"], "fp64")
+    assert np.max(np.abs(n64[idx] - n_o)) <= FP64_N_ABS
+    print("config3 rho fp32 %.15e fp64 %.15e rel %.3e" % (rho32, rho64, rho32 / rho64 - 1))
+    assert abs(rho32 / rho64 - 1) <= 1e-5
+    m = n32.reshape(2048, 2048)
+    assert np.all(m[1024] == 0.0)
