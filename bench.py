@@ -25,11 +25,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "momentum point-steps/s (FP32 vs FP64 form) at stated n(p) error; p50/p99 solve ms"
 
-# Algorithmic work per point-step of the propagation kernels: three plane
+# Algorithmic work per point-step of the propagation kernel: three plane
 # rotations of the Bloch vector per Strang step.
-#   FP64 form: 2 FMA per rotated component -> 12 FMA = 24 flop, 12 VALU instructions
-#   FP32 form: mul + fma + add per rotated component -> 24 flop, 18 VALU instructions
-ALGO = {("strang", "fp64"): (24, 12), ("strang", "fp32"): (24, 18)}
+#   shear form (every rotation angle <= pi/2): 3 FMA per rotation -> 9 FMA = 18 flop, 9 VALU instructions
+#   versine form, FP64: 2 FMA per rotated component -> 12 FMA = 24 flop, 12 instructions
+#   versine form, FP32: mul + fma + add per rotated component -> 24 flop, 18 instructions
+ALGO = {(0, "fp64"): (18, 9), (0, "fp32"): (18, 9), (1, "fp64"): (24, 12), (1, "fp32"): (24, 18)}
 # MI355X vector peaks from its unit counts and clock (256 CU, 2.4 GHz): FP64
 # issues 64 lanes per clock per CU (78.6 TFLOP/s with FMA); unpacked FP32 with
 # VGPR operands issues 128 lanes per clock per CU (157.3 TFLOP/s with FMA).
@@ -63,10 +64,10 @@ def traffic_from_profile(precision: str):
         return None
 
 
-def time_form(pd, torch, c, precision, steps, warmup, ppl, block):
+def time_form(pd, torch, c, precision, steps, warmup, ppl, block, stage=0, chunk=0):
     s = pd.Solver.for_grid(c["grid"], precision, "strang")
-    if ppl or block:
-        s.set_launch(ppl, block)
+    if ppl or block or stage or chunk:
+        s.set_launch(ppl, block, stage, chunk)
     s.set_field(c["field"], c["n_steps"])
     st = torch.cuda.Stream()
     for _ in range(warmup):
@@ -176,7 +177,7 @@ def main():
     t = main_form["t_total"]
     value = ps_per_solve * K / t
     kern_ms = float(np.mean(main_form["kernel_ms"]))
-    flops, instr = ALGO[("strang", args.precision)]
+    flops, instr = ALGO[(main_form["info"]["rotation_form"], args.precision)]
     achieved = flops * ps_per_solve / (kern_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     wall_ms = np.array(main_form["wall"]) * 1e3
@@ -213,7 +214,7 @@ def main():
     }
     if other is not None:
         okm = float(np.mean(other["kernel_ms"]))
-        f64, i64 = ALGO[("strang", "fp64")]
+        f64, i64 = ALGO[(other["info"]["rotation_form"], "fp64")]
         line["fp64_form"] = {
             "value": ps_per_solve * K / other["t_total"], "ms_per_step": other["t_total"] / K * 1e3,
             "kernel_ms": okm, "n_error_max_abs": n_err.get("fp64"), "rho": other["rho"],

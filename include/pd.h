@@ -106,6 +106,10 @@ typedef struct {
   int scheme;               /* pd_scheme */
   int points_per_lane;      /* launch shape in use */
   int block_threads;
+  int table_stage;          /* 1 = LDS chunks, 2 = scalar-unit reads */
+  int chunk_steps;
+  int rotation_form;        /* Strang: 0 = three shears per rotation (every rotation angle of the
+                               solve <= pi/2), 1 = versine form (h = cos - 1, s = sin) */
   size_t device_bytes;      /* device memory the handle owns */
 } pd_info;
 
@@ -165,10 +169,14 @@ size_t pd_state_bytes(pd_grid g);
    dev_ptr = NULL returns to the handle's own buffer. */
 pd_status pd_bind_state(pd_grid g, void* dev_ptr, size_t bytes);
 
-/* Override the launch shape: points_per_lane in {1, 2, 4}, block_threads in
-   {64, 128, 256}; 0 keeps the current value.  Results do not depend on the
-   launch shape (bit for bit). */
-pd_status pd_set_launch(pd_grid g, int points_per_lane, int block_threads);
+/* Override the launch shape of the propagation kernel: points_per_lane in
+   {1, 2, 4}; block_threads in {64, 128, 256}; table_stage 1 = the per-step
+   field rows are staged through LDS in time chunks (read from VGPRs), 2 = read
+   directly by the scalar unit (SGPR operands); chunk_steps = LDS chunk length,
+   a power of two in [64, 4096] (at most 1024 in the FP32 form, whose
+   renormalisation period it must divide).  0 keeps the current value.  Results
+   do not depend on the launch shape (bit for bit). */
+pd_status pd_set_launch(pd_grid g, int points_per_lane, int block_threads, int table_stage, int chunk_steps);
 
 pd_status pd_get_info(pd_grid g, pd_info* out);
 

@@ -64,6 +64,9 @@ class pd_info(ctypes.Structure):
         ("scheme", ctypes.c_int),
         ("points_per_lane", ctypes.c_int),
         ("block_threads", ctypes.c_int),
+        ("table_stage", ctypes.c_int),
+        ("chunk_steps", ctypes.c_int),
+        ("rotation_form", ctypes.c_int),
         ("device_bytes", ctypes.c_size_t),
     ]
 
@@ -93,7 +96,7 @@ SIGNATURES = [
     ("pd_density", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _vp]),
     ("pd_state_bytes", ctypes.c_size_t, [_vp]),
     ("pd_bind_state", ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
-    ("pd_set_launch", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    ("pd_set_launch", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     ("pd_get_info", ctypes.c_int, [_vp, ctypes.POINTER(pd_info)]),
     ("pd_destroy_grid", None, [_vp]),
     ("pd_last_error", ctypes.c_char_p, []),
@@ -235,8 +238,10 @@ class Solver:
             check(load().pd_bind_state(self._h, ptr, nbytes), "pd_bind_state")
         return self
 
-    def set_launch(self, points_per_lane: int = 0, block_threads: int = 0):
-        check(load().pd_set_launch(self._h, int(points_per_lane), int(block_threads)), "pd_set_launch")
+    def set_launch(self, points_per_lane: int = 0, block_threads: int = 0, table_stage: int = 0,
+                   chunk_steps: int = 0):
+        check(load().pd_set_launch(self._h, int(points_per_lane), int(block_threads), int(table_stage),
+                                   int(chunk_steps)), "pd_set_launch")
         return self
 
     def info(self) -> dict:

@@ -201,7 +201,7 @@ size_t table_row_bytes(int scheme, int precision) {
   return precision == PD_FP32 ? 2 * sizeof(float) : 2 * sizeof(double);
 }
 
-void build_step_table(const FieldTables& t, int scheme, int precision, std::vector<unsigned char>* rows) {
+void build_step_table(const FieldTables& t, int scheme, int precision, int form, std::vector<unsigned char>* rows) {
   size_t n = (size_t)t.n_steps;
   rows->resize(n * table_row_bytes(scheme, precision));
   if (scheme == PD_SCHEME_MIDPOINT) {
@@ -209,22 +209,78 @@ void build_step_table(const FieldTables& t, int scheme, int precision, std::vect
     for (size_t k = 0; k < n; ++k) d[k] = t.dt * t.A_mid[k];
     return;
   }
-  // The sigma_x factor exp(-i dt A_k sigma_x) rotates the Bloch vector by 2 dt A_k
-  // about x: store h = cos(2a) - 1 = -2 sin^2 a and s = sin(2a) = 2 sin a cos a.
+  // The sigma_x factor exp(-i dt A_k sigma_x) rotates the Bloch vector by
+  // phi = 2a, a = dt A_k, about x: store (tan a, sin 2a) for the shear form or
+  // (cos 2a - 1, sin 2a) = (-2 sin^2 a, 2 sin a cos a) for the versine form.
   for (size_t k = 0; k < n; ++k) {
     double a = t.dt * t.A_mid[k];
     double sa = std::sin(a), ca = std::cos(a);
-    double h = -2.0 * sa * sa, s = 2.0 * sa * ca;
+    double c0 = form == kFormShear ? sa / ca : -2.0 * sa * sa, c1 = 2.0 * sa * ca;
     if (precision == PD_FP32) {
       float* r = reinterpret_cast<float*>(rows->data()) + 2 * k;
-      r[0] = (float)h;
-      r[1] = (float)s;
+      r[0] = (float)c0;
+      r[1] = (float)c1;
     } else {
       double* r = reinterpret_cast<double*>(rows->data()) + 2 * k;
-      r[0] = h;
-      r[1] = s;
+      r[0] = c0;
+      r[1] = c1;
     }
   }
+}
+
+namespace {
+
+// Coefficients of the rotation by phi = 2 * half in the given form.
+void rotation_coefficients(double half, int form, double* a, double* s) {
+  double sh = std::sin(half), ch = std::cos(half);
+  *s = 2.0 * sh * ch;
+  *a = form == kFormShear ? sh / ch : -2.0 * sh * sh;
+}
+
+template <typename R>
+void put(std::vector<unsigned char>* bytes, size_t offset, size_t index, double v) {
+  reinterpret_cast<R*>(bytes->data() + offset)[index] = (R)v;
+}
+
+}  // namespace
+
+void build_point_coefficients(const Grid& g, double dt, int precision, int form, std::vector<unsigned char>* bytes,
+                              size_t* col_offset, size_t* row_offset) {
+  const size_t v = precision == PD_FP32 ? sizeof(float) : sizeof(double);
+  auto align = [](size_t n) { return (n + 255) / 256 * 256; };
+  *col_offset = align(bytes->size());
+  *row_offset = align(*col_offset + 2 * v * (size_t)g.nx);
+  bytes->resize(align(*row_offset + 4 * v * (size_t)g.ny));
+  auto store = [&](size_t off, size_t idx, double x) {
+    if (precision == PD_FP32)
+      put<float>(bytes, off, idx, x);
+    else
+      put<double>(bytes, off, idx, x);
+  };
+  double a, s;
+  for (int i = 0; i < g.nx; ++i) {
+    rotation_coefficients(dt * g.px(i), form, &a, &s);  // rotation by 2 dt px about x
+    store(*col_offset, 2 * (size_t)i, a);
+    store(*col_offset, 2 * (size_t)i + 1, s);
+  }
+  for (int j = 0; j < g.ny; ++j) {
+    double py = g.py(j);
+    rotation_coefficients(dt * py, form, &a, &s);  // rotation by 2 dt py about y
+    store(*row_offset, 4 * (size_t)j, a);
+    store(*row_offset, 4 * (size_t)j + 1, s);
+    rotation_coefficients(0.5 * dt * py, form, &a, &s);  // half step: rotation by dt py
+    store(*row_offset, 4 * (size_t)j + 2, a);
+    store(*row_offset, 4 * (size_t)j + 3, s);
+  }
+}
+
+int strang_form(const Grid& g, const FieldTables& t) {
+  // Bloch rotation angles of a step: 2 dt A_k, 2 dt px and 2 dt py.
+  double amax = std::fmax(std::fabs(t.A_min), std::fabs(t.A_max));
+  double pxmax = std::fmax(std::fabs(g.px(0)), std::fabs(g.px(g.nx - 1)));
+  double pymax = std::fmax(std::fabs(g.py(0)), std::fabs(g.py(g.ny - 1)));
+  double phi = 2.0 * t.dt * std::fmax(amax, std::fmax(pxmax, pymax));
+  return phi <= kShearMaxAngle ? kFormShear : kFormVersine;
 }
 
 int taylor_order(double x_max, int precision) {

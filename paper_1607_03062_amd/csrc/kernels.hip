@@ -1,10 +1,10 @@
-// gfx950 kernels of libpd: split-operator propagation of one spinor per momentum
+// gfx950 kernels of libpd: split-operator propagation of one state per momentum
 // point, projection on the final positive-energy state, and the density sum.
 //
 // One lane per momentum point (points_per_lane of them, strided by the block
 // size so loads and stores stay coalesced).  The per-step field row is the same
-// for every lane: it is read with uniform (scalar-unit) loads from the table in
-// global memory, so the vector ALUs only see the rotation arithmetic.
+// for every lane: it is either staged through LDS in time chunks (every lane then
+// reads it into VGPRs) or read by the scalar unit into SGPRs.
 //
 // Strang scheme (Sec. III, Eqs. (11)-(12), with the midpoint Hamiltonian
 // sigma_x P_x + sigma_y p_y split into its two parts):
@@ -14,11 +14,17 @@
 // phase of psi is unobservable): exp(-i a sx) rotates r by 2a about x and
 // exp(-i b sy) by 2b about y.  Since exp(-i dt (px + A_k) sx) =
 // exp(-i dt px sx) exp(-i dt A_k sx), every step is three plane rotations:
-// by 2 dt A_k about x (table row, same for all lanes), by 2 dt px about x and
-// by 2 dt py about y (per-point constants computed once); the half steps of
-// neighbouring steps are merged.  Each rotation costs four FMAs.
-// The projection on u_out is n = |u_out^dagger psi|^2 = (1 + r . r_u) / 2 with
-// r_u = P_out / |P_out| the Bloch vector of u_out (Sec. II, Eqs. (1), (3)).
+// by 2 dt A_k about x (table row, the same for all lanes), by 2 dt px about x
+// and by 2 dt py about y (per-point constants computed once); the half steps of
+// neighbouring steps are merged.
+//
+// A plane rotation by phi is applied either as three shears (Paeth's
+// decomposition; one FMA each, coefficients tan(phi/2) and sin(phi)), or, when
+// some angle of the solve is too large for the shears to stay well conditioned,
+// in versine form with h = cos(phi) - 1 and s = sin(phi).
+// The projection on u_out is n = |u_out^dagger psi|^2 = (1 + r.r_u) / 2 with
+// r_u = P_out / |P_out| the Bloch vector of u_out (Sec. II, Eqs. (1), (3)); r
+// is normalised first (the exact steps are unitary, Sec. III).
 //
 // Midpoint scheme (Sec. III, Eq. (13)): per step the closed 2x2 form
 //   U = cos(dt E) I - i sigma.P sin(dt E) / E,  P = p + A_k,
@@ -33,30 +39,49 @@ namespace {
 
 constexpr long long kRenormEvery = 1024;  // FP32 form: renormalise after every 1024th step
 
+// Two coefficients of a plane rotation: (tan(phi/2), sin(phi)) in the shear
+// form, (cos(phi) - 1, sin(phi)) in the versine form.
 template <typename R>
 struct Row {
-  R h, s;
+  R a, s;
 };
 
-// Plane rotation of (u, v) by an angle with h = cos - 1, s = sin:
-//   u' = u + h u - s v,  v' = v + h v + s u.
-__device__ __forceinline__ void rotate(double& u, double& v, double h, double s) {
+// Rotation of (u, v) by phi: u' = u cos - v sin, v' = u sin + v cos.
+// Shear form, t = tan(phi/2), s = sin(phi): u -= t v; v += s u; u -= t v.
+template <typename R>
+__device__ __forceinline__ void rotate_shear(R& u, R& v, R t, R s) {
+  u = fma(-t, v, u);
+  v = fma(s, u, v);
+  u = fma(-t, v, u);
+}
+
+// Versine form, h = cos - 1: u' = u + h u - s v,  v' = v + h v + s u.
+__device__ __forceinline__ void rotate_versine(double& u, double& v, double h, double s) {
   double nu = fma(h, u, fma(-s, v, u));
   double nv = fma(h, v, fma(s, u, v));
   u = nu;
   v = nv;
 }
 
-// FP32 form: the small increment is formed first and added once, so the state
-// sees a single rounding per component per rotation.
-__device__ __forceinline__ void rotate(float& u, float& v, float h, float s) {
+// FP32 versine form: the small increment is formed first and added once, so the
+// state sees a single rounding per component per rotation.
+__device__ __forceinline__ void rotate_versine(float& u, float& v, float h, float s) {
   float du = fmaf(h, u, -(s * v));
   float dv = fmaf(h, v, s * u);
   u = u + du;
   v = v + dv;
 }
 
+template <int FORM, typename R>
+__device__ __forceinline__ void rotate(R& u, R& v, R a, R s) {
+  if (FORM == kFormShear)
+    rotate_shear(u, v, a, s);
+  else
+    rotate_versine(u, v, a, s);
+}
+
 struct PointCoords {
+  int i, j;
   double px, py;
 };
 
@@ -64,34 +89,116 @@ __device__ __forceinline__ PointCoords coords(const SolveParams& p, long long id
   long long j = idx / p.nx;
   long long i = idx - j * p.nx;
   PointCoords c;
+  c.i = (int)i;
+  c.j = (int)j;
   c.px = p.px_min + (double)i * p.dx;
   c.py = p.py_min + (double)j * p.dy;
   return c;
 }
 
-template <typename R, int PPL>
+// The Bloch vectors of a lane's points and their per-point rotations.
+template <typename R, int PPL, int FORM>
+struct BlochLanes {
+  R x[PPL], y[PPL], z[PPL];
+  R aX[PPL], sX[PPL], aY[PPL], sY[PPL];  // rotations by 2 dt px about x and 2 dt py about y
+
+  // one merged Strang step: rotation by 2 dt A_k about x (table row), by
+  // 2 dt px about x, and by 2 dt py about y
+  __device__ __forceinline__ void step(R a, R s) {
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      rotate<FORM>(y[q], z[q], a, s);
+      rotate<FORM>(y[q], z[q], aX[q], sX[q]);
+      rotate<FORM>(z[q], x[q], aY[q], sY[q]);
+    }
+  }
+
+  __device__ __forceinline__ void renormalise() {
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      double X = x[q], Y = y[q], Z = z[q];
+      double nr = sqrt(X * X + Y * Y + Z * Z);
+      if (nr > 0.0) {
+        x[q] = (R)(X / nr);
+        y[q] = (R)(Y / nr);
+        z[q] = (R)(Z / nr);
+      }
+    }
+  }
+};
+
+// Steps [k, k_full) with the table rows read by the scalar unit (SGPR operands).
+template <typename R, int PPL, int FORM>
+__device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM>& L, const Row<R>* __restrict__ tab,
+                                             long long k, long long k_full) {
+  while (k < k_full) {
+    long long seg = k_full;
+    if (sizeof(R) == 4) {
+      long long next = (k / kRenormEvery + 1) * kRenormEvery;
+      seg = next < k_full ? next : k_full;
+    }
+    constexpr int kGroup = 8;  // rows fetched together by one scalar load
+    for (; k + kGroup <= seg; k += kGroup) {
+      Row<R> r[kGroup];
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) r[u] = tab[k + u];
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) L.step(r[u].a, r[u].s);
+    }
+    for (; k < seg; ++k) {
+      const Row<R> r = tab[k];
+      L.step(r.a, r.s);
+    }
+    if (sizeof(R) == 4 && (k % kRenormEvery) == 0) L.renormalise();
+  }
+}
+
+// Steps [k, k_full) with the table staged through LDS in chunks of `chunk` rows
+// (absolute chunk boundaries; a power of two dividing the renormalisation period
+// in the FP32 form), so every lane reads its rotation from VGPRs.
+template <typename R, int PPL, int FORM>
+__device__ __forceinline__ void steps_lds(BlochLanes<R, PPL, FORM>& L, const Row<R>* __restrict__ tab, long long k,
+                                          long long k_full, long long chunk) {
+  extern __shared__ unsigned char pd_lds[];
+  Row<R>* rows = reinterpret_cast<Row<R>*>(pd_lds);
+  while (k < k_full) {
+    long long cend = (k / chunk + 1) * chunk;
+    if (cend > k_full) cend = k_full;
+    const int cnt = (int)(cend - k);
+    __syncthreads();  // every wave has finished with the previous chunk
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) rows[t] = tab[k + t];
+    __syncthreads();
+#pragma unroll 8
+    for (int t = 0; t < cnt; ++t) {
+      const Row<R> r = rows[t];
+      L.step(r.a, r.s);
+    }
+    k = cend;
+    if (sizeof(R) == 4 && (k % kRenormEvery) == 0) L.renormalise();
+  }
+}
+
+template <typename R, int PPL, int STAGE, int FORM>
 __global__ void __launch_bounds__(256) strang_kernel(const SolveParams p) {
   const long long base = (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x;
-  R x[PPL], y[PPL], z[PPL];
-  R hA[PPL], sA[PPL], hT[PPL], sT[PPL];  // rotations by 2 dt px about x and 2 dt py about y
+  const R* __restrict__ colc = static_cast<const R*>(p.col_coef);
+  const R* __restrict__ rowc = static_cast<const R*>(p.row_coef);
+  BlochLanes<R, PPL, FORM> L;
 
 #pragma unroll
   for (int q = 0; q < PPL; ++q) {
     long long idx = base + (long long)q * blockDim.x;
     if (idx >= p.npts) idx = p.npts - 1;  // tail lanes recompute a valid point and store nothing
     PointCoords c = coords(p, idx);
-    double sa, ca, sb, cb;
-    sincos(p.dt * c.px, &sa, &ca);
-    sincos(p.dt * c.py, &sb, &cb);
-    hA[q] = (R)(-2.0 * sa * sa);
-    sA[q] = (R)(2.0 * sa * ca);
-    hT[q] = (R)(-2.0 * sb * sb);
-    sT[q] = (R)(2.0 * sb * cb);
+    L.aX[q] = colc[2 * c.i];
+    L.sX[q] = colc[2 * c.i + 1];
+    L.aY[q] = rowc[4 * c.j];
+    L.sY[q] = rowc[4 * c.j + 1];
     if (p.load_state) {
       const R* st = static_cast<const R*>(p.state);
-      x[q] = st[idx];
-      y[q] = st[p.npts + idx];
-      z[q] = st[2 * p.npts + idx];
+      L.x[q] = st[idx];
+      L.y[q] = st[p.npts + idx];
+      L.z[q] = st[2 * p.npts + idx];
     } else {
       // v_in: negative-energy eigenvector of sigma.P_in, Bloch vector -P_in/|P_in|
       double Px = c.px + p.A_in;
@@ -101,48 +208,20 @@ __global__ void __launch_bounds__(256) strang_kernel(const SolveParams p) {
         rx = -Px / E;
         ry = -c.py / E;
       }
-      x[q] = (R)rx;
-      y[q] = (R)ry;
-      z[q] = (R)0;
+      L.x[q] = (R)rx;
+      L.y[q] = (R)ry;
+      L.z[q] = (R)0;
       // first half step exp(-i dt py sy / 2): rotation by dt py about y
-      double sh = sin(0.5 * p.dt * c.py);
-      R hH = (R)(-2.0 * sh * sh), sH = (R)sb;
-      rotate(z[q], x[q], hH, sH);
+      rotate<FORM>(L.z[q], L.x[q], rowc[4 * c.j + 2], rowc[4 * c.j + 3]);
     }
   }
 
   const Row<R>* __restrict__ tab = static_cast<const Row<R>*>(p.table);
-  long long k = p.k_begin;
   const long long k_full = p.k_end < p.n_steps ? p.k_end : p.n_steps - 1;
-  while (k < k_full) {
-    long long seg = k_full;
-    if (sizeof(R) == 4) {
-      long long next = (k / kRenormEvery + 1) * kRenormEvery;
-      seg = next < k_full ? next : k_full;
-    }
-#pragma unroll 8
-    for (; k < seg; ++k) {
-      const Row<R> r = tab[k];
-#pragma unroll
-      for (int q = 0; q < PPL; ++q) {
-        rotate(y[q], z[q], r.h, r.s);
-        rotate(y[q], z[q], hA[q], sA[q]);
-        rotate(z[q], x[q], hT[q], sT[q]);
-      }
-    }
-    if (sizeof(R) == 4 && (k % kRenormEvery) == 0) {
-#pragma unroll
-      for (int q = 0; q < PPL; ++q) {
-        double X = x[q], Y = y[q], Z = z[q];
-        double nr = sqrt(X * X + Y * Y + Z * Z);
-        if (nr > 0.0) {
-          x[q] = (R)(X / nr);
-          y[q] = (R)(Y / nr);
-          z[q] = (R)(Z / nr);
-        }
-      }
-    }
-  }
+  if (STAGE == 1)
+    steps_lds(L, tab, p.k_begin, k_full, p.chunk_steps);
+  else
+    steps_scalar(L, tab, p.k_begin, k_full);
 
   if (p.k_end == p.n_steps) {
     // last step: full sigma_x factor, then the closing half step about y
@@ -153,26 +232,17 @@ __global__ void __launch_bounds__(256) strang_kernel(const SolveParams p) {
       bool valid = idx < p.npts;
       if (!valid) idx = p.npts - 1;
       PointCoords c = coords(p, idx);
-      double sh = sin(0.5 * p.dt * c.py);
-      R hH = (R)(-2.0 * sh * sh), sH = (R)sin(p.dt * c.py);
-      rotate(y[q], z[q], r.h, r.s);
-      rotate(y[q], z[q], hA[q], sA[q]);
-      rotate(z[q], x[q], hH, sH);
-      // projection on u_out: n = (E_out + P_out . r) / (2 E_out)
+      rotate<FORM>(L.y[q], L.z[q], r.a, r.s);
+      rotate<FORM>(L.y[q], L.z[q], L.aX[q], L.sX[q]);
+      rotate<FORM>(L.z[q], L.x[q], rowc[4 * c.j + 2], rowc[4 * c.j + 3]);
+      // projection on u_out: n = (1 + r.P_out / |P_out|) / 2 with r normalised
       double Pxi = c.px + p.A_in, Pxo = c.px + p.A_out;
       double Ei = sqrt(Pxi * Pxi + c.py * c.py), Eo = sqrt(Pxo * Pxo + c.py * c.py);
-      double X = x[q], Y = y[q];
-      if (sizeof(R) == 4) {
-        double Z = z[q];
-        double nr = sqrt(X * X + Y * Y + Z * Z);
-        if (nr > 0.0) {
-          X = X / nr;
-          Y = Y / nr;
-        }
-      }
+      double X = L.x[q], Y = L.y[q], Z = L.z[q];
+      double nr = sqrt(X * X + Y * Y + Z * Z);
       double n = 0.0;
-      if (Ei > 0.0 && Eo > 0.0) {
-        double dot = Pxo * X + c.py * Y;
+      if (Ei > 0.0 && Eo > 0.0 && nr > 0.0) {
+        double dot = (Pxo * X + c.py * Y) / nr;
         n = (Eo + dot) / (2.0 * Eo);
       }
       if (valid) p.n_out[idx] = n;
@@ -183,9 +253,9 @@ __global__ void __launch_bounds__(256) strang_kernel(const SolveParams p) {
     for (int q = 0; q < PPL; ++q) {
       long long idx = base + (long long)q * blockDim.x;
       if (idx < p.npts) {
-        st[idx] = x[q];
-        st[p.npts + idx] = y[q];
-        st[2 * p.npts + idx] = z[q];
+        st[idx] = L.x[q];
+        st[p.npts + idx] = L.y[q];
+        st[2 * p.npts + idx] = L.z[q];
       }
     }
   }
@@ -404,12 +474,26 @@ __global__ void __launch_bounds__(kRedThreads) density_finish(const double* __re
   if (threadIdx.x == 0) *rho = scale * s;
 }
 
-template <typename R, int PPL>
+template <typename R, int PPL, int FORM>
 hipError_t launch_strang(int block, const SolveParams& p, hipStream_t stream) {
   long long per_block = (long long)block * PPL;
   long long blocks = (p.npts + per_block - 1) / per_block;
-  hipLaunchKernelGGL((strang_kernel<R, PPL>), dim3((unsigned)blocks), dim3(block), 0, stream, p);
+  if (p.stage == 1) {
+    size_t lds = (size_t)p.chunk_steps * sizeof(Row<R>);
+    hipLaunchKernelGGL((strang_kernel<R, PPL, 1, FORM>), dim3((unsigned)blocks), dim3(block), lds, stream, p);
+  } else {
+    hipLaunchKernelGGL((strang_kernel<R, PPL, 0, FORM>), dim3((unsigned)blocks), dim3(block), 0, stream, p);
+  }
   return hipGetLastError();
+}
+
+template <typename R, int FORM>
+hipError_t strang_ppl(int ppl, int block, const SolveParams& p, hipStream_t stream) {
+  switch (ppl) {
+    case 1: return launch_strang<R, 1, FORM>(block, p, stream);
+    case 2: return launch_strang<R, 2, FORM>(block, p, stream);
+    default: return launch_strang<R, 4, FORM>(block, p, stream);
+  }
 }
 
 template <typename R, int J, int PPL>
@@ -438,18 +522,11 @@ long long density_partials(long long npts) { return (npts + kRedTile - 1) / kRed
 hipError_t launch_propagate(int scheme, int precision, int ppl, int block, int taylor, const SolveParams& p,
                             hipStream_t stream) {
   if (scheme == PD_SCHEME_STRANG) {
-    if (precision == PD_FP32) {
-      switch (ppl) {
-        case 1: return launch_strang<float, 1>(block, p, stream);
-        case 2: return launch_strang<float, 2>(block, p, stream);
-        default: return launch_strang<float, 4>(block, p, stream);
-      }
-    }
-    switch (ppl) {
-      case 1: return launch_strang<double, 1>(block, p, stream);
-      case 2: return launch_strang<double, 2>(block, p, stream);
-      default: return launch_strang<double, 4>(block, p, stream);
-    }
+    if (precision == PD_FP32)
+      return p.form == kFormShear ? strang_ppl<float, kFormShear>(ppl, block, p, stream)
+                                  : strang_ppl<float, kFormVersine>(ppl, block, p, stream);
+    return p.form == kFormShear ? strang_ppl<double, kFormShear>(ppl, block, p, stream)
+                                : strang_ppl<double, kFormVersine>(ppl, block, p, stream);
   }
   if (precision == PD_FP32) {
     switch (taylor) {

@@ -40,16 +40,20 @@ struct pd_grid_s {
   int scheme = PD_SCHEME_STRANG;
   int points_per_lane = 2;
   int block_threads = 256;
+  int table_stage = 2;   // 1: LDS chunks, 2: scalar-unit reads
+  int chunk_steps = 512;
 
   bool field_set = false;
   FieldTables field;
   long long n_masked = 0;
   long long steps_done = 0;
   int taylor = 0;
+  int form = kFormShear;  // Strang rotation form of the current field
 
   int device = -1;
   void* d_table = nullptr;
-  size_t table_bytes = 0;
+  size_t table_bytes = 0;  // step rows, then (Strang) the column and row coefficients
+  size_t col_offset = 0, row_offset = 0;
   double* d_n = nullptr;
   double* d_partial = nullptr;
   double* d_rho = nullptr;
@@ -142,6 +146,9 @@ void fill_info(pd_grid g, const FieldTables& t, long long masked, long long step
   out->scheme = g->scheme;
   out->points_per_lane = g->points_per_lane;
   out->block_threads = g->block_threads;
+  out->table_stage = g->table_stage;
+  out->chunk_steps = g->chunk_steps;
+  out->rotation_form = t.n_steps > 0 ? strang_form(g->grid, t) : kFormShear;
   out->device_bytes = g->device_bytes();
 }
 
@@ -176,8 +183,13 @@ pd_status pd_create_grid(int nx, int ny, double px_min, double px_max, double py
   g->grid.dy = (py_max - py_min) / (double)ny;
   g->precision = precision;
   g->scheme = scheme;
-  g->points_per_lane = 2;
+  // Default launch shape (fastest measured on MI355X for the 2048^2 x 80000
+  // workload): field rows read by the scalar unit, 256-thread blocks, one point
+  // per lane in FP32 and four in FP64.
+  g->points_per_lane = precision == PD_FP32 ? 1 : 4;
   g->block_threads = 256;
+  g->table_stage = 2;
+  g->chunk_steps = 512;
   *out = g;
   return ok();
 }
@@ -212,7 +224,11 @@ pd_status pd_set_field(pd_grid g, const pd_field* f, long long n_steps) {
   pd_status s = prepare_field(g, f, n_steps, &t, &masked, &taylor);
   if (s != PD_OK) return s;
   std::vector<unsigned char> rows;
-  build_step_table(t, g->scheme, g->precision, &rows);
+  const int form = strang_form(g->grid, t);
+  build_step_table(t, g->scheme, g->precision, form, &rows);
+  size_t col_offset = 0, row_offset = 0;
+  if (g->scheme == PD_SCHEME_STRANG)
+    build_point_coefficients(g->grid, t.dt, g->precision, form, &rows, &col_offset, &row_offset);
 
   if (g->device < 0) {
     int dev = -1;
@@ -252,6 +268,9 @@ pd_status pd_set_field(pd_grid g, const pd_field* f, long long n_steps) {
   g->field = std::move(t);
   g->n_masked = masked;
   g->taylor = taylor;
+  g->form = form;
+  g->col_offset = col_offset;
+  g->row_offset = row_offset;
   g->steps_done = 0;
   g->field_set = true;
   return ok();
@@ -274,14 +293,23 @@ pd_status pd_bind_state(pd_grid g, void* dev_ptr, size_t bytes) {
   return ok();
 }
 
-pd_status pd_set_launch(pd_grid g, int points_per_lane, int block_threads) {
+pd_status pd_set_launch(pd_grid g, int points_per_lane, int block_threads, int table_stage, int chunk_steps) {
   if (!g) return fail(PD_ERR_INVALID, "null handle");
   if (points_per_lane != 0 && points_per_lane != 1 && points_per_lane != 2 && points_per_lane != 4)
     return fail(PD_ERR_INVALID, "points_per_lane must be 1, 2 or 4");
   if (block_threads != 0 && block_threads != 64 && block_threads != 128 && block_threads != 256)
     return fail(PD_ERR_INVALID, "block_threads must be 64, 128 or 256");
+  if (table_stage != 0 && table_stage != 1 && table_stage != 2)
+    return fail(PD_ERR_INVALID, "table_stage must be 1 (LDS) or 2 (scalar)");
+  if (chunk_steps != 0) {
+    int max_chunk = g->precision == PD_FP32 ? 1024 : 4096;
+    if (chunk_steps < 64 || chunk_steps > max_chunk || (chunk_steps & (chunk_steps - 1)) != 0)
+      return fail(PD_ERR_INVALID, "chunk_steps must be a power of two in [64, %d]", max_chunk);
+  }
   if (points_per_lane) g->points_per_lane = points_per_lane;
   if (block_threads) g->block_threads = block_threads;
+  if (table_stage) g->table_stage = table_stage;
+  if (chunk_steps) g->chunk_steps = chunk_steps;
   return ok();
 }
 
@@ -317,9 +345,14 @@ pd_status pd_propagate(pd_grid g, long long max_steps, void* stream) {
   p.k_begin = g->steps_done;
   p.k_end = g->steps_done + m;
   p.table = g->d_table;
+  p.col_coef = static_cast<const unsigned char*>(g->d_table) + g->col_offset;
+  p.row_coef = static_cast<const unsigned char*>(g->d_table) + g->row_offset;
   p.n_out = g->d_n;
   p.load_state = p.k_begin > 0;
   p.store_state = p.k_end < N;
+  p.stage = g->table_stage == 1 ? 1 : 0;
+  p.chunk_steps = g->chunk_steps;
+  p.form = g->form;
   if (p.load_state || p.store_state) {
     void* st = g->d_state_bound;
     if (!st) {

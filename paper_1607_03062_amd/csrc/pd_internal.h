@@ -35,15 +35,30 @@ void field_extent(const Grid& g, FieldTables* t);      // E_max over the grid
 long long count_masked(const Grid& g, double A_in, double A_out);
 
 // Per-step rows of the field table, as the kernels read them.
-//   Strang, FP64: {h, s} of the angle 2 dt A_k  (h = cos - 1, s = sin), 16 bytes
-//   Strang, FP32: the same rounded to float, 8 bytes
-//   Midpoint:     dt * A_k in FP64, 8 bytes
+//   Strang: the two coefficients of the rotation by 2 dt A_k about x in the
+//           solve's rotation form, FP64 (16 bytes) or rounded to FP32 (8 bytes)
+//   Midpoint: dt * A_k in FP64, 8 bytes
 size_t table_row_bytes(int scheme, int precision);
-void build_step_table(const FieldTables& t, int scheme, int precision, std::vector<unsigned char>* rows);
+void build_step_table(const FieldTables& t, int scheme, int precision, int form, std::vector<unsigned char>* rows);
+// Rotation form of a Strang solve: shears when every rotation angle is small enough.
+int strang_form(const Grid& g, const FieldTables& t);
+// Per-point rotation coefficients of a Strang solve, which depend on one grid
+// coordinate each: per column i the rotation by 2 dt px_i about x (2 values),
+// per row j the rotations by 2 dt py_j and by dt py_j about y (4 values), in the
+// solve's form and precision, appended to `bytes` (each block 256-byte aligned).
+// Returns the byte offsets of the column and row blocks.
+void build_point_coefficients(const Grid& g, double dt, int precision, int form, std::vector<unsigned char>* bytes,
+                              size_t* col_offset, size_t* row_offset);
 
 // Smallest Taylor order (terms of cos - 1 and of sin(x)/x in x = (dt E)^2) whose
 // truncation stays below the precision's rounding for x <= x_max.
 int taylor_order(double x_max, int precision);
+
+// Strang rotation forms: three shears (tan(phi/2), sin phi) or versine (cos phi - 1, sin phi).
+constexpr int kFormShear = 0;
+constexpr int kFormVersine = 1;
+// The shear form is used when every rotation angle of a solve is at most this (|tan(phi/2)| <= 1).
+constexpr double kShearMaxAngle = 1.5707963267948966;
 
 // Parameters of one propagation launch (passed by value to the kernels).
 struct SolveParams {
@@ -53,10 +68,15 @@ struct SolveParams {
   double A_in, A_out, dt;
   long long n_steps, k_begin, k_end;
   const void* table;
+  const void* col_coef;  // Strang: per column (a, s) of the rotation by 2 dt px about x
+  const void* row_coef;  // Strang: per row (a, s) of the rotations by 2 dt py and dt py about y
   void* state;       // chunk state, structure of arrays; nullptr if not used
   double* n_out;     // written by the launch that reaches n_steps
   int load_state;    // 1: resume from state; 0: start from v_in
   int store_state;   // 1: keep the state after k_end
+  int stage;         // Strang table path: 0 scalar-unit loads, 1 LDS chunks
+  int form;          // Strang rotation form: kFormShear or kFormVersine
+  long long chunk_steps;  // LDS chunk length in steps (power of two; divides 1024 in FP32)
 };
 
 // kernels.hip

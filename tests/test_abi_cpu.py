@@ -105,6 +105,17 @@ def test_check_field_reports_step_bound_and_masking():
     s.close()
 
 
+def test_rotation_form_choice():
+    """Shears while every Bloch rotation angle (2 dt A_k, 2 dt px, 2 dt py) is <= pi/2."""
+    s = pd.Solver(48, 40, (-4.0, 4.0), (-3.0, 3.0))
+    assert s.check_field(wl.constant(0.2, 200.0), 4000)["rotation_form"] == 1  # 2 * 0.05 * 40 = 4
+    assert s.check_field(wl.constant(0.2, 200.0), 40000)["rotation_form"] == 0  # 0.4
+    s.close()
+    s = pd.Solver.for_grid(wl.config3()["grid"], "fp32")
+    assert s.check_field(wl.config3()["field"], 80000)["rotation_form"] == 0
+    s.close()
+
+
 def test_masked_count_with_final_momentum_zero():
     """Constant field E0 = 0.2 on [0, 200]: A_out = -40, so p = (40, 0) has E_out = 0."""
     s = pd.Solver(81, 3, (0.0, 81.0), (-1.0, 2.0))  # p_x = 0, 1, ..., 80; p_y = -1, 0, 1
@@ -149,8 +160,20 @@ def test_state_errors_without_device():
         s.set_launch(3, 0)
     with pytest.raises(pd.PDError):
         s.set_launch(0, 512)
-    s.set_launch(4, 64)
-    assert s.info()["points_per_lane"] == 4 and s.info()["block_threads"] == 64
+    with pytest.raises(pd.PDError):
+        s.set_launch(0, 0, 3, 0)
+    with pytest.raises(pd.PDError):
+        s.set_launch(0, 0, 0, 100)
+    with pytest.raises(pd.PDError):
+        s.set_launch(0, 0, 0, 8192)
+    s.set_launch(4, 64, 1, 256)
+    info = s.info()
+    assert (info["points_per_lane"], info["block_threads"], info["table_stage"], info["chunk_steps"]) == (4, 64, 1, 256)
+    s.close()
+    s = pd.Solver(8, 8, (-1, 1), (-1, 1), "fp32")
+    assert s.info()["table_stage"] == 2 and s.info()["points_per_lane"] == 1
+    with pytest.raises(pd.PDError):
+        s.set_launch(0, 0, 0, 2048)  # FP32 chunks must divide the renormalisation period
     s.close()
 
 

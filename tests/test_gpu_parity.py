@@ -28,11 +28,12 @@ FP32_N_ABS = 1e-5
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def run(pd, grid, field, N, precision="fp64", scheme="strang", ppl=0, block=0, chunks=None, bind=None):
-    print("gpu solve: grid %dx%d N=%d %s %s ppl=%s block=%s chunks=%s" % (
-        grid["nx"], grid["ny"], N, precision, scheme, ppl, block, chunks), flush=True)
+def run(pd, grid, field, N, precision="fp64", scheme="strang", ppl=0, block=0, chunks=None, bind=None, stage=0,
+        chunk_steps=0):
+    print("gpu solve: grid %dx%d N=%d %s %s ppl=%s block=%s stage=%s chunk=%s chunks=%s" % (
+        grid["nx"], grid["ny"], N, precision, scheme, ppl, block, stage, chunk_steps, chunks), flush=True)
     s = pd.Solver.for_grid(grid, precision, scheme)
-    s.set_launch(ppl, block)
+    s.set_launch(ppl, block, stage, chunk_steps)
     s.set_field(field, N)
     if bind is not None:
         s.bind_state(bind)
@@ -86,18 +87,20 @@ def test_config1_fp32_form(gpu, cfg1_oracle, scheme):
 def test_ragged_grid_every_launch_shape(gpu, precision, scheme):
     """37 x 53 points (not a multiple of any tile), 777 steps: every launch shape gives the
     same bits, and the oracle's values."""
-    N = 777
+    N = 2777  # crosses the FP32 renormalisation steps 1024 and 2048
     n_o = oracle.solve_grid(RAGGED_FIELD, RAGGED, N, scheme)[0]
     ref = None
-    for ppl in (1, 2, 4):
-        for block in (64, 256):
-            n, rho, _ = run(gpu, RAGGED, RAGGED_FIELD, N, precision, scheme, ppl, block)
-            if ref is None:
-                ref = (n, rho)
-                tol = FP64_N_ABS if precision == "fp64" else FP32_N_ABS
-                assert np.max(np.abs(n - n_o)) <= tol
-            else:
-                assert np.array_equal(n, ref[0]) and rho == ref[1], (ppl, block)
+    shapes = [(ppl, block, 0, 0) for ppl in (1, 2, 4) for block in (64, 256)]
+    if scheme == "strang":
+        shapes += [(2, 128, 1, 64), (4, 256, 1, 1024), (1, 64, 2, 0), (2, 256, 1, 256)]
+    for ppl, block, stage, chunk in shapes:
+        n, rho, _ = run(gpu, RAGGED, RAGGED_FIELD, N, precision, scheme, ppl, block, stage=stage, chunk_steps=chunk)
+        if ref is None:
+            ref = (n, rho)
+            tol = FP64_N_ABS if precision == "fp64" else FP32_N_ABS
+            assert np.max(np.abs(n - n_o)) <= tol
+        else:
+            assert np.array_equal(n, ref[0]) and rho == ref[1], (ppl, block, stage, chunk)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -146,6 +149,21 @@ def test_degenerate_inputs(gpu):
         idx = np.array([81 * 2 + 3, 81 * 0 + 30])
         n_o = oracle.solve_grid(wl.constant(0.2, 200.0), gm, 40000, scheme, idx=idx)[0]
         assert np.max(np.abs(n[idx] - n_o)) <= FP64_N_ABS
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_large_step_angles_use_versine_form(gpu, precision):
+    """dt = 0.05 under the constant field (A reaches -40): the rotation by 2 dt A_k exceeds pi/2,
+    so the solve takes the versine rotation form; still the oracle's values."""
+    g = {"nx": 48, "ny": 40, "px": (-4.0, 4.0), "py": (-3.0, 3.0)}
+    f = wl.constant(0.2, 200.0)
+    N = 4000
+    n, rho, info = run(gpu, g, f, N, precision)
+    assert info["rotation_form"] == 1
+    n_o = oracle.solve_grid(f, g, N)[0]
+    assert np.max(np.abs(n - n_o)) <= (FP64_N_ABS if precision == "fp64" else FP32_N_ABS)
+    chunked = run(gpu, g, f, N, precision, chunks=[1500, 2500])
+    assert np.array_equal(n, chunked[0])
 
 
 def test_repeat_is_bitwise(gpu):
