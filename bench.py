@@ -101,9 +101,131 @@ def time_form(pd, torch, c, precision, steps, warmup, ppl, block, stage=0, chunk
     return {"t_total": t1 - t0, "wall": wall, "kernel_ms": kern_ms, "rho": rho, "n": n, "info": info}
 
 
+def run_batch(args):
+    """Config 4: 64 seeded solves of uneven grid sizes and step counts, FP32 form, in one
+    persistent graph-captured launch per pass (a step = one pass over all 64 solves)."""
+    import numpy as np
+    import torch
+
+    import paper_1607_03062_amd as pd
+    from paper_1607_03062_amd import workloads as wl
+
+    cfgs = wl.config4(count=args.batch_count)
+    solvers = []
+    for c in cfgs:
+        s = pd.Solver.for_grid(c["grid"], c["precision"])
+        s.set_field(c["field"], c["n_steps"])
+        solvers.append(s)
+    total = float(sum(c["grid"]["nx"] * c["grid"]["ny"] * c["n_steps"] for c in cfgs))
+    st = torch.cuda.Stream()
+    b = pd.Batch(solvers)
+    t_tune = time.perf_counter()
+    if not args.no_autotune:
+        b.autotune(512, stream=st)
+    t_tune = time.perf_counter() - t_tune
+    for _ in range(args.warmup):
+        b.run(stream=st)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    wall = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        w0 = time.perf_counter()
+        ev[i][0].record(st)
+        rho = b.run(stream=st)
+        ev[i][1].record(st)
+        wall.append(time.perf_counter() - w0)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    dev_ms = float(np.mean([a.elapsed_time(c) for a, c in ev]))
+    info = b.info()
+    # the same solves one after another, each alone with its default launch
+    t1 = time.perf_counter()
+    rho_alone = []
+    for s in solvers:
+        s.rewind()
+        s.propagate(-1, stream=st)
+        rho_alone.append(s.density(stream=st))
+    t_seq = time.perf_counter() - t1
+    same = bool(np.array_equal(np.array(rho_alone), rho))
+    b.close()
+    for s in solvers:
+        s.close()
+    flops = 18 * total  # every config-4 solve takes the shear form (checked by the tests)
+    line = {
+        "metric": METRIC, "value": total * args.steps / t, "unit": "point-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "%d seeded solves (grids 256^2..2048^2 on [-4,4]^2, 8k-78k steps), FP32 form, "
+                               "one persistent graph-captured launch per pass" % len(cfgs),
+                   "solves": len(cfgs), "point_steps_per_pass": total, "points_per_lane": info["points_per_lane"],
+                   "block_threads": info["block_threads"], "work_items": info["work_items"]},
+        "graph_captured": info["graph_captured"], "device_ms_per_pass": dev_ms,
+        "p50_ms": float(np.percentile(np.array(wall) * 1e3, 50)),
+        "p99_ms": float(np.percentile(np.array(wall) * 1e3, 99)),
+        "autotune_s": t_tune,
+        "sequential_alone": {"value": total / t_seq, "ms": t_seq * 1e3, "rho_bitwise_equal_to_batch": same},
+        "roofline": {"bound": "alu", "achieved": flops / (dev_ms * 1e-3) / 1e12, "peak": PEAK_TFLOPS["fp32"],
+                     "unit": "TFLOP/s", "frac": flops / (dev_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
+                     "traffic": None},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_serve(args):
+    """Config 5: a Poisson stream of solve requests (config-4 distributions, 50/50 FP32 /
+    FP64) served by continuous batching; arrival rate 0.7 x the measured capacity."""
+    import numpy as np
+    import torch
+
+    import paper_1607_03062_amd as pd
+    from paper_1607_03062_amd import serve
+    from paper_1607_03062_amd import workloads as wl
+
+    st = torch.cuda.Stream()
+    budget = int(args.budget_gb * (1 << 30))
+    # capacity: a closed set of requests, all present at t = 0
+    cap_reqs = [serve.Request.from_workload(w) for w in wl.config5(count=args.capacity_requests, seed=55,
+                                                                     rate_per_s=1e9)]
+    ex = serve.GpuExecutor(pd, stream=st)
+    cap = serve.Server(ex, budget, epoch_steps=args.epoch_steps).run(cap_reqs)
+    ex.close()
+    mean_ps = float(np.mean([r.point_steps for r in cap_reqs]))
+    capacity_rps = cap.point_steps_per_s / mean_ps
+    rate = args.load * capacity_rps
+    reqs = [serve.Request.from_workload(w) for w in wl.config5(count=args.requests, seed=5, rate_per_s=rate)]
+    ex = serve.GpuExecutor(pd, stream=st)
+    res = serve.Server(ex, budget, epoch_steps=args.epoch_steps).run(reqs)
+    ex.close()
+    line = {
+        "metric": METRIC, "value": res.point_steps_per_s, "unit": "point-steps/s", "n_gpus": 1,
+        "steps": res.completed, "warmup": 0, "ms_per_step": res.makespan_s / max(res.completed, 1) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "Poisson stream of %d solve requests (config-4 distributions, 50/50 FP32/FP64), "
+                               "rate %.1f req/s = %.2f x capacity, HBM budget %.0f GiB, epochs of %d steps" % (
+                                   args.requests, rate, args.load, args.budget_gb, args.epoch_steps),
+                   "requests": args.requests, "rate_per_s": rate, "budget_bytes": budget,
+                   "epoch_steps": args.epoch_steps},
+        "p50_ms": res.p50_ms, "p99_ms": res.p99_ms, "mean_ms": res.mean_ms, "serve": res.as_dict(),
+        "capacity": {"requests_per_s": capacity_rps, "point_steps_per_s": cap.point_steps_per_s,
+                     "requests": args.capacity_requests},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["cfg3", "batch", "serve"], default="cfg3")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--requests", type=int, default=1000)
+    ap.add_argument("--capacity-requests", type=int, default=48)
+    ap.add_argument("--load", type=float, default=0.7)
+    ap.add_argument("--budget-gb", type=float, default=16.0)
+    ap.add_argument("--epoch-steps", type=int, default=2048)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
@@ -130,6 +252,10 @@ def main():
 
     pd.require_native()
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        return run_batch(args)
+    if args.workload == "serve":
+        return run_serve(args)
     c = wl.config3(n=args.grid, precision=args.precision)
     npts = c["grid"]["nx"] * c["grid"]["ny"]
     ps_per_solve = npts * c["n_steps"]

@@ -111,6 +111,8 @@ typedef struct {
   int rotation_form;        /* Strang: 0 = three shears per rotation (every rotation angle of the
                                solve <= pi/2), 1 = versine form (h = cos - 1, s = sin) */
   size_t device_bytes;      /* device memory the handle owns */
+  size_t solve_bytes;       /* device memory a solve of this field needs, chunk state included:
+                               tables + n(p) + density partials + state (for admission control) */
 } pd_info;
 
 /* Create a solver on an nx x ny node grid (1 <= nx, ny <= 65536; finite ranges
@@ -182,6 +184,78 @@ pd_status pd_get_info(pd_grid g, pd_info* out);
 
 /* Release the handle and the device memory it owns.  NULL is a no-op. */
 void pd_destroy_grid(pd_grid g);
+
+/* Choose the launch shape of g by timing candidates on the first
+   min(trial_steps, N) steps of g's own solve on `stream`: points_per_lane
+   {1, 2, 4} x block_threads {64, 256} x (scalar-unit rows, LDS chunks of 256 or
+   1024 steps for Strang).  The fastest is applied as by pd_set_launch; the solve
+   is left rewound (steps_done = 0).  With use_cache != 0 and the environment
+   variable PD_AUTOTUNE_CACHE naming a file, a shape stored there for the same
+   (GPU architecture, precision, scheme, rotation form, floor(log2 points)) is
+   applied without timing, and a newly timed one is appended. */
+pd_status pd_autotune(pd_grid g, long long trial_steps, int use_cache, void* stream);
+
+/* ---- Batches: many Strang solves in one persistent launch ----------------
+
+   A batch holds grids (any sizes, fields, step counts and precisions, each with
+   its field set).  Its launch is one persistent kernel: each block takes the
+   next work item -- one tile of block_threads * points_per_lane points of one
+   grid -- from a device counter until none is left; the items of the grids with
+   the most steps come first.  Every item does the same arithmetic as the
+   single-grid kernel with the scalar-unit table path, so each grid's n(p) and
+   rho are bit-identical to its solve alone.  Densities of the grids that finish
+   are reduced in the same launch sequence (per grid, same fixed order as
+   pd_density).  Grids must stay alive while they are members and must not be
+   used with pd_propagate while a batch call on them is in flight. */
+typedef struct pd_batch_s* pd_batch;
+
+typedef struct {
+  int n_grids;
+  int points_per_lane;
+  int block_threads;
+  int graph_captured;     /* 1 if the whole-solve launch is captured and current */
+  int work_items;         /* items of the last launch */
+  long long n_points;     /* sum over members */
+  double point_steps;     /* sum over members of points x N */
+} pd_batch_info;
+
+pd_status pd_batch_create(pd_batch* out);
+/* Add a Strang grid (PD_ERR_UNSUPPORTED for the midpoint scheme). */
+pd_status pd_batch_add(pd_batch b, pd_grid g);
+/* Remove one member (PD_ERR_INVALID if it is not one); remove a grid from every
+   batch before destroying it.  Neither call touches the grids themselves. */
+pd_status pd_batch_remove(pd_batch b, pd_grid g);
+/* Remove every member. */
+pd_status pd_batch_clear(pd_batch b);
+int pd_batch_size(pd_batch b);
+/* Members in the order they were added; capacity >= pd_batch_size(b). */
+pd_status pd_batch_members(pd_batch b, pd_grid* out, int capacity);
+/* Launch shape of the persistent kernel: points_per_lane {1, 2, 4},
+   block_threads {64, 128, 256}; 0 keeps the current value. */
+pd_status pd_batch_set_launch(pd_batch b, int points_per_lane, int block_threads);
+/* Run every member's whole solve from t_i: counter reset, the persistent
+   kernel and the batched density, captured into a HIP graph on the first call
+   and replayed while the membership, the members' fields and the launch shape
+   are unchanged (the graph holds kernel nodes only).  Members end with
+   steps_done = N and n(p) in their buffers (pd_density works on them).
+   rho_out: host array of pd_batch_size(b) doubles, in member order (may be
+   NULL; if given, the call waits for stream). */
+pd_status pd_batch_run(pd_batch b, double* rho_out, void* stream);
+/* One epoch of continuous batching: advance every member that is not complete
+   by up to max_steps steps from where it stands (state kept in each grid's
+   device state buffer between calls), in one persistent launch, and reduce the
+   densities of the members that complete.  rho_out[i] (host, may be NULL) is
+   written for members that complete in this call; finished_out[i] (host, may
+   be NULL) is 1 for every complete member.  Waits for stream if rho_out is
+   given. */
+pd_status pd_batch_step(pd_batch b, long long max_steps, double* rho_out, int* finished_out, void* stream);
+pd_status pd_batch_get_info(pd_batch b, pd_batch_info* out);
+/* Time points_per_lane {1, 2, 4} x block_threads {64, 128, 256} over the first
+   trial_steps steps of every member, keep the fastest; members are left
+   rewound. */
+pd_status pd_batch_autotune(pd_batch b, long long trial_steps, void* stream);
+/* Release the batch (not its grids).  NULL is a no-op. */
+void pd_batch_destroy(pd_batch b);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* pd_last_error(void);

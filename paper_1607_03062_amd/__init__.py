@@ -9,6 +9,7 @@ load the library; the first solver does, and fails loudly if it is not built.
 from ._lib import (  # noqa: F401
     LIB_PATH,
     PDError,
+    Batch,
     Solver,
     load,
 )

@@ -68,6 +68,7 @@ class pd_info(ctypes.Structure):
         ("chunk_steps", ctypes.c_int),
         ("rotation_form", ctypes.c_int),
         ("device_bytes", ctypes.c_size_t),
+        ("solve_bytes", ctypes.c_size_t),
     ]
 
     def as_dict(self) -> dict:
@@ -101,7 +102,35 @@ SIGNATURES = [
     ("pd_destroy_grid", None, [_vp]),
     ("pd_last_error", ctypes.c_char_p, []),
     ("pd_version", ctypes.c_char_p, []),
+    ("pd_autotune", ctypes.c_int, [_vp, ctypes.c_longlong, ctypes.c_int, _vp]),
+    ("pd_batch_create", ctypes.c_int, [ctypes.POINTER(_vp)]),
+    ("pd_batch_add", ctypes.c_int, [_vp, _vp]),
+    ("pd_batch_remove", ctypes.c_int, [_vp, _vp]),
+    ("pd_batch_clear", ctypes.c_int, [_vp]),
+    ("pd_batch_size", ctypes.c_int, [_vp]),
+    ("pd_batch_members", ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_int]),
+    ("pd_batch_set_launch", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    ("pd_batch_run", ctypes.c_int, [_vp, _dp, _vp]),
+    ("pd_batch_step", ctypes.c_int, [_vp, ctypes.c_longlong, _dp, ctypes.POINTER(ctypes.c_int), _vp]),
+    ("pd_batch_get_info", ctypes.c_int, [_vp, ctypes.c_void_p]),
+    ("pd_batch_autotune", ctypes.c_int, [_vp, ctypes.c_longlong, _vp]),
+    ("pd_batch_destroy", None, [_vp]),
 ]
+
+
+class pd_batch_info(ctypes.Structure):
+    _fields_ = [
+        ("n_grids", ctypes.c_int),
+        ("points_per_lane", ctypes.c_int),
+        ("block_threads", ctypes.c_int),
+        ("graph_captured", ctypes.c_int),
+        ("work_items", ctypes.c_int),
+        ("n_points", ctypes.c_longlong),
+        ("point_steps", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 def load() -> ctypes.CDLL:
@@ -244,6 +273,11 @@ class Solver:
                                    int(chunk_steps)), "pd_set_launch")
         return self
 
+    def autotune(self, trial_steps: int = 2048, use_cache: bool = False, stream=None):
+        check(load().pd_autotune(self._h, int(trial_steps), 1 if use_cache else 0, stream_handle(stream)),
+              "pd_autotune")
+        return self
+
     def info(self) -> dict:
         info = pd_info()
         check(load().pd_get_info(self._h, ctypes.byref(info)), "pd_get_info")
@@ -266,3 +300,74 @@ class Solver:
     def __exit__(self, *exc):
         self.close()
         return False
+
+
+class Batch:
+    """Many Strang solves in one persistent launch (pd_batch handle).  Member
+    Solvers must stay alive while they are in the batch."""
+
+    def __init__(self, solvers=()):
+        h = _vp()
+        check(load().pd_batch_create(ctypes.byref(h)), "pd_batch_create")
+        self._h = h
+        self.members = []
+        for s in solvers:
+            self.add(s)
+
+    def add(self, solver: Solver):
+        check(load().pd_batch_add(self._h, solver.handle), "pd_batch_add")
+        self.members.append(solver)
+        return self
+
+    def remove(self, solver: Solver):
+        check(load().pd_batch_remove(self._h, solver.handle), "pd_batch_remove")
+        self.members.remove(solver)
+        return self
+
+    def clear(self):
+        check(load().pd_batch_clear(self._h), "pd_batch_clear")
+        self.members = []
+        return self
+
+    def __len__(self):
+        return int(load().pd_batch_size(self._h))
+
+    def set_launch(self, points_per_lane: int = 0, block_threads: int = 0):
+        check(load().pd_batch_set_launch(self._h, int(points_per_lane), int(block_threads)), "pd_batch_set_launch")
+        return self
+
+    def run(self, stream=None, want_rho: bool = True):
+        """Every member's whole solve; returns the members' rho (numpy array) or None."""
+        rho = np.zeros(len(self.members)) if want_rho else None
+        check(load().pd_batch_run(self._h, rho.ctypes.data_as(_dp) if want_rho else None, stream_handle(stream)),
+              "pd_batch_run")
+        return rho
+
+    def step(self, max_steps: int, stream=None, want_rho: bool = True):
+        """One epoch; returns (rho array with NaN for members not completing now, finished flags)."""
+        n = len(self.members)
+        rho = np.full(n, np.nan)
+        fin = (ctypes.c_int * max(n, 1))()
+        check(load().pd_batch_step(self._h, int(max_steps), rho.ctypes.data_as(_dp) if want_rho else None, fin,
+                                   stream_handle(stream)), "pd_batch_step")
+        return (rho if want_rho else None), np.array(fin[:n], dtype=bool)
+
+    def autotune(self, trial_steps: int = 1024, stream=None):
+        check(load().pd_batch_autotune(self._h, int(trial_steps), stream_handle(stream)), "pd_batch_autotune")
+        return self
+
+    def info(self) -> dict:
+        info = pd_batch_info()
+        check(load().pd_batch_get_info(self._h, ctypes.byref(info)), "pd_batch_get_info")
+        return info.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

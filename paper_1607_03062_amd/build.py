@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpd.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["kernels.hip", "pd_api.cpp", "field.cpp", "batch.cpp"]
+SOURCES = ["kernels.hip", "pd_api.cpp", "field.cpp", "batch.cpp", "autotune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PD_OFFLOAD_ARCH", "gfx950")

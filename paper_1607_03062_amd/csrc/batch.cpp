@@ -1,0 +1,412 @@
+// Batched Strang solves (declared and documented in include/pd.h): many grids,
+// of any size, field, step count and precision, in one persistent launch.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pd.h"
+#include "pd_internal.h"
+
+using namespace pdx;
+
+struct pd_batch_s {
+  std::vector<pd_grid> grids;
+  int device = -1;
+  int points_per_lane = 1;
+  int block_threads = 256;
+
+  // device descriptors
+  BatchSolve* d_solves = nullptr;
+  size_t cap_solves = 0;
+  BatchItem* d_items = nullptr;
+  size_t cap_items = 0;
+  DensityJob* d_jobs = nullptr;
+  size_t cap_jobs = 0;
+  double* d_rho = nullptr;  // one rho per member, in member order
+  size_t cap_rho_dev = 0;
+  unsigned int* d_counter = nullptr;
+
+  // pinned host staging of the descriptors and of rho
+  unsigned char* h_stage = nullptr;
+  size_t cap_stage = 0;
+  double* h_rho = nullptr;
+  size_t cap_rho = 0;
+  hipEvent_t staged = nullptr;  // recorded after the last upload from h_stage
+
+  // captured whole-solve launch
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<pd_grid> graph_grids;
+  std::vector<long long> graph_versions;
+  int graph_ppl = 0, graph_block = 0;
+  int n_items_last = 0;
+};
+
+namespace {
+
+void free_dev(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+template <typename T>
+pd_status ensure_device(T** p, size_t* cap, size_t n) {
+  if (n <= *cap) return PD_OK;
+  free_dev(*p);
+  *p = nullptr;
+  *cap = 0;
+  size_t want = std::max(n, *cap * 2);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), want * sizeof(T));
+  if (e != hipSuccess) return hip_error(e, "hipMalloc(batch descriptors)");
+  *cap = want;
+  return PD_OK;
+}
+
+pd_status ensure_pinned(unsigned char** p, size_t* cap, size_t n) {
+  if (n <= *cap) return PD_OK;
+  if (*p) (void)hipHostFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  size_t want = std::max(n, *cap * 2);
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(p), want, hipHostMallocDefault);
+  if (e != hipSuccess) return hip_error(e, "hipHostMalloc(batch staging)");
+  *cap = want;
+  return PD_OK;
+}
+
+void drop_graph(pd_batch b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->graph_grids.clear();
+  b->graph_versions.clear();
+}
+
+bool graph_current(pd_batch b) {
+  if (!b->exec || b->graph_grids != b->grids || b->graph_ppl != b->points_per_lane ||
+      b->graph_block != b->block_threads)
+    return false;
+  for (size_t i = 0; i < b->grids.size(); ++i)
+    if (b->graph_versions[i] != b->grids[i]->version) return false;
+  return true;
+}
+
+struct Plan {
+  std::vector<BatchSolve> solves;
+  std::vector<BatchItem> items;
+  std::vector<DensityJob> jobs;
+  long long density_tiles = 0;
+};
+
+// Descriptors for advancing member i over steps [begin[i], end[i]) (no work
+// where begin == end); jobs for the members whose end reaches their last step.
+pd_status make_plan(pd_batch b, const std::vector<long long>& begin, const std::vector<long long>& end, Plan* plan) {
+  const size_t n = b->grids.size();
+  plan->solves.resize(n);
+  std::vector<size_t> order;
+  for (size_t i = 0; i < n; ++i) {
+    pd_grid g = b->grids[i];
+    void* st = nullptr;
+    if (begin[i] < end[i] && (begin[i] > 0 || end[i] < g->field.n_steps)) {
+      pd_status s = grid_state_buffer(g, &st);
+      if (s != PD_OK) return s;
+    }
+    plan->solves[i].p = g->solve_params(begin[i], end[i], st);
+    plan->solves[i].p.stage = 0;  // the persistent kernel reads field rows with the scalar unit
+    plan->solves[i].precision = g->precision;
+    plan->solves[i].form = g->form;
+    if (begin[i] < end[i]) order.push_back(i);
+  }
+  // Longest first: every tile of a solve costs (end - begin) steps per point.
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t a, size_t c) { return end[a] - begin[a] > end[c] - begin[c]; });
+  const long long tile = (long long)b->block_threads * b->points_per_lane;
+  plan->items.clear();
+  for (size_t i : order) {
+    long long npts = b->grids[i]->grid.points();
+    for (long long base = 0; base < npts; base += tile) plan->items.push_back(BatchItem{(int)i, 0, base});
+  }
+  if (plan->items.size() > (size_t)0x7fffffff) return set_error(PD_ERR_INVALID, "too many work items");
+  plan->jobs.clear();
+  plan->density_tiles = 0;
+  for (size_t i = 0; i < n; ++i) {
+    pd_grid g = b->grids[i];
+    if (!(begin[i] < end[i] && end[i] == g->field.n_steps)) continue;
+    DensityJob j{};
+    j.n = g->d_n;
+    j.npts = g->grid.points();
+    j.tile_begin = plan->density_tiles;
+    j.partial = g->d_partial;
+    j.rho = g->d_rho;
+    j.rho_copy = b->d_rho + i;
+    j.scale = g->density_scale();
+    plan->jobs.push_back(j);
+    plan->density_tiles += density_partials(j.npts);
+  }
+  return PD_OK;
+}
+
+// Copy the plan's descriptors to the device through the pinned staging buffer.
+pd_status upload(pd_batch b, const Plan& plan, hipStream_t stream) {
+  pd_status s;
+  if ((s = ensure_device(&b->d_solves, &b->cap_solves, std::max<size_t>(plan.solves.size(), 1))) != PD_OK) return s;
+  if ((s = ensure_device(&b->d_items, &b->cap_items, std::max<size_t>(plan.items.size(), 1))) != PD_OK) return s;
+  if ((s = ensure_device(&b->d_jobs, &b->cap_jobs, std::max<size_t>(plan.jobs.size(), 1))) != PD_OK) return s;
+  const size_t a = plan.solves.size() * sizeof(BatchSolve), c = plan.items.size() * sizeof(BatchItem),
+               d = plan.jobs.size() * sizeof(DensityJob);
+  // the previous upload from the staging buffer must have been consumed
+  hipError_t e = hipEventSynchronize(b->staged);
+  if (e != hipSuccess) return hip_error(e, "hipEventSynchronize");
+  if ((s = ensure_pinned(&b->h_stage, &b->cap_stage, a + c + d + 1)) != PD_OK) return s;
+  std::memcpy(b->h_stage, plan.solves.data(), a);
+  std::memcpy(b->h_stage + a, plan.items.data(), c);
+  std::memcpy(b->h_stage + a + c, plan.jobs.data(), d);
+  if (a && (e = hipMemcpyAsync(b->d_solves, b->h_stage, a, hipMemcpyHostToDevice, stream)) != hipSuccess)
+    return hip_error(e, "hipMemcpyAsync(solves)");
+  if (c && (e = hipMemcpyAsync(b->d_items, b->h_stage + a, c, hipMemcpyHostToDevice, stream)) != hipSuccess)
+    return hip_error(e, "hipMemcpyAsync(items)");
+  if (d && (e = hipMemcpyAsync(b->d_jobs, b->h_stage + a + c, d, hipMemcpyHostToDevice, stream)) != hipSuccess)
+    return hip_error(e, "hipMemcpyAsync(jobs)");
+  if ((e = hipEventRecord(b->staged, stream)) != hipSuccess) return hip_error(e, "hipEventRecord");
+  return PD_OK;
+}
+
+pd_status enqueue(pd_batch b, const Plan& plan, hipStream_t stream) {
+  hipError_t e;
+  if (!plan.items.empty()) {
+    int per_cu = batch_blocks_per_cu(b->points_per_lane, b->block_threads);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || cus <= 0)
+      cus = 1;
+    long long blocks = std::min<long long>((long long)cus * per_cu, (long long)plan.items.size());
+    e = launch_batch(b->points_per_lane, b->block_threads, (int)blocks, b->d_solves, b->d_items,
+                     (int)plan.items.size(), b->d_counter, stream);
+    if (e != hipSuccess) return hip_error(e, "batch launch");
+  }
+  e = launch_batch_density(b->d_jobs, (int)plan.jobs.size(), plan.density_tiles, stream);
+  if (e != hipSuccess) return hip_error(e, "batch density launch");
+  return PD_OK;
+}
+
+pd_status check_members(pd_batch b) {
+  if (b->grids.empty()) return set_error(PD_ERR_STATE, "empty batch");
+  for (pd_grid g : b->grids) {
+    if (!g->field_set) return set_error(PD_ERR_STATE, "a member grid has no field");
+    if (g->device != b->device) return set_error(PD_ERR_INVALID, "member grids are on different devices");
+  }
+  return PD_OK;
+}
+
+// Copy the members' rho to rho_out; only members with completed[i] set (all if
+// completed is null) are written.
+pd_status copy_rho(pd_batch b, double* rho_out, const std::vector<char>* completed, hipStream_t stream) {
+  if (!rho_out) return PD_OK;
+  const size_t n = b->grids.size();
+  pd_status s = ensure_pinned(reinterpret_cast<unsigned char**>(&b->h_rho), &b->cap_rho, n * sizeof(double));
+  if (s != PD_OK) return s;
+  hipError_t e = hipMemcpyAsync(b->h_rho, b->d_rho, n * sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return hip_error(e, "copy of rho");
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_error(e, "hipStreamSynchronize");
+  for (size_t i = 0; i < n; ++i)
+    if (!completed || (*completed)[i]) rho_out[i] = b->h_rho[i];
+  return PD_OK;
+}
+
+pd_status prepare_device(pd_batch b) {
+  if (b->device >= 0) return PD_OK;
+  b->device = b->grids.empty() ? -1 : b->grids[0]->device;
+  if (b->device < 0) return set_error(PD_ERR_STATE, "a member grid has no field");
+  DeviceScope scope(b->device);
+  hipError_t e;
+  if ((e = hipMalloc(&b->d_counter, sizeof(unsigned int))) != hipSuccess) return hip_error(e, "hipMalloc(counter)");
+  if ((e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming)) != hipSuccess)
+    return hip_error(e, "hipEventCreate");
+  if ((e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+    return hip_error(e, "hipStreamCreate");
+  return PD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pd_status pd_batch_create(pd_batch* out) {
+  if (!out) return set_error(PD_ERR_INVALID, "null output handle pointer");
+  *out = new (std::nothrow) pd_batch_s();
+  if (!*out) return set_error(PD_ERR_NOMEM, "host allocation failed");
+  return PD_OK;
+}
+
+pd_status pd_batch_add(pd_batch b, pd_grid g) {
+  if (!b || !g) return set_error(PD_ERR_INVALID, "null handle");
+  if (g->scheme != PD_SCHEME_STRANG) return set_error(PD_ERR_UNSUPPORTED, "batches run Strang solves only");
+  if (std::find(b->grids.begin(), b->grids.end(), g) != b->grids.end())
+    return set_error(PD_ERR_INVALID, "grid already in the batch");
+  b->grids.push_back(g);
+  return PD_OK;
+}
+
+pd_status pd_batch_remove(pd_batch b, pd_grid g) {
+  if (!b || !g) return set_error(PD_ERR_INVALID, "null handle");
+  auto it = std::find(b->grids.begin(), b->grids.end(), g);
+  if (it == b->grids.end()) return set_error(PD_ERR_INVALID, "grid is not in the batch");
+  b->grids.erase(it);
+  // a captured graph may still name the grid: drop it so no replay can reach it
+  if (std::find(b->graph_grids.begin(), b->graph_grids.end(), g) != b->graph_grids.end()) {
+    DeviceScope scope(b->device);
+    drop_graph(b);
+  }
+  return PD_OK;
+}
+
+pd_status pd_batch_clear(pd_batch b) {
+  if (!b) return set_error(PD_ERR_INVALID, "null handle");
+  b->grids.clear();
+  if (b->exec) {
+    DeviceScope scope(b->device);
+    drop_graph(b);
+  }
+  return PD_OK;
+}
+
+int pd_batch_size(pd_batch b) { return b ? (int)b->grids.size() : 0; }
+
+pd_status pd_batch_members(pd_batch b, pd_grid* out, int capacity) {
+  if (!b || (!out && capacity > 0)) return set_error(PD_ERR_INVALID, "null argument");
+  if (capacity < (int)b->grids.size()) return set_error(PD_ERR_INVALID, "capacity smaller than the batch");
+  for (size_t i = 0; i < b->grids.size(); ++i) out[i] = b->grids[i];
+  return PD_OK;
+}
+
+pd_status pd_batch_set_launch(pd_batch b, int points_per_lane, int block_threads) {
+  if (!b) return set_error(PD_ERR_INVALID, "null handle");
+  if (points_per_lane != 0 && points_per_lane != 1 && points_per_lane != 2 && points_per_lane != 4)
+    return set_error(PD_ERR_INVALID, "points_per_lane must be 1, 2 or 4");
+  if (block_threads != 0 && block_threads != 64 && block_threads != 128 && block_threads != 256)
+    return set_error(PD_ERR_INVALID, "block_threads must be 64, 128 or 256");
+  if (points_per_lane) b->points_per_lane = points_per_lane;
+  if (block_threads) b->block_threads = block_threads;
+  return PD_OK;
+}
+
+pd_status pd_batch_run(pd_batch b, double* rho_out, void* stream) {
+  if (!b) return set_error(PD_ERR_INVALID, "null handle");
+  pd_status s = PD_OK;
+  if (!b->grids.empty() && b->device < 0 && b->grids[0]->field_set && (s = prepare_device(b)) != PD_OK) return s;
+  if ((s = check_members(b)) != PD_OK) return s;
+  DeviceScope scope(b->device);
+  if (!scope.ok) return set_error(PD_ERR_DEVICE, "cannot select device %d", b->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!graph_current(b)) {
+    drop_graph(b);
+    const size_t n = b->grids.size();
+    if ((s = ensure_device(&b->d_rho, &b->cap_rho_dev, n)) != PD_OK) return s;
+    std::vector<long long> begin(n, 0), end(n);
+    for (size_t i = 0; i < n; ++i) end[i] = b->grids[i]->field.n_steps;
+    Plan plan;
+    if ((s = make_plan(b, begin, end, &plan)) != PD_OK) return s;
+    if ((s = upload(b, plan, b->capture_stream)) != PD_OK) return s;
+    hipError_t e = hipStreamSynchronize(b->capture_stream);
+    if (e != hipSuccess) return hip_error(e, "hipStreamSynchronize");
+    // Capture: counter reset, persistent kernel, batched density (kernels only).
+    if ((e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_error(e, "hipStreamBeginCapture");
+    pd_status se = enqueue(b, plan, b->capture_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(b->capture_stream, &graph);
+    if (se != PD_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return se;
+    }
+    if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
+    b->graph = graph;
+    if ((e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+      drop_graph(b);
+      return hip_error(e, "hipGraphInstantiate");
+    }
+    b->graph_grids = b->grids;
+    b->graph_versions.clear();
+    for (pd_grid g : b->grids) b->graph_versions.push_back(g->version);
+    b->graph_ppl = b->points_per_lane;
+    b->graph_block = b->block_threads;
+    b->n_items_last = (int)plan.items.size();
+  }
+  hipError_t e = hipGraphLaunch(b->exec, st);
+  if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
+  for (pd_grid g : b->grids) g->steps_done = g->field.n_steps;
+  return copy_rho(b, rho_out, nullptr, st);
+}
+
+pd_status pd_batch_step(pd_batch b, long long max_steps, double* rho_out, int* finished_out, void* stream) {
+  if (!b) return set_error(PD_ERR_INVALID, "null handle");
+  if (max_steps < 1) return set_error(PD_ERR_INVALID, "max_steps must be >= 1");
+  pd_status s = PD_OK;
+  if (!b->grids.empty() && b->device < 0 && b->grids[0]->field_set && (s = prepare_device(b)) != PD_OK) return s;
+  if ((s = check_members(b)) != PD_OK) return s;
+  DeviceScope scope(b->device);
+  if (!scope.ok) return set_error(PD_ERR_DEVICE, "cannot select device %d", b->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t n = b->grids.size();
+  if ((s = ensure_device(&b->d_rho, &b->cap_rho_dev, n)) != PD_OK) return s;
+  std::vector<long long> begin(n), end(n);
+  for (size_t i = 0; i < n; ++i) {
+    pd_grid g = b->grids[i];
+    begin[i] = g->steps_done;
+    end[i] = std::min(g->field.n_steps, g->steps_done + max_steps);
+  }
+  Plan plan;
+  if ((s = make_plan(b, begin, end, &plan)) != PD_OK) return s;
+  if ((s = upload(b, plan, st)) != PD_OK) return s;
+  if ((s = enqueue(b, plan, st)) != PD_OK) return s;
+  b->n_items_last = (int)plan.items.size();
+  std::vector<char> completed(n, 0);
+  for (size_t i = 0; i < n; ++i) {
+    completed[i] = begin[i] < end[i] && end[i] == b->grids[i]->field.n_steps;
+    b->grids[i]->steps_done = end[i];
+  }
+  if (finished_out)
+    for (size_t i = 0; i < n; ++i) finished_out[i] = b->grids[i]->steps_done == b->grids[i]->field.n_steps;
+  return copy_rho(b, rho_out, &completed, st);
+}
+
+pd_status pd_batch_get_info(pd_batch b, pd_batch_info* out) {
+  if (!b || !out) return set_error(PD_ERR_INVALID, "null argument");
+  std::memset(out, 0, sizeof *out);
+  out->n_grids = (int)b->grids.size();
+  out->points_per_lane = b->points_per_lane;
+  out->block_threads = b->block_threads;
+  out->graph_captured = graph_current(b) ? 1 : 0;
+  out->work_items = b->n_items_last;
+  for (pd_grid g : b->grids) {
+    out->n_points += g->grid.points();
+    out->point_steps += (double)g->grid.points() * (double)g->field.n_steps;
+  }
+  return PD_OK;
+}
+
+void pd_batch_destroy(pd_batch b) {
+  if (!b) return;
+  if (b->device >= 0) {
+    DeviceScope scope(b->device);
+    drop_graph(b);
+    if (b->staged) {
+      (void)hipEventSynchronize(b->staged);
+      (void)hipEventDestroy(b->staged);
+    }
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    free_dev(b->d_solves);
+    free_dev(b->d_items);
+    free_dev(b->d_jobs);
+    free_dev(b->d_rho);
+    free_dev(b->d_counter);
+    if (b->h_stage) (void)hipHostFree(b->h_stage);
+    if (b->h_rho) (void)hipHostFree(b->h_rho);
+  }
+  delete b;
+}
+
+}  // extern "C"

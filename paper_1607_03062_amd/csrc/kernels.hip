@@ -178,9 +178,10 @@ __device__ __forceinline__ void steps_lds(BlochLanes<R, PPL, FORM>& L, const Row
   }
 }
 
+// One tile of a Strang solve: the block's lanes own points base + q * blockDim.x,
+// q < PPL; steps [p.k_begin, p.k_end).
 template <typename R, int PPL, int STAGE, int FORM>
-__global__ void __launch_bounds__(256) strang_kernel(const SolveParams p) {
-  const long long base = (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x;
+__device__ __forceinline__ void strang_tile(const SolveParams& p, const long long base) {
   const R* __restrict__ colc = static_cast<const R*>(p.col_coef);
   const R* __restrict__ rowc = static_cast<const R*>(p.row_coef);
   BlochLanes<R, PPL, FORM> L;
@@ -257,6 +258,50 @@ __global__ void __launch_bounds__(256) strang_kernel(const SolveParams p) {
         st[p.npts + idx] = L.y[q];
         st[2 * p.npts + idx] = L.z[q];
       }
+    }
+  }
+}
+
+template <typename R, int PPL, int STAGE, int FORM>
+__global__ void __launch_bounds__(256) strang_kernel(const SolveParams p) {
+  strang_tile<R, PPL, STAGE, FORM>(p, (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Batched Strang solves in one persistent launch.  Every block takes the next
+// work item (one tile of one solve) from a global counter until none is left;
+// the host orders the items longest first.  An item's arithmetic is the same as
+// in the single-solve kernel, so each solve's result does not depend on the
+// batch it runs in.
+
+__global__ void batch_reset(unsigned int* counter) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
+}
+
+template <int PPL>
+__global__ void __launch_bounds__(256) batch_kernel(const BatchSolve* __restrict__ solves,
+                                                    const BatchItem* __restrict__ items, int n_items,
+                                                    unsigned int* counter) {
+  __shared__ int next;
+  for (;;) {
+    __syncthreads();  // every lane has read the previous item index
+    if (threadIdx.x == 0) next = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int it = next;
+    if (it >= n_items) return;  // uniform over the block
+    const BatchItem w = items[it];
+    const BatchSolve& s = solves[w.solve];
+    const long long base = w.base + threadIdx.x;
+    if (s.precision == PD_FP32) {
+      if (s.form == kFormShear)
+        strang_tile<float, PPL, 0, kFormShear>(s.p, base);
+      else
+        strang_tile<float, PPL, 0, kFormVersine>(s.p, base);
+    } else {
+      if (s.form == kFormShear)
+        strang_tile<double, PPL, 0, kFormShear>(s.p, base);
+      else
+        strang_tile<double, PPL, 0, kFormVersine>(s.p, base);
     }
   }
 }
@@ -453,25 +498,62 @@ __device__ __forceinline__ double block_sum(double v) {
   return s;
 }
 
-__global__ void __launch_bounds__(kRedThreads) density_tiles(const double* __restrict__ n, long long npts,
-                                                             double* __restrict__ partial) {
-  const long long base = (long long)blockIdx.x * kRedTile + threadIdx.x;
+// Sum of tile `tile` of n (2048 points), valid in thread 0.
+__device__ __forceinline__ double tile_sum(const double* __restrict__ n, long long npts, long long tile) {
+  const long long base = tile * kRedTile + threadIdx.x;
   double s = 0.0;
 #pragma unroll
   for (int q = 0; q < kRedPerThread; ++q) {
     long long i = base + (long long)q * kRedThreads;
     if (i < npts) s += n[i];
   }
-  s = block_sum(s);
+  return block_sum(s);
+}
+
+// Sum of the tile partials, valid in thread 0.
+__device__ __forceinline__ double partials_sum(const double* __restrict__ partial, long long count) {
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < count; i += kRedThreads) s += partial[i];
+  return block_sum(s);
+}
+
+__global__ void __launch_bounds__(kRedThreads) density_tiles(const double* __restrict__ n, long long npts,
+                                                             double* __restrict__ partial) {
+  double s = tile_sum(n, npts, blockIdx.x);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
 __global__ void __launch_bounds__(kRedThreads) density_finish(const double* __restrict__ partial, long long count,
                                                               double scale, double* __restrict__ rho) {
-  double s = 0.0;
-  for (long long i = threadIdx.x; i < count; i += kRedThreads) s += partial[i];
-  s = block_sum(s);
+  double s = partials_sum(partial, count);
   if (threadIdx.x == 0) *rho = scale * s;
+}
+
+// Batched densities: the tiles of every job in one launch (block -> job by
+// binary search over the jobs' first tiles), then one block per job.
+__global__ void __launch_bounds__(kRedThreads) batch_density_tiles(const DensityJob* __restrict__ jobs, int n_jobs) {
+  const long long b = blockIdx.x;
+  int lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) / 2;
+    if (jobs[mid].tile_begin <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const DensityJob& j = jobs[lo];
+  const long long tile = b - j.tile_begin;
+  double s = tile_sum(j.n, j.npts, tile);
+  if (threadIdx.x == 0) j.partial[tile] = s;
+}
+
+__global__ void __launch_bounds__(kRedThreads) batch_density_finish(const DensityJob* __restrict__ jobs) {
+  const DensityJob& j = jobs[blockIdx.x];
+  double s = partials_sum(j.partial, (j.npts + kRedTile - 1) / kRedTile);
+  if (threadIdx.x == 0) {
+    *j.rho = j.scale * s;
+    if (j.rho_copy) *j.rho_copy = j.scale * s;
+  }
 }
 
 template <typename R, int PPL, int FORM>
@@ -550,6 +632,45 @@ hipError_t launch_density(const double* n, long long npts, double scale, double*
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(density_finish, dim3(1), dim3(kRedThreads), 0, stream, partial, tiles, scale, rho);
   return hipGetLastError();
+}
+
+hipError_t launch_batch_density(const DensityJob* jobs, int n_jobs, long long total_tiles, hipStream_t stream) {
+  if (n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_density_tiles, dim3((unsigned)total_tiles), dim3(kRedThreads), 0, stream, jobs, n_jobs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(batch_density_finish, dim3((unsigned)n_jobs), dim3(kRedThreads), 0, stream, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(int ppl, int block, int grid_blocks, const BatchSolve* solves, const BatchItem* items,
+                        int n_items, unsigned int* counter, hipStream_t stream) {
+  hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, stream, counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  switch (ppl) {
+    case 1:
+      hipLaunchKernelGGL(batch_kernel<1>, dim3(grid_blocks), dim3(block), 0, stream, solves, items, n_items, counter);
+      break;
+    case 2:
+      hipLaunchKernelGGL(batch_kernel<2>, dim3(grid_blocks), dim3(block), 0, stream, solves, items, n_items, counter);
+      break;
+    default:
+      hipLaunchKernelGGL(batch_kernel<4>, dim3(grid_blocks), dim3(block), 0, stream, solves, items, n_items, counter);
+      break;
+  }
+  return hipGetLastError();
+}
+
+int batch_blocks_per_cu(int ppl, int block) {
+  int n = 0;
+  hipError_t e;
+  switch (ppl) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<1>, block, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<2>, block, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<4>, block, 0); break;
+  }
+  return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 }  // namespace pdx

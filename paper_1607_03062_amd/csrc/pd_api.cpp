@@ -1,6 +1,7 @@
 // C ABI of libpd (declared and documented in include/pd.h).
 #include <hip/hip_runtime_api.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -15,10 +16,17 @@
 using namespace pdx;
 
 namespace {
-
 thread_local std::string g_error;
+constexpr double kPi = 3.14159265358979323846;
+std::atomic<long long> g_versions{0};
+// Versions come from one process-wide counter, so a handle created at the
+// address of a destroyed one never matches the old handle's version.
+long long next_version() { return ++g_versions; }
+}  // namespace
 
-pd_status fail(pd_status s, const char* fmt, ...) {
+namespace pdx {
+
+pd_status set_error(pd_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -28,72 +36,64 @@ pd_status fail(pd_status s, const char* fmt, ...) {
   return s;
 }
 
-pd_status ok() { return PD_OK; }
+pd_status hip_error(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) return set_error(PD_ERR_NOMEM, "%s: %s", what, hipGetErrorString(e));
+  return set_error(PD_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
 
-constexpr double kPi = 3.14159265358979323846;
-
-}  // namespace
-
-struct pd_grid_s {
-  Grid grid;
-  int precision = PD_FP64;
-  int scheme = PD_SCHEME_STRANG;
-  int points_per_lane = 2;
-  int block_threads = 256;
-  int table_stage = 2;   // 1: LDS chunks, 2: scalar-unit reads
-  int chunk_steps = 512;
-
-  bool field_set = false;
-  FieldTables field;
-  long long n_masked = 0;
-  long long steps_done = 0;
-  int taylor = 0;
-  int form = kFormShear;  // Strang rotation form of the current field
-
-  int device = -1;
-  void* d_table = nullptr;
-  size_t table_bytes = 0;  // step rows, then (Strang) the column and row coefficients
-  size_t col_offset = 0, row_offset = 0;
-  double* d_n = nullptr;
-  double* d_partial = nullptr;
-  double* d_rho = nullptr;
-  void* d_state_own = nullptr;
-  void* d_state_bound = nullptr;
-  size_t state_bound_bytes = 0;
-
-  size_t device_bytes() const {
-    size_t b = table_bytes;
-    if (d_n) b += (size_t)grid.points() * sizeof(double);
-    if (d_partial) b += (size_t)density_partials(grid.points()) * sizeof(double) + sizeof(double);
-    if (d_state_own) b += state_bytes();
-    return b;
+pd_status grid_state_buffer(pd_grid g, void** out) {
+  if (g->d_state_bound) {
+    *out = g->d_state_bound;
+    return PD_OK;
   }
-  size_t state_bytes() const {
-    size_t v = precision == PD_FP32 ? sizeof(float) : sizeof(double);
-    return (size_t)grid.points() * state_values_per_point(scheme) * v;
+  if (!g->d_state_own) {
+    hipError_t e = hipMalloc(&g->d_state_own, g->state_bytes());
+    if (e != hipSuccess) return hip_error(e, "hipMalloc(state)");
   }
-};
+  *out = g->d_state_own;
+  return PD_OK;
+}
+
+}  // namespace pdx
+
+double pd_grid_s::density_scale() const { return 4.0 * grid.dx * grid.dy / (4.0 * kPi * kPi); }
+
+SolveParams pd_grid_s::solve_params(long long k_begin, long long k_end, void* state) const {
+  SolveParams p{};
+  p.npts = grid.points();
+  p.nx = grid.nx;
+  p.px_min = grid.px_min;
+  p.dx = grid.dx;
+  p.py_min = grid.py_min;
+  p.dy = grid.dy;
+  p.A_in = field.A_in;
+  p.A_out = field.A_out;
+  p.dt = field.dt;
+  p.n_steps = field.n_steps;
+  p.k_begin = k_begin;
+  p.k_end = k_end;
+  p.table = d_table;
+  p.col_coef = static_cast<const unsigned char*>(d_table) + col_offset;
+  p.row_coef = static_cast<const unsigned char*>(d_table) + row_offset;
+  p.n_out = d_n;
+  p.load_state = k_begin > 0;
+  p.store_state = k_end < field.n_steps;
+  p.state = (p.load_state || p.store_state) ? state : nullptr;
+  p.stage = table_stage == 1 ? 1 : 0;
+  p.chunk_steps = chunk_steps;
+  p.form = form;
+  return p;
+}
 
 namespace {
 
-// Makes the handle's device current for the duration of a call.
-struct DeviceScope {
-  int prev = -1;
-  bool ok = true;
-  explicit DeviceScope(int dev) {
-    if (dev < 0) return;
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
-  }
-  ~DeviceScope() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
-
-pd_status hip_fail(hipError_t e, const char* what) {
-  if (e == hipErrorOutOfMemory) return fail(PD_ERR_NOMEM, "%s: %s", what, hipGetErrorString(e));
-  return fail(PD_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+pd_status fail(pd_status s, const char* msg) { return set_error(s, "%s", msg); }
+template <typename... A>
+pd_status fail(pd_status s, const char* fmt, A... a) {
+  return set_error(s, fmt, a...);
 }
+pd_status ok() { return PD_OK; }
+pd_status hip_fail(hipError_t e, const char* what) { return hip_error(e, what); }
 
 void release(void*& p) {
   if (p) (void)hipFree(p);
@@ -150,6 +150,19 @@ void fill_info(pd_grid g, const FieldTables& t, long long masked, long long step
   out->chunk_steps = g->chunk_steps;
   out->rotation_form = t.n_steps > 0 ? strang_form(g->grid, t) : kFormShear;
   out->device_bytes = g->device_bytes();
+  if (t.n_steps > 0) {
+    std::vector<unsigned char> rows;
+    size_t table = (size_t)t.n_steps * table_row_bytes(g->scheme, g->precision);
+    if (g->scheme == PD_SCHEME_STRANG) {
+      rows.resize(table);
+      size_t c0, r0;
+      build_point_coefficients(g->grid, t.dt, g->precision, kFormShear, &rows, &c0, &r0);
+      table = rows.size();
+    }
+    const size_t npts = (size_t)g->grid.points();
+    out->solve_bytes = table + npts * sizeof(double) + (size_t)density_partials((long long)npts) * sizeof(double) +
+                       sizeof(double) + g->state_bytes();
+  }
 }
 
 }  // namespace
@@ -273,6 +286,7 @@ pd_status pd_set_field(pd_grid g, const pd_field* f, long long n_steps) {
   g->row_offset = row_offset;
   g->steps_done = 0;
   g->field_set = true;
+  g->version = next_version();
   return ok();
 }
 
@@ -310,6 +324,7 @@ pd_status pd_set_launch(pd_grid g, int points_per_lane, int block_threads, int t
   if (block_threads) g->block_threads = block_threads;
   if (table_stage) g->table_stage = table_stage;
   if (chunk_steps) g->chunk_steps = chunk_steps;
+  g->version = next_version();
   return ok();
 }
 
@@ -331,39 +346,13 @@ pd_status pd_propagate(pd_grid g, long long max_steps, void* stream) {
   DeviceScope scope(g->device);
   if (!scope.ok) return fail(PD_ERR_DEVICE, "cannot select device %d", g->device);
 
-  SolveParams p{};
-  p.npts = g->grid.points();
-  p.nx = g->grid.nx;
-  p.px_min = g->grid.px_min;
-  p.dx = g->grid.dx;
-  p.py_min = g->grid.py_min;
-  p.dy = g->grid.dy;
-  p.A_in = g->field.A_in;
-  p.A_out = g->field.A_out;
-  p.dt = g->field.dt;
-  p.n_steps = N;
-  p.k_begin = g->steps_done;
-  p.k_end = g->steps_done + m;
-  p.table = g->d_table;
-  p.col_coef = static_cast<const unsigned char*>(g->d_table) + g->col_offset;
-  p.row_coef = static_cast<const unsigned char*>(g->d_table) + g->row_offset;
-  p.n_out = g->d_n;
-  p.load_state = p.k_begin > 0;
-  p.store_state = p.k_end < N;
-  p.stage = g->table_stage == 1 ? 1 : 0;
-  p.chunk_steps = g->chunk_steps;
-  p.form = g->form;
-  if (p.load_state || p.store_state) {
-    void* st = g->d_state_bound;
-    if (!st) {
-      if (!g->d_state_own) {
-        hipError_t e = hipMalloc(&g->d_state_own, g->state_bytes());
-        if (e != hipSuccess) return hip_fail(e, "hipMalloc(state)");
-      }
-      st = g->d_state_own;
-    }
-    p.state = st;
+  const long long k_begin = g->steps_done, k_end = g->steps_done + m;
+  void* st = nullptr;
+  if (k_begin > 0 || k_end < N) {
+    pd_status s = grid_state_buffer(g, &st);
+    if (s != PD_OK) return s;
   }
+  const SolveParams p = g->solve_params(k_begin, k_end, st);
   hipError_t e = launch_propagate(g->scheme, g->precision, g->points_per_lane, g->block_threads, g->taylor, p,
                                   static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "propagate launch");
@@ -380,8 +369,7 @@ pd_status pd_density(pd_grid g, double* n_out, int n_out_on_device, double* rho_
   if (!scope.ok) return fail(PD_ERR_DEVICE, "cannot select device %d", g->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const long long npts = g->grid.points();
-  const double scale = 4.0 * g->grid.dx * g->grid.dy / (4.0 * kPi * kPi);
-  hipError_t e = launch_density(g->d_n, npts, scale, g->d_partial, g->d_rho, s);
+  hipError_t e = launch_density(g->d_n, npts, g->density_scale(), g->d_partial, g->d_rho, s);
   if (e != hipSuccess) return hip_fail(e, "density launch");
   bool wait = false;
   if (n_out) {

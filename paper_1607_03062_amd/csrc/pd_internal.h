@@ -79,12 +79,110 @@ struct SolveParams {
   long long chunk_steps;  // LDS chunk length in steps (power of two; divides 1024 in FP32)
 };
 
+// One solve of a batched launch (device descriptor).
+struct BatchSolve {
+  SolveParams p;
+  int precision;
+  int form;
+};
+
+// One work item of a batched launch: the tile of block_threads * points_per_lane
+// points of solve `solve` starting at point `base`.
+struct BatchItem {
+  int solve;
+  int pad;
+  long long base;
+};
+
+// One density reduction of a batched launch: rho = scale * sum n, tiles
+// [tile_begin, tile_begin + ceil(npts / 2048)) of the batched tile launch.
+struct DensityJob {
+  const double* n;
+  long long npts;
+  long long tile_begin;
+  double* partial;
+  double* rho;
+  double* rho_copy;  // optional second destination (nullptr: none)
+  double scale;
+};
+
 // kernels.hip
 hipError_t launch_propagate(int scheme, int precision, int points_per_lane, int block_threads, int taylor,
                             const SolveParams& p, hipStream_t stream);
 hipError_t launch_density(const double* n, long long npts, double scale, double* partial, double* rho,
                           hipStream_t stream);
+hipError_t launch_batch(int points_per_lane, int block_threads, int grid_blocks, const BatchSolve* solves,
+                        const BatchItem* items, int n_items, unsigned int* counter, hipStream_t stream);
+hipError_t launch_batch_density(const DensityJob* jobs, int n_jobs, long long total_tiles, hipStream_t stream);
+int batch_blocks_per_cu(int points_per_lane, int block_threads);
 long long density_partials(long long npts);
 size_t state_values_per_point(int scheme);
 
+}  // namespace pdx
+
+// The solver handle behind pd_grid (pd_api.cpp; also used by the batch code).
+struct pd_grid_s {
+  pdx::Grid grid;
+  int precision = PD_FP64;
+  int scheme = PD_SCHEME_STRANG;
+  int points_per_lane = 2;
+  int block_threads = 256;
+  int table_stage = 2;  // 1: LDS chunks, 2: scalar-unit reads
+  int chunk_steps = 512;
+  long long version = 0;  // bumped whenever the field or the launch shape changes
+
+  bool field_set = false;
+  pdx::FieldTables field;
+  long long n_masked = 0;
+  long long steps_done = 0;
+  int taylor = 0;
+  int form = pdx::kFormShear;  // Strang rotation form of the current field
+
+  int device = -1;
+  void* d_table = nullptr;
+  size_t table_bytes = 0;  // step rows, then (Strang) the column and row coefficients
+  size_t col_offset = 0, row_offset = 0;
+  double* d_n = nullptr;
+  double* d_partial = nullptr;
+  double* d_rho = nullptr;
+  void* d_state_own = nullptr;
+  void* d_state_bound = nullptr;
+  size_t state_bound_bytes = 0;
+
+  size_t device_bytes() const {
+    size_t b = table_bytes;
+    if (d_n) b += (size_t)grid.points() * sizeof(double);
+    if (d_partial) b += (size_t)pdx::density_partials(grid.points()) * sizeof(double) + sizeof(double);
+    if (d_state_own) b += state_bytes();
+    return b;
+  }
+  size_t state_bytes() const {
+    size_t v = precision == PD_FP32 ? sizeof(float) : sizeof(double);
+    return (size_t)grid.points() * pdx::state_values_per_point(scheme) * v;
+  }
+  double density_scale() const;
+  // Launch parameters of steps [k_begin, k_end); `state` is the chunk state buffer (may be null).
+  pdx::SolveParams solve_params(long long k_begin, long long k_end, void* state) const;
+};
+
+namespace pdx {
+// Makes a device current for the lifetime of the scope.
+struct DeviceScope {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceScope(int dev) {
+    if (dev < 0) return;
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceScope() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// Error reporting shared by the C entry points (pd_api.cpp).
+pd_status set_error(pd_status s, const char* fmt, ...);
+pd_status hip_error(hipError_t e, const char* what);
+// The chunk state buffer of a handle, allocated on first use.
+pd_status grid_state_buffer(pd_grid g, void** out);
 }  // namespace pdx

@@ -1,0 +1,260 @@
+"""Continuous-batching solve server.
+
+Requests (a grid, a field, a step count and a precision) arrive over time.  The
+server keeps a set of active solves on the device and runs them in epochs: each
+epoch advances every active solve by up to `epoch_steps` steps in one batched
+persistent launch (pd_batch_step), with every solve's state resident in device
+memory between epochs.  Solves that reach their last step are projected and
+reduced in the same epoch and leave the set; arrivals are admitted between
+epochs, in arrival order, while their device footprint (tables, state, n(p),
+partials; pd_info.solve_bytes) fits in the memory budget.  A request larger than
+the whole budget is rejected.  Latency is the time from a request's arrival to
+its density being on the host.
+
+The device work is in libpd; this module is the host-side scheduler.  The
+executor interface (footprint / admit / epoch / release) has a GPU
+implementation over the C ABI and a CPU fake with a cost model, used to test the
+scheduling without a GPU.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    name: str
+    arrival_s: float
+    grid: dict
+    field: dict
+    n_steps: int
+    precision: str = "fp32"
+    scheme: str = "strang"
+    # filled by the server
+    admitted_s: float = float("nan")
+    done_s: float = float("nan")
+    rho: float = float("nan")
+    bytes: int = 0
+    status: str = "pending"
+    reason: str = ""
+
+    @property
+    def points(self) -> int:
+        return int(self.grid["nx"]) * int(self.grid["ny"])
+
+    @property
+    def point_steps(self) -> float:
+        return float(self.points) * float(self.n_steps)
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+    @classmethod
+    def from_workload(cls, w: dict) -> "Request":
+        return cls(name=w["name"], arrival_s=float(w.get("arrival_s", 0.0)), grid=w["grid"], field=w["field"],
+                   n_steps=int(w["n_steps"]), precision=w.get("precision", "fp32"), scheme=w.get("scheme", "strang"))
+
+
+class GpuExecutor:
+    """Active solves as pd_grid handles in one pd_batch."""
+
+    def __init__(self, pd, stream=None, points_per_lane: int = 0, block_threads: int = 0, keep_n: bool = False):
+        self.pd = pd
+        self.stream = stream
+        self.batch = pd.Batch()
+        if points_per_lane or block_threads:
+            self.batch.set_launch(points_per_lane, block_threads)
+        self.solvers = {}   # request name -> Solver
+        self.order = []     # request names in batch member order
+        self.left = {}      # request name -> steps still to run
+        self.keep_n = keep_n
+        self.n_results = {}
+
+    def footprint(self, req: Request) -> int:
+        s = self.pd.Solver.for_grid(req.grid, req.precision, req.scheme)
+        try:
+            return int(s.check_field(req.field, req.n_steps)["solve_bytes"])
+        finally:
+            s.close()
+
+    def admit(self, req: Request):
+        s = self.pd.Solver.for_grid(req.grid, req.precision, req.scheme)
+        s.set_field(req.field, req.n_steps)
+        self.solvers[req.name] = s
+        self.order.append(req.name)
+        self.left[req.name] = req.n_steps
+        self.batch.add(s)
+
+    def epoch(self, steps: int):
+        """Advance every active solve; returns [(name, rho)] of the solves that completed.
+        Which solves complete is known on the host, so the call only waits for the device
+        in epochs where one does; otherwise the next epoch is enqueued behind this one."""
+        completing = any(self.left[name] <= steps for name in self.order)
+        rho, fin = self.batch.step(steps, stream=self.stream, want_rho=completing)
+        done = []
+        for i, name in enumerate(self.order):
+            self.left[name] = max(0, self.left[name] - steps)
+            if completing and not np.isnan(rho[i]):
+                done.append((name, float(rho[i])))
+        return done
+
+    def release(self, name: str):
+        s = self.solvers.pop(name)
+        if self.keep_n:
+            n = np.empty(s.nx * s.ny)
+            s.density(n_out=n, stream=self.stream)
+            self.n_results[name] = n
+        self.order.remove(name)
+        del self.left[name]
+        self.batch.remove(s)  # leave the batch before the grid is destroyed
+        s.close()
+
+    def close(self):
+        self.batch.close()
+        for s in self.solvers.values():
+            s.close()
+        self.solvers = {}
+        self.order = []
+
+
+class FakeExecutor:
+    """CPU stand-in with the same interface: a solve costs point-steps / rate seconds of
+    device time, shared evenly by the active solves; rho is a fixed function of the request."""
+
+    def __init__(self, rate_point_steps_per_s: float = 1e12, bytes_per_point: int = 40):
+        self.rate = rate_point_steps_per_s
+        self.bytes_per_point = bytes_per_point
+        self.active = collections.OrderedDict()  # name -> [request, steps_done]
+        self.clock = 0.0                          # simulated device time
+
+    def footprint(self, req: Request) -> int:
+        return req.points * self.bytes_per_point + 16 * req.n_steps
+
+    def admit(self, req: Request):
+        self.active[req.name] = [req, 0]
+
+    def epoch(self, steps: int):
+        work = 0.0
+        done = []
+        for name, entry in self.active.items():
+            req, k = entry
+            m = min(steps, req.n_steps - k)
+            work += float(req.points) * m
+            entry[1] = k + m
+            if entry[1] == req.n_steps and m > 0:
+                done.append((name, 1e-3 * req.points / (1.0 + req.n_steps)))
+        self.clock += work / self.rate
+        return done
+
+    def release(self, name: str):
+        del self.active[name]
+
+    def close(self):
+        pass
+
+
+@dataclasses.dataclass
+class ServeStats:
+    completed: int
+    rejected: int
+    makespan_s: float
+    p50_ms: float
+    p99_ms: float
+    mean_ms: float
+    point_steps_per_s: float
+    epochs: int
+    mean_active: float
+    peak_bytes: int
+    budget_bytes: int
+
+    def as_dict(self) -> dict:
+        return dataclasses.asdict(self)
+
+
+class Server:
+    def __init__(self, executor, budget_bytes: int, epoch_steps: int = 2048, max_active: int = 4096,
+                 backfill: bool = False):
+        if epoch_steps < 1:
+            raise ValueError("epoch_steps must be >= 1")
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.epoch_steps = int(epoch_steps)
+        self.max_active = int(max_active)
+        self.backfill = backfill
+        self.in_use = 0
+        self.peak = 0
+        self.active = {}
+
+    def _now(self, t0, simulated):
+        return self.ex.clock if simulated else time.perf_counter() - t0
+
+    def run(self, requests, simulated: bool = False) -> ServeStats:
+        """Serve the requests (arrival times in seconds from the start).  With
+        simulated=True the clock is the executor's device-time model (FakeExecutor)."""
+        reqs = sorted(requests, key=lambda r: r.arrival_s)
+        pending = collections.deque(reqs)
+        waiting = collections.deque()  # arrived, not yet admitted
+        t0 = time.perf_counter()
+        epochs = 0
+        active_sum = 0
+        while pending or waiting or self.active:
+            now = self._now(t0, simulated)
+            while pending and pending[0].arrival_s <= now:
+                r = pending.popleft()
+                r.bytes = self.ex.footprint(r)
+                if r.bytes > self.budget:
+                    r.status, r.reason = "rejected", "footprint %d bytes exceeds the budget %d" % (r.bytes, self.budget)
+                    r.done_s = now
+                    continue
+                waiting.append(r)
+            # admit in arrival order while memory and slots allow (optionally skipping a blocked head)
+            blocked = []
+            while waiting and len(self.active) < self.max_active:
+                r = waiting[0]
+                if self.in_use + r.bytes <= self.budget:
+                    waiting.popleft()
+                    self.ex.admit(r)
+                    r.admitted_s, r.status = now, "active"
+                    self.active[r.name] = r
+                    self.in_use += r.bytes
+                    self.peak = max(self.peak, self.in_use)
+                elif self.backfill:
+                    blocked.append(waiting.popleft())
+                else:
+                    break
+            for r in reversed(blocked):
+                waiting.appendleft(r)
+            if not self.active:
+                if pending:
+                    if simulated:
+                        self.ex.clock = max(self.ex.clock, pending[0].arrival_s)
+                    else:
+                        time.sleep(max(0.0, min(pending[0].arrival_s - (time.perf_counter() - t0), 0.05)))
+                    continue
+                if waiting:
+                    raise RuntimeError("a waiting request can never be admitted")
+                break
+            done = self.ex.epoch(self.epoch_steps)
+            epochs += 1
+            active_sum += len(self.active)
+            now = self._now(t0, simulated)
+            for name, rho in done:
+                r = self.active.pop(name)
+                r.rho, r.done_s, r.status = rho, now, "done"
+                self.in_use -= r.bytes
+                self.ex.release(name)
+        end = self._now(t0, simulated)
+        done = [r for r in reqs if r.status == "done"]
+        lat = np.array([r.latency_s for r in done]) * 1e3 if done else np.zeros(1)
+        first = min((r.arrival_s for r in reqs), default=0.0)
+        makespan = max(end - first, 1e-12)
+        return ServeStats(completed=len(done), rejected=sum(r.status == "rejected" for r in reqs),
+                          makespan_s=makespan, p50_ms=float(np.percentile(lat, 50)),
+                          p99_ms=float(np.percentile(lat, 99)), mean_ms=float(lat.mean()),
+                          point_steps_per_s=sum(r.point_steps for r in done) / makespan, epochs=epochs,
+                          mean_active=active_sum / max(epochs, 1), peak_bytes=self.peak, budget_bytes=self.budget)

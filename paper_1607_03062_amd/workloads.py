@@ -90,18 +90,28 @@ def steps_for(field: dict, half_width: float, n_requested: int, max_phase: float
 
 # Config 4: 64 solves, E0 ~ U[0.05,0.5], omega ~ U[0.1,1.0], cycles ~ U{4..40}, steps ~ U{5000..80000}
 # (raised per steps_for), square grids from {256,512,1024,2048} on [-4,4]^2.
+def _draw_solve(rng, sizes, step_range, max_steps):
+    E0 = float(rng.uniform(0.05, 0.5))
+    omega = float(rng.uniform(0.1, 1.0))
+    cycles = int(rng.integers(4, 41))
+    n_req = int(rng.integers(step_range[0], step_range[1] + 1))
+    n = int(rng.choice(np.asarray(sizes)))
+    f = sin2(E0, omega, cycles)
+    # raised to keep dt * E_bound <= 0.5, capped at max_steps (dt * E_bound stays below pi:
+    # T <= 2513 and E_bound <= 21 give dt * E_bound <= 0.66 at 80000 steps)
+    steps = max(n_req, min(steps_for(f, 4.0, n_req), max_steps))
+    return n, f, steps
+
+
+# Config 4: 64 solves, E0 ~ U[0.05,0.5], omega ~ U[0.1,1.0], cycles ~ U{4..40}, steps ~ U{5000..80000}
+# (raised per steps_for, at most 80000), square grids from {256,512,1024,2048} on [-4,4]^2.
+# step_range and sizes shrink the same recipe for tests.
 def config4(count: int = 64, seed: int = 4, sizes=(256, 512, 1024, 2048), precision: str = "fp32",
-            max_steps: int = 80000) -> list:
+            step_range=(5000, 80000), max_steps: int = 80000) -> list:
     rng = np.random.default_rng(seed)
     out = []
     for q in range(count):
-        E0 = float(rng.uniform(0.05, 0.5))
-        omega = float(rng.uniform(0.1, 1.0))
-        cycles = int(rng.integers(4, 41))
-        n_req = int(rng.integers(5000, 80001))
-        n = int(rng.choice(np.asarray(sizes)))
-        f = sin2(E0, omega, cycles)
-        steps = min(steps_for(f, 4.0, n_req), max(max_steps, n_req))
+        n, f, steps = _draw_solve(rng, sizes, step_range, max_steps)
         out.append({"name": "cfg4_%02d" % q, "grid": grid(n, 4.0), "field": f, "n_steps": steps,
                     "precision": precision, "scheme": "strang"})
     return out
@@ -110,20 +120,14 @@ def config4(count: int = 64, seed: int = 4, sizes=(256, 512, 1024, 2048), precis
 # Config 5: a Poisson stream of solve requests with config-4 parameter and size distributions,
 # accuracy class 50/50 FP32 / FP64.
 def config5(count: int = 10000, seed: int = 5, rate_per_s: float = 1.0, sizes=(256, 512, 1024, 2048),
-            max_steps: int = 80000) -> list:
+            step_range=(5000, 80000), max_steps: int = 80000) -> list:
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
     for q in range(count):
         t += float(rng.exponential(1.0 / rate_per_s))
-        E0 = float(rng.uniform(0.05, 0.5))
-        omega = float(rng.uniform(0.1, 1.0))
-        cycles = int(rng.integers(4, 41))
-        n_req = int(rng.integers(5000, 80001))
-        n = int(rng.choice(np.asarray(sizes)))
+        n, f, steps = _draw_solve(rng, sizes, step_range, max_steps)
         prec = "fp32" if rng.random() < 0.5 else "fp64"
-        f = sin2(E0, omega, cycles)
-        steps = min(steps_for(f, 4.0, n_req), max(max_steps, n_req))
         out.append({"name": "req_%05d" % q, "arrival_s": t, "grid": grid(n, 4.0), "field": f, "n_steps": steps,
                     "precision": prec, "scheme": "strang"})
     return out

@@ -1,0 +1,168 @@
+"""Batched solves (one persistent, graph-captured launch over many grids) against
+the same grids solved alone, and the autotuner.
+
+Every work item of the persistent kernel performs the same arithmetic as the
+single-grid kernel, and densities use the same fixed-order reduction, so each
+member's n(p) and rho must equal its solve alone bit for bit, in every launch
+shape, across graph replays and across epoch-by-epoch stepping.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1607_03062_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def members(pd, mix_precision=True, count=10):
+    cfgs = wl.config4(count=count, sizes=(64, 96, 128), step_range=(500, 3000))
+    extra = {"name": "ragged", "grid": {"nx": 37, "ny": 53, "px": (-1.3, 2.1), "py": (-0.9, 1.7)},
+             "field": wl.sin2(0.3, 0.6, 3), "n_steps": 2777, "precision": "fp64", "scheme": "strang"}
+    cfgs.append(extra)
+    solvers = []
+    for q, c in enumerate(cfgs):
+        prec = ("fp32" if q % 2 else "fp64") if mix_precision else c["precision"]
+        s = pd.Solver.for_grid(c["grid"], prec)
+        s.set_field(c["field"], c["n_steps"])
+        solvers.append((c, s))
+    return solvers
+
+
+def alone(s):
+    s.rewind()
+    s.propagate(-1)
+    n = np.empty(s.nx * s.ny)
+    rho = s.density(n_out=n)
+    return n, rho
+
+
+def member_n(s):
+    n = np.empty(s.nx * s.ny)
+    rho = s.density(n_out=n)
+    return n, rho
+
+
+def test_batch_equals_solves_alone(gpu):
+    ms = members(gpu)
+    ref = [alone(s) for _, s in ms]
+    b = gpu.Batch([s for _, s in ms])
+    print("batch of %d grids, %.3e point-steps" % (len(b), b.info()["point_steps"]), flush=True)
+    rho = b.run()
+    for (c, s), (n0, r0), r in zip(ms, ref, rho):
+        n, rr = member_n(s)
+        assert np.array_equal(n, n0), c["name"]
+        assert r == r0 and rr == r0, c["name"]
+    # one spot check against the oracle (FP64 member)
+    c, s = ms[0]
+    idx = np.array([0, 17, s.nx * s.ny // 2 + 5, s.nx * s.ny - 1])
+    n_o = oracle.solve_grid(c["field"], c["grid"], c["n_steps"], idx=idx)[0]
+    assert np.max(np.abs(ref[0][0][idx] - n_o)) <= 1e-12
+    b.close()
+
+
+def test_graph_replays_match_eager(gpu):
+    """The whole-solve launch is captured once and replayed; eager work and synchronisation
+    between replays, every replay checked against the eager results, then a member's field
+    changes and the batch is re-captured."""
+    import torch
+
+    ms = members(gpu, count=6)
+    ref = [alone(s) for _, s in ms]
+    b = gpu.Batch([s for _, s in ms])
+    st = torch.cuda.Stream()
+    other = gpu.Solver.for_grid(wl.config1()["grid"])
+    other.set_field(wl.config1()["field"], 4000)
+    for rep in range(3):
+        rho = b.run(stream=st)
+        assert b.info()["graph_captured"] == 1
+        for (c, s), (n0, r0), r in zip(ms, ref, rho):
+            n, _ = member_n(s)
+            assert np.array_equal(n, n0) and r == r0, (rep, c["name"])
+        alone(other)  # eager work between replays
+        torch.cuda.synchronize()
+    # a member's field changes: the batch re-captures and follows
+    c0, s0 = ms[0]
+    s0.set_field(wl.sin2(0.2, 0.4, 4), 3000)
+    assert b.info()["graph_captured"] == 0
+    new0 = alone(s0)
+    rho = b.run(stream=st)
+    assert rho[0] == new0[1] and np.array_equal(member_n(s0)[0], new0[0])
+    for (c, s), (n0, r0), r in list(zip(ms, ref, rho))[1:]:
+        assert r == r0
+    b.close()
+    other.close()
+
+
+def test_epochs_equal_single_launch(gpu):
+    """Continuous-batching epochs: every member advances up to 700 steps per call with its
+    state kept in device memory; members finish at different epochs and report rho then."""
+    ms = members(gpu, count=8)
+    ref = [alone(s) for _, s in ms]
+    for _, s in ms:
+        s.rewind()
+    b = gpu.Batch([s for _, s in ms])
+    done_rho = [None] * len(ms)
+    epochs = 0
+    while True:
+        rho, fin = b.step(700)
+        epochs += 1
+        for i in range(len(ms)):
+            if not np.isnan(rho[i]):
+                assert done_rho[i] is None
+                done_rho[i] = rho[i]
+        if fin.all():
+            break
+        assert epochs < 100
+    for (c, s), (n0, r0), r in zip(ms, ref, done_rho):
+        assert r == r0, c["name"]
+        assert np.array_equal(member_n(s)[0], n0), c["name"]
+    b.close()
+
+
+@pytest.mark.parametrize("ppl,block", [(1, 64), (2, 128), (4, 256)])
+def test_batch_launch_shapes(gpu, ppl, block):
+    ms = members(gpu, count=5)
+    ref = [alone(s) for _, s in ms]
+    b = gpu.Batch([s for _, s in ms]).set_launch(ppl, block)
+    rho = b.run()
+    for (c, s), (n0, r0), r in zip(ms, ref, rho):
+        assert r == r0 and np.array_equal(member_n(s)[0], n0)
+    b.close()
+
+
+def test_batch_autotune(gpu):
+    ms = members(gpu, count=5)
+    ref = [alone(s) for _, s in ms]
+    b = gpu.Batch([s for _, s in ms])
+    b.autotune(256)
+    info = b.info()
+    assert info["points_per_lane"] in (1, 2, 4) and info["block_threads"] in (64, 128, 256)
+    rho = b.run()
+    for (c, s), (n0, r0), r in zip(ms, ref, rho):
+        assert r == r0 and np.array_equal(member_n(s)[0], n0)
+    b.close()
+
+
+def test_single_grid_autotune_and_cache(gpu, tmp_path, monkeypatch):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PD_AUTOTUNE_CACHE", str(cache))
+    c = wl.config1()
+    s = gpu.Solver.for_grid(c["grid"], "fp32")
+    s.set_field(c["field"], c["n_steps"])
+    ref = alone(s)
+    s.autotune(512, use_cache=True)
+    shape = s.info()
+    assert s.info()["steps_done"] == 0
+    assert cache.exists() and len(cache.read_text().splitlines()) == 1
+    n, rho = alone(s)
+    assert np.array_equal(n, ref[0]) and rho == ref[1]
+    s2 = gpu.Solver.for_grid(c["grid"], "fp32")
+    s2.set_field(c["field"], c["n_steps"])
+    s2.autotune(512, use_cache=True)  # from the cache: no new line
+    assert len(cache.read_text().splitlines()) == 1
+    i2 = s2.info()
+    assert (i2["points_per_lane"], i2["block_threads"], i2["table_stage"], i2["chunk_steps"]) == (
+        shape["points_per_lane"], shape["block_threads"], shape["table_stage"], shape["chunk_steps"])
+    s.close()
+    s2.close()

@@ -1,0 +1,78 @@
+"""The continuous-batching scheduler with the CPU fake executor (simulated device time):
+admission by footprint, queueing, rejection, completion and latency accounting."""
+import numpy as np
+import pytest
+
+from paper_1607_03062_amd import serve
+from paper_1607_03062_amd import workloads as wl
+
+
+def stream(count=40, rate=200.0, seed=5):
+    ws = wl.config5(count=count, seed=seed, rate_per_s=rate, sizes=(64, 128, 256), step_range=(500, 4000))
+    return [serve.Request.from_workload(w) for w in ws]
+
+
+def test_every_request_completes_within_budget():
+    ex = serve.FakeExecutor(rate_point_steps_per_s=2e10)
+    reqs = stream()
+    budget = 4 * max(ex.footprint(r) for r in reqs)
+    st = serve.Server(ex, budget, epoch_steps=512).run(reqs, simulated=True)
+    assert st.completed == len(reqs) and st.rejected == 0
+    assert st.peak_bytes <= budget
+    for r in reqs:
+        assert r.status == "done"
+        assert r.admitted_s >= r.arrival_s - 1e-12 and r.done_s >= r.admitted_s
+        # at least its own work at the full device rate
+        assert r.done_s - r.admitted_s >= r.point_steps / 2e10 * (1 - 1e-9)
+
+
+def test_fifo_admission_and_queueing():
+    ex = serve.FakeExecutor(rate_point_steps_per_s=1e10)
+    reqs = stream(count=30, rate=1000.0)
+    budget = max(ex.footprint(r) for r in reqs) + 1  # forces queueing
+    st = serve.Server(ex, budget, epoch_steps=1024).run(reqs, simulated=True)
+    assert st.completed == len(reqs)
+    adm = [r.admitted_s for r in sorted(reqs, key=lambda r: r.arrival_s)]
+    assert all(a <= b for a, b in zip(adm, adm[1:]))  # in arrival order
+    assert any(r.admitted_s > r.arrival_s for r in reqs)  # someone waited
+    assert st.peak_bytes <= budget
+
+
+def test_oversized_request_is_rejected():
+    ex = serve.FakeExecutor()
+    reqs = stream(count=10)
+    big = serve.Request("huge", 0.0, wl.grid(4096, 4.0), wl.sin2(0.1, 0.5, 8), 1000)
+    budget = max(ex.footprint(r) for r in reqs) * 2
+    st = serve.Server(ex, budget).run(reqs + [big], simulated=True)
+    assert big.status == "rejected" and "budget" in big.reason
+    assert st.rejected == 1 and st.completed == len(reqs)
+
+
+def test_percentiles_and_throughput():
+    ex = serve.FakeExecutor(rate_point_steps_per_s=5e10)
+    reqs = stream(count=25)
+    st = serve.Server(ex, 10 ** 12, epoch_steps=256).run(reqs, simulated=True)
+    lat = np.array([r.latency_s for r in reqs]) * 1e3
+    assert st.p50_ms == pytest.approx(np.percentile(lat, 50))
+    assert st.p99_ms == pytest.approx(np.percentile(lat, 99))
+    total = sum(r.point_steps for r in reqs)
+    assert st.point_steps_per_s == pytest.approx(total / st.makespan_s)
+    assert st.point_steps_per_s <= 5e10 * (1 + 1e-9)
+
+
+def test_epoch_count_of_a_lone_request():
+    ex = serve.FakeExecutor()
+    r = serve.Request("one", 0.0, wl.grid(64, 2.0), wl.sin2(0.1, 0.5, 8), 5000)
+    st = serve.Server(ex, 10 ** 12, epoch_steps=2048).run([r], simulated=True)
+    assert st.epochs == 3 and r.status == "done"
+
+
+def test_backfill_admits_smaller_requests_past_a_blocked_head():
+    ex = serve.FakeExecutor(rate_point_steps_per_s=1e10)
+    small = [serve.Request("s%d" % i, 0.001 * (i + 1), wl.grid(64, 2.0), wl.sin2(0.1, 0.5, 8), 2000)
+             for i in range(4)]
+    first = serve.Request("first", 0.0, wl.grid(256, 2.0), wl.sin2(0.1, 0.5, 8), 20000)
+    head = serve.Request("head", 0.0005, wl.grid(256, 2.0), wl.sin2(0.1, 0.5, 8), 2000)
+    budget = ex.footprint(first) + ex.footprint(small[0]) * 4 + 1
+    serve.Server(ex, budget, epoch_steps=512, backfill=True).run([first, head] + small, simulated=True)
+    assert all(s.admitted_s < head.admitted_s for s in small)
