@@ -165,6 +165,12 @@ pd_status pd_density(pd_grid g, double* n_out, int n_out_on_device, double* rho_
    PD_SCHEME_MIDPOINT). */
 size_t pd_state_bytes(pd_grid g);
 
+/* Device memory a solve of n_steps steps on g needs, chunk state included
+   (field table and rotation tables, n(p), density partials, state); closed form,
+   no field sampling, no device work (0 for a null handle or n_steps < 1).  Used
+   for admission control. */
+size_t pd_solve_bytes(pd_grid g, long long n_steps);
+
 /* Use caller-owned device memory (at least pd_state_bytes, 256-byte aligned)
    for the chunked state instead of the handle's own buffer.  The caller keeps
    it alive until the handle is destroyed or another buffer is bound.

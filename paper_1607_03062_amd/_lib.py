@@ -96,6 +96,7 @@ SIGNATURES = [
     ("pd_propagate", ctypes.c_int, [_vp, ctypes.c_longlong, _vp]),
     ("pd_density", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _vp]),
     ("pd_state_bytes", ctypes.c_size_t, [_vp]),
+    ("pd_solve_bytes", ctypes.c_size_t, [_vp, ctypes.c_longlong]),
     ("pd_bind_state", ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     ("pd_set_launch", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     ("pd_get_info", ctypes.c_int, [_vp, ctypes.POINTER(pd_info)]),
@@ -257,6 +258,9 @@ class Solver:
 
     def state_bytes(self) -> int:
         return int(load().pd_state_bytes(self._h))
+
+    def solve_bytes(self, n_steps: int) -> int:
+        return int(load().pd_solve_bytes(self._h, int(n_steps)))
 
     def bind_state(self, buf=None):
         if buf is None:

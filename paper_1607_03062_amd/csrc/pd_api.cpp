@@ -150,19 +150,7 @@ void fill_info(pd_grid g, const FieldTables& t, long long masked, long long step
   out->chunk_steps = g->chunk_steps;
   out->rotation_form = t.n_steps > 0 ? strang_form(g->grid, t) : kFormShear;
   out->device_bytes = g->device_bytes();
-  if (t.n_steps > 0) {
-    std::vector<unsigned char> rows;
-    size_t table = (size_t)t.n_steps * table_row_bytes(g->scheme, g->precision);
-    if (g->scheme == PD_SCHEME_STRANG) {
-      rows.resize(table);
-      size_t c0, r0;
-      build_point_coefficients(g->grid, t.dt, g->precision, kFormShear, &rows, &c0, &r0);
-      table = rows.size();
-    }
-    const size_t npts = (size_t)g->grid.points();
-    out->solve_bytes = table + npts * sizeof(double) + (size_t)density_partials((long long)npts) * sizeof(double) +
-                       sizeof(double) + g->state_bytes();
-  }
+  if (t.n_steps > 0) out->solve_bytes = pd_solve_bytes(g, t.n_steps);
 }
 
 }  // namespace
@@ -291,6 +279,21 @@ pd_status pd_set_field(pd_grid g, const pd_field* f, long long n_steps) {
 }
 
 size_t pd_state_bytes(pd_grid g) { return g ? g->state_bytes() : 0; }
+
+size_t pd_solve_bytes(pd_grid g, long long n_steps) {
+  if (!g || n_steps < 1) return 0;
+  auto align = [](size_t n) { return (n + 255) / 256 * 256; };
+  size_t table = (size_t)n_steps * table_row_bytes(g->scheme, g->precision);
+  if (g->scheme == PD_SCHEME_STRANG) {
+    const size_t v = g->precision == PD_FP32 ? sizeof(float) : sizeof(double);
+    size_t col = align(table);
+    size_t row = align(col + 2 * v * (size_t)g->grid.nx);
+    table = align(row + 4 * v * (size_t)g->grid.ny);
+  }
+  const size_t npts = (size_t)g->grid.points();
+  return table + npts * sizeof(double) + (size_t)density_partials((long long)npts) * sizeof(double) +
+         sizeof(double) + g->state_bytes();
+}
 
 pd_status pd_bind_state(pd_grid g, void* dev_ptr, size_t bytes) {
   if (!g) return fail(PD_ERR_INVALID, "null handle");

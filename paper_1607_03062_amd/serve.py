@@ -78,13 +78,18 @@ class GpuExecutor:
     def footprint(self, req: Request) -> int:
         s = self.pd.Solver.for_grid(req.grid, req.precision, req.scheme)
         try:
-            return int(s.check_field(req.field, req.n_steps)["solve_bytes"])
+            return s.solve_bytes(req.n_steps)
         finally:
             s.close()
 
     def admit(self, req: Request):
+        """Raises PDError if the library refuses the request (e.g. the step-size condition)."""
         s = self.pd.Solver.for_grid(req.grid, req.precision, req.scheme)
-        s.set_field(req.field, req.n_steps)
+        try:
+            s.set_field(req.field, req.n_steps)
+        except Exception:
+            s.close()
+            raise
         self.solvers[req.name] = s
         self.order.append(req.name)
         self.left[req.name] = req.n_steps
@@ -218,7 +223,11 @@ class Server:
                 r = waiting[0]
                 if self.in_use + r.bytes <= self.budget:
                     waiting.popleft()
-                    self.ex.admit(r)
+                    try:
+                        self.ex.admit(r)
+                    except Exception as e:  # refused by the solver: reported, not retried
+                        r.status, r.reason, r.done_s = "rejected", str(e), now
+                        continue
                     r.admitted_s, r.status = now, "active"
                     self.active[r.name] = r
                     self.in_use += r.bytes

@@ -76,3 +76,30 @@ def test_backfill_admits_smaller_requests_past_a_blocked_head():
     budget = ex.footprint(first) + ex.footprint(small[0]) * 4 + 1
     serve.Server(ex, budget, epoch_steps=512, backfill=True).run([first, head] + small, simulated=True)
     assert all(s.admitted_s < head.admitted_s for s in small)
+
+
+def test_request_refused_at_admission_is_rejected_and_frees_nothing():
+    class Picky(serve.FakeExecutor):
+        def admit(self, req):
+            if req.name == "bad":
+                raise RuntimeError("dt * E_max exceeds pi")
+            super().admit(req)
+
+    ex = Picky()
+    reqs = stream(count=6)
+    bad = serve.Request("bad", 0.0, wl.grid(64, 2.0), wl.sin2(0.1, 0.5, 8), 10)
+    srv = serve.Server(ex, 10 ** 12)
+    st = srv.run(reqs + [bad], simulated=True)
+    assert bad.status == "rejected" and "pi" in bad.reason
+    assert st.completed == len(reqs) and srv.in_use == 0
+
+
+def test_solve_bytes_closed_form_matches_check_field():
+    import paper_1607_03062_amd as pd
+
+    for prec in ("fp32", "fp64"):
+        for scheme in ("strang", "midpoint"):
+            s = pd.Solver(100, 60, (-4, 4), (-4, 4), prec, scheme)
+            info = s.check_field(wl.sin2(0.2, 0.5, 8), 5000)
+            assert s.solve_bytes(5000) == info["solve_bytes"] > 6000 * 8
+            s.close()
