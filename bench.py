@@ -31,6 +31,20 @@ METRIC = "momentum point-steps/s (FP32 vs FP64 form) at stated n(p) error; p50/p
 #   versine form, FP64: 2 FMA per rotated component -> 12 FMA = 24 flop, 12 instructions
 #   versine form, FP32: mul + fma + add per rotated component -> 24 flop, 18 instructions
 ALGO = {(0, "fp64"): (18, 9), (0, "fp32"): (18, 9), (1, "fp64"): (24, 12), (1, "fp32"): (24, 18)}
+
+
+def algo(info: dict, precision: str):
+    """(flop, VALU instructions) per point-step of the solve described by pd_info.
+    Midpoint step with Taylor order J: phase X = dt(px + A_k) (1 add) and x = X^2 + Y^2
+    (1 fma) in FP64; cos - 1 (J - 1 fma + 1 mul) and sin(x)/x (J fma); alpha, beta (2 mul);
+    the 2x2 update: FP64 3 fma per component (24 flop, 12 instr), FP32 mul + 2 fma + add
+    per component (24 flop, 16 instr) plus 3 conversions."""
+    if info["scheme"] == 0:
+        return ALGO[(info["rotation_form"], precision)]
+    J = info["taylor_order"]
+    flops = 3 + (2 * (J - 1) + 1) + 2 * J + 2 + 24
+    instr = 2 + 2 * J + 2 + (12 if precision == "fp64" else 16 + 3)
+    return flops, instr
 # MI355X vector peaks from its unit counts and clock (256 CU, 2.4 GHz): FP64
 # issues 64 lanes per clock per CU (78.6 TFLOP/s with FMA); unpacked FP32 with
 # VGPR operands issues 128 lanes per clock per CU (157.3 TFLOP/s with FMA).
@@ -64,8 +78,8 @@ def traffic_from_profile(precision: str):
         return None
 
 
-def time_form(pd, torch, c, precision, steps, warmup, ppl, block, stage=0, chunk=0):
-    s = pd.Solver.for_grid(c["grid"], precision, "strang")
+def time_form(pd, torch, c, precision, steps, warmup, ppl, block, stage=0, chunk=0, scheme="strang"):
+    s = pd.Solver.for_grid(c["grid"], precision, scheme)
     if ppl or block or stage or chunk:
         s.set_launch(ppl, block, stage, chunk)
     s.set_field(c["field"], c["n_steps"])
@@ -229,6 +243,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--scheme", choices=["strang", "midpoint"], default="strang")
     ap.add_argument("--ppl", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid", type=int, default=2048)
@@ -270,11 +285,12 @@ def main():
         torch.cuda.synchronize()
         print("copy calibration: %d bytes read, %d bytes written" % (nb, nb), file=sys.stderr)
 
-    main_form = time_form(pd, torch, c, args.precision, args.steps, args.warmup, args.ppl, args.block)
+    sch = args.scheme
+    main_form = time_form(pd, torch, c, args.precision, args.steps, args.warmup, args.ppl, args.block, scheme=sch)
     other = None
     if not args.no_fp64_form and args.precision != "fp64":
         other = time_form(pd, torch, wl.config3(n=args.grid, precision="fp64"), "fp64", args.steps, args.warmup,
-                          args.ppl, args.block)
+                          args.ppl, args.block, scheme=sch)
 
     # oracle on the 64 x 64 subsample: n(p) error of each form and the CPU baseline
     n_err = {}
@@ -286,12 +302,12 @@ def main():
         idx = wl.subsample_indices(args.grid, sub)
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         t0 = time.perf_counter()
-        n_o = oracle.solve_grid(c["field"], c["grid"], c["n_steps"], "strang", idx=idx, threads=threads)[0]
+        n_o = oracle.solve_grid(c["field"], c["grid"], c["n_steps"], sch, idx=idx, threads=threads)[0]
         t_cpu = time.perf_counter() - t0
         cpu = {"value": idx.shape[0] * c["n_steps"] / t_cpu, "unit": "point-steps/s", "cores": threads,
                "kind": "oracle",
-               "sample": "%dx%d subsample (stride %d) of the %d^2 grid, %d FP64 Strang steps, %.1f s" % (
-                   sub, sub, args.grid // sub, args.grid, c["n_steps"], t_cpu)}
+               "sample": "%dx%d subsample (stride %d) of the %d^2 grid, %d FP64 %s steps, %.1f s" % (
+                   sub, sub, args.grid // sub, args.grid, c["n_steps"], sch, t_cpu)}
         # the 64 x 64 subsample (stride grid/64) is contained in the larger one
         in64 = np.isin(idx, wl.subsample_indices(args.grid, 64))
         n_err[args.precision] = float(np.max(np.abs(main_form["n"][idx] - n_o)))
@@ -303,7 +319,7 @@ def main():
     t = main_form["t_total"]
     value = ps_per_solve * K / t
     kern_ms = float(np.mean(main_form["kernel_ms"]))
-    flops, instr = ALGO[(main_form["info"]["rotation_form"], args.precision)]
+    flops, instr = algo(main_form["info"], args.precision)
     achieved = flops * ps_per_solve / (kern_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     wall_ms = np.array(main_form["wall"]) * 1e3
@@ -321,9 +337,10 @@ def main():
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": "%dx%d momentum grid on [-2,2]^2, sin^2 pulse E0=0.1 omega=0.5 30 cycles, "
-                               "%d Strang steps, %s form" % (args.grid, args.grid, c["n_steps"],
-                                                              args.precision.upper()),
-                   "n_points": npts, "n_steps": c["n_steps"], "precision": args.precision, "scheme": "strang",
+                               "%d %s steps, %s form" % (args.grid, args.grid, c["n_steps"],
+                                                         "Strang" if sch == "strang" else "midpoint",
+                                                         args.precision.upper()),
+                   "n_points": npts, "n_steps": c["n_steps"], "precision": args.precision, "scheme": sch,
                    "points_per_lane": main_form["info"]["points_per_lane"],
                    "block_threads": main_form["info"]["block_threads"]},
         "n_error_max_abs": n_err.get(args.precision),
@@ -333,14 +350,15 @@ def main():
         "p99_ms": float(np.percentile(wall_ms, 99)),
         "kernel_ms": kern_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": traffic_from_profile(args.precision),
+                     "frac": achieved / peak,
+                     "traffic": traffic_from_profile(args.precision) if sch == "strang" else None,
                      "valu_issue_frac": instr * ps_per_solve / (kern_ms * 1e-3) / (
                          CU_CLOCKS_PER_S * LANES_PER_CLK[args.precision])},
         "cpu_baseline": cpu,
     }
     if other is not None:
         okm = float(np.mean(other["kernel_ms"]))
-        f64, i64 = ALGO[(other["info"]["rotation_form"], "fp64")]
+        f64, i64 = algo(other["info"], "fp64")
         line["fp64_form"] = {
             "value": ps_per_solve * K / other["t_total"], "ms_per_step": other["t_total"] / K * 1e3,
             "kernel_ms": okm, "n_error_max_abs": n_err.get("fp64"), "rho": other["rho"],

@@ -110,6 +110,7 @@ typedef struct {
   int chunk_steps;
   int rotation_form;        /* Strang: 0 = three shears per rotation (every rotation angle of the
                                solve <= pi/2), 1 = versine form (h = cos - 1, s = sin) */
+  int taylor_order;         /* midpoint: terms J of the series of cos - 1 and sin(x)/x in x = (dt E)^2 */
   size_t device_bytes;      /* device memory the handle owns */
   size_t solve_bytes;       /* device memory a solve of this field needs, chunk state included:
                                tables + n(p) + density partials + state (for admission control) */

@@ -67,6 +67,7 @@ class pd_info(ctypes.Structure):
         ("table_stage", ctypes.c_int),
         ("chunk_steps", ctypes.c_int),
         ("rotation_form", ctypes.c_int),
+        ("taylor_order", ctypes.c_int),
         ("device_bytes", ctypes.c_size_t),
         ("solve_bytes", ctypes.c_size_t),
     ]

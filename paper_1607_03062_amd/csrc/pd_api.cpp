@@ -149,6 +149,10 @@ void fill_info(pd_grid g, const FieldTables& t, long long masked, long long step
   out->table_stage = g->table_stage;
   out->chunk_steps = g->chunk_steps;
   out->rotation_form = t.n_steps > 0 ? strang_form(g->grid, t) : kFormShear;
+  if (g->scheme == PD_SCHEME_MIDPOINT && t.n_steps > 0) {
+    double xm = t.dt * t.E_max;
+    out->taylor_order = taylor_order(xm * xm, g->precision);
+  }
   out->device_bytes = g->device_bytes();
   if (t.n_steps > 0) out->solve_bytes = pd_solve_bytes(g, t.n_steps);
 }

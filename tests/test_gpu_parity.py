@@ -166,6 +166,42 @@ def test_large_step_angles_use_versine_form(gpu, precision):
     assert np.array_equal(n, chunked[0])
 
 
+PAPER_PULSE = {"kind": "pulse", "E0": 1.0, "omega": 0.4876, "phi": 0.3, "omega_rise": 0.0609,
+               "omega_fall": 0.0609, "duration": 70.9}
+
+
+@pytest.mark.parametrize("scheme", ["strang", "midpoint"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_paper_laser_pulse(gpu, scheme, precision):
+    """The rise / flat / fall pulse of Sec. IV, Eq. (14) in reduced units (10 THz, 1e7 V/m,
+    5.5 periods): A_out != 0, so the final spinor uses p + A(t_f)."""
+    g = {"nx": 48, "ny": 40, "px": (-3.0, 3.0), "py": (-2.5, 2.5)}
+    N = 4000
+    n, rho, info = run(gpu, g, PAPER_PULSE, N, precision, scheme)
+    assert abs(info["A_out"]) > 1e-3
+    n_o = oracle.solve_grid(PAPER_PULSE, g, N, scheme)[0]
+    tol = FP64_N_ABS if precision == "fp64" else FP32_N_ABS
+    assert np.max(np.abs(n - n_o)) <= tol
+    if precision == "fp64":
+        assert abs(rho / oracle.density(g, n_o) - 1) <= FP64_RHO_REL
+
+
+@pytest.mark.parametrize("scheme", ["strang", "midpoint"])
+def test_caller_field_table(gpu, scheme):
+    """A field given as its own midpoint table (any time dependence): a sum of sinusoids."""
+    N = 3000
+    t_i, t_f = 0.0, 60.0
+    dt = (t_f - t_i) / N
+    tm = t_i + (np.arange(N) + 0.5) * dt
+    def A(t):
+        return 0.3 * np.sin(0.7 * t) * np.exp(-((t - 30.0) / 15.0) ** 2) + 0.05 * np.sin(1.9 * t + 0.4)
+    f = {"kind": "table", "A_mid": A(tm), "t_i": t_i, "t_f": t_f, "A_in": float(A(t_i)), "A_out": float(A(t_f))}
+    n, rho, info = run(gpu, RAGGED, f, N, "fp64", scheme)
+    n_o = oracle.solve_grid(f, RAGGED, N, scheme)[0]
+    assert np.max(np.abs(n - n_o)) <= FP64_N_ABS
+    assert n.max() > 1e-6
+
+
 def test_repeat_is_bitwise(gpu):
     c = wl.config1()
     a = run(gpu, c["grid"], c["field"], c["n_steps"])
