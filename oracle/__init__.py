@@ -17,6 +17,15 @@ from .pyoracle import (  # noqa: F401
     field_A,
     field_E,
     field_table,
+    field_table_y,
+    field_Ay,
+    field_Ey,
+    composition,
+    boundary_A,
+    snapshot_points,
+    snapshot_grid,
+    state_at,
+    step_matrix_xy,
     times,
     step_matrix,
     spinors,

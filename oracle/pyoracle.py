@@ -4,9 +4,13 @@ Test infrastructure only.  Field and grid descriptions are plain dicts:
 
   field: {"kind": "sin2", "E0", "omega", "cycles"}
          {"kind": "constant", "E0", "t_end"}
-         {"kind": "table", "A_mid" (array, n_steps values), "t_i", "t_f", "A_in", "A_out"}
+         {"kind": "table", "A_mid" (array, stages * n_steps values), "t_i", "t_f", "A_in", "A_out"}
          {"kind": "pulse", "E0", "omega", "phi", "omega_rise", "omega_fall", "duration"}
+         optional y component: "ellipticity" (sin2, pulse, constant), or
+         "Ay_mid", "Ay_in", "Ay_out" (table)
   grid:  {"nx", "ny", "px": (min, max), "py": (min, max)}
+  scheme: "strang", "midpoint" (second order) or "strang4", "midpoint4"
+          (Suzuki's fourth-order composition of the same step; 5 stages)
 """
 from __future__ import annotations
 
@@ -21,7 +25,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 _KINDS = {"sin2": 0, "constant": 1, "table": 2, "pulse": 3}
-_SCHEMES = {"strang": 0, "midpoint": 1}
+_SCHEMES = {"strang": (0, 2), "midpoint": (1, 2), "strang4": (0, 4), "midpoint4": (1, 4)}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _llp = ctypes.POINTER(ctypes.c_longlong)
@@ -46,6 +50,11 @@ class _Problem(ctypes.Structure):
         ("n_steps", ctypes.c_longlong),
         ("scheme", ctypes.c_int),
         ("valley", ctypes.c_int),
+        ("order", ctypes.c_int),
+        ("ellipticity", ctypes.c_double),
+        ("Ay_mid", _dp),
+        ("Ay_in", ctypes.c_double),
+        ("Ay_out", ctypes.c_double),
     ]
 
 
@@ -95,6 +104,23 @@ def _configure(lib):
     lib.oracle_grid_p.restype = ctypes.c_double
     lib.oracle_field_table.argtypes = [P, _dp, _dp, _dp, _dp]
     lib.oracle_field_table.restype = ctypes.c_int
+    lib.oracle_field_table_y.argtypes = [P, _dp, _dp, _dp]
+    lib.oracle_field_table_y.restype = ctypes.c_int
+    lib.oracle_Ay.argtypes = [P, ctypes.c_double]
+    lib.oracle_Ay.restype = ctypes.c_double
+    lib.oracle_Ey.argtypes = [P, ctypes.c_double]
+    lib.oracle_Ey.restype = ctypes.c_double
+    lib.oracle_composition.argtypes = [ctypes.c_int, _dp, _dp]
+    lib.oracle_composition.restype = ctypes.c_int
+    lib.oracle_step_matrix_xy.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, _dp]
+    lib.oracle_step_matrix_xy.restype = None
+    lib.oracle_snapshot_points.argtypes = [P, ctypes.c_longlong, ctypes.c_longlong, _dp, _dp, _dp, ctypes.c_int]
+    lib.oracle_snapshot_points.restype = ctypes.c_longlong
+    lib.oracle_state_at.argtypes = [P, ctypes.c_longlong, ctypes.c_double, ctypes.c_double, _dp]
+    lib.oracle_state_at.restype = ctypes.c_int
+    lib.oracle_boundary_A.argtypes = [P, ctypes.c_longlong, _dp, _dp]
+    lib.oracle_boundary_A.restype = ctypes.c_int
     return lib
 
 
@@ -154,20 +180,31 @@ def _problem(field: dict, n_steps: int = 1, scheme: str = "strang", valley: int 
     p.omega = float(field.get("omega", 0.0))
     p.cycles = int(field.get("cycles", 0))
     p.t_end = float(field.get("t_end", 0.0))
+    sch, order = _SCHEMES[scheme]
+    stages = 5 if order == 4 else 1
     if kind == "table":
         A = np.ascontiguousarray(field["A_mid"], dtype=np.float64)
-        if A.shape[0] != n_steps:
-            raise ValueError("table field needs exactly n_steps midpoint values")
+        if A.shape[0] != stages * n_steps:
+            raise ValueError("table field needs exactly stages * n_steps sample values")
         keep.append(A)
         p.A_mid = _ptr(A)
         p.t_i, p.t_f = float(field["t_i"]), float(field["t_f"])
         p.A_in, p.A_out = float(field["A_in"]), float(field["A_out"])
+        if field.get("Ay_mid") is not None:
+            Ay = np.ascontiguousarray(field["Ay_mid"], dtype=np.float64)
+            if Ay.shape[0] != stages * n_steps:
+                raise ValueError("table field needs exactly stages * n_steps A_y values")
+            keep.append(Ay)
+            p.Ay_mid = _ptr(Ay)
+            p.Ay_in, p.Ay_out = float(field["Ay_in"]), float(field["Ay_out"])
+    p.ellipticity = float(field.get("ellipticity", 0.0))
     p.phi = float(field.get("phi", 0.0))
     p.omega_rise = float(field.get("omega_rise", 0.0))
     p.omega_fall = float(field.get("omega_fall", 0.0))
     p.duration = float(field.get("duration", 0.0))
     p.n_steps = int(n_steps)
-    p.scheme = _SCHEMES[scheme]
+    p.scheme = sch
+    p.order = order
     p.valley = 1 if valley >= 0 else -1
     return p, keep
 
@@ -243,14 +280,105 @@ def times(field):
     return a.value, b.value
 
 
-def field_table(field, n_steps):
-    """(A at the step midpoints, A_in, A_out, dt)."""
+def field_Ay(field, t):
     lib = _load()
-    p, keep = _problem(field, n_steps)
-    A = np.zeros(int(n_steps))
+    p, keep = _problem(field)
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    return np.array([lib.oracle_Ay(ctypes.byref(p), float(x)) for x in t])
+
+
+def field_Ey(field, t):
+    lib = _load()
+    p, keep = _problem(field)
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    return np.array([lib.oracle_Ey(ctypes.byref(p), float(x)) for x in t])
+
+
+def composition(order):
+    """(stage coefficients c, stage midpoints sigma) of the oracle's composition."""
+    c = np.zeros(5)
+    sg = np.zeros(5)
+    S = _load().oracle_composition(int(order), _ptr(c), _ptr(sg))
+    return c[:S].copy(), sg[:S].copy()
+
+
+def field_table(field, n_steps, scheme="strang"):
+    """(A_x at the sample times (stages * n_steps values), A_x(t_i), A_x(t_f), dt)."""
+    lib = _load()
+    p, keep = _problem(field, n_steps, scheme)
+    A = np.zeros(int(n_steps) * (5 if _SCHEMES[scheme][1] == 4 else 1))
     a_in, a_out, dt = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     lib.oracle_field_table(ctypes.byref(p), _ptr(A), ctypes.byref(a_in), ctypes.byref(a_out), ctypes.byref(dt))
     return A, a_in.value, a_out.value, dt.value
+
+
+def field_table_y(field, n_steps, scheme="strang"):
+    """(A_y at the sample times, A_y(t_i), A_y(t_f))."""
+    lib = _load()
+    p, keep = _problem(field, n_steps, scheme)
+    A = np.zeros(int(n_steps) * (5 if _SCHEMES[scheme][1] == 4 else 1))
+    a_in, a_out = ctypes.c_double(), ctypes.c_double()
+    if lib.oracle_field_table_y(ctypes.byref(p), _ptr(A), ctypes.byref(a_in), ctypes.byref(a_out)) != 0:
+        raise MemoryError("oracle allocation failed")
+    return A, a_in.value, a_out.value
+
+
+def boundary_A(field, n_steps, k, scheme="strang"):
+    """(A_x, A_y) at the step boundary t_i + k dt."""
+    lib = _load()
+    p, keep = _problem(field, n_steps, scheme)
+    ax, ay = ctypes.c_double(), ctypes.c_double()
+    if lib.oracle_boundary_A(ctypes.byref(p), int(k), ctypes.byref(ax), ctypes.byref(ay)) != 0:
+        raise MemoryError("oracle allocation failed")
+    return ax.value, ay.value
+
+
+def snapshot_points(field, px, py, n_steps, k_steps, scheme="strang", valley=1, threads=0):
+    """Occupation of the instantaneous positive-energy state after k_steps of n_steps steps."""
+    lib = _load()
+    px = np.ascontiguousarray(px, dtype=np.float64).ravel()
+    py = np.ascontiguousarray(py, dtype=np.float64).ravel()
+    n = np.zeros(px.shape[0])
+    p, keep = _problem(field, n_steps, scheme, valley)
+    m = lib.oracle_snapshot_points(ctypes.byref(p), int(k_steps), px.shape[0], _ptr(px), _ptr(py), _ptr(n),
+                                   int(threads))
+    if m < 0:
+        raise MemoryError("oracle allocation failed")
+    return n, int(m)
+
+
+def snapshot_grid(field, grid, n_steps, k_steps, scheme="strang", valley=1, idx=None, threads=0):
+    """snapshot_points on grid points (idx = linear indices j*nx + i; None: all)."""
+    nx, ny = int(grid["nx"]), int(grid["ny"])
+    if idx is None:
+        idx = np.arange(nx * ny, dtype=np.int64)
+    idx = np.asarray(idx, dtype=np.int64)
+    px = np.array([grid_p(grid["px"][0], grid["px"][1], nx, int(k % nx)) for k in idx])
+    py = np.array([grid_p(grid["py"][0], grid["py"][1], ny, int(k // nx)) for k in idx])
+    return snapshot_points(field, px, py, n_steps, k_steps, scheme, valley, threads)
+
+
+def state_at(field, px, py, n_steps, k_steps, scheme="strang", valley=1):
+    """psi after k_steps steps at one momentum (None if masked)."""
+    lib = _load()
+    p, keep = _problem(field, n_steps, scheme, valley)
+    psi = np.zeros(4)
+    m = lib.oracle_state_at(ctypes.byref(p), int(k_steps), float(px), float(py), _ptr(psi))
+    if m < 0:
+        raise MemoryError("oracle allocation failed")
+    if m:
+        return None
+    return np.array([psi[0] + 1j * psi[1], psi[2] + 1j * psi[3]])
+
+
+def step_matrix_xy(px, py, dt, Ax, Ay, scheme="strang", valley=1):
+    """Complex 2x2 matrix of one second-order step with both components of A."""
+    lib = _load()
+    p, keep = _problem({"kind": "constant"}, 1, scheme, valley)
+    U = np.zeros(8)
+    lib.oracle_step_matrix_xy(ctypes.byref(p), float(px), float(py), float(dt), float(Ax), float(Ay), _ptr(U))
+    return np.array([[U[0] + 1j * U[1], U[4] + 1j * U[5]],
+                     [U[2] + 1j * U[3], U[6] + 1j * U[7]]])
 
 
 def step_matrix(px, py, dt, A_k, scheme="strang", valley=1):

@@ -15,6 +15,10 @@ Units are hbar = v_F = e = 1.  A field is a plain dict:
                                               Sec. IV, Eq. (14), t in [0, duration]
   {"kind": "table", "A_mid", "t_i", "t_f", "A_in", "A_out"}
 
+Elliptic polarisation adds a y component: "ellipticity" e (sin2: E_y =
+e E0 sin^2(pi t/T) cos(omega t); pulse: E_y = e E0 env(t) sin(omega t + phi);
+constant: E_y = e E0), or for a table "Ay_mid", "Ay_in", "Ay_out".
+
 A grid is {"nx", "ny", "px": (min, max), "py": (min, max)} on the node
 convention p_j = p_min + j (p_max - p_min) / n, j < n.
 """
@@ -30,12 +34,18 @@ def grid(n: int, half_width: float) -> dict:
             "py": (-float(half_width), float(half_width))}
 
 
-def sin2(E0: float, omega: float, cycles: int) -> dict:
-    return {"kind": "sin2", "E0": float(E0), "omega": float(omega), "cycles": int(cycles)}
+def sin2(E0: float, omega: float, cycles: int, ellipticity: float = 0.0) -> dict:
+    f = {"kind": "sin2", "E0": float(E0), "omega": float(omega), "cycles": int(cycles)}
+    if ellipticity:
+        f["ellipticity"] = float(ellipticity)
+    return f
 
 
-def constant(E0: float, t_end: float) -> dict:
-    return {"kind": "constant", "E0": float(E0), "t_end": float(t_end)}
+def constant(E0: float, t_end: float, ellipticity: float = 0.0) -> dict:
+    f = {"kind": "constant", "E0": float(E0), "t_end": float(t_end)}
+    if ellipticity:
+        f["ellipticity"] = float(ellipticity)
+    return f
 
 
 def sin2_duration(field: dict) -> float:

@@ -9,6 +9,7 @@ import oracle
 from paper_1607_03062_amd import workloads as wl
 
 from . import test_oracle_pins as pins
+from . import test_oracle_pins_ext as ext
 
 MUTANTS = {
     "apply_x_sign": ("psi[0] = a1 + (h * a1 + s * b2);", "psi[0] = a1 + (h * a1 - s * b2);"),
@@ -17,9 +18,9 @@ MUTANTS = {
                            "double al = g * sig * Py, be = g * sig * Px;"),
     "midpoint_term_sign": ("psi[1] = b1 + ((h * b1 - be * b2) - al * a2);",
                            "psi[1] = b1 + ((h * b1 - be * b2) + al * a2);"),
-    "strang_full_first_half": ("apply_y(psi, g * 0.5 * dt * py);\n    apply_x",
-                               "apply_y(psi, g * dt * py);\n    apply_x"),
-    "step_time_not_midpoint": ("t_i + ((double)k + 0.5) * dt", "t_i + ((double)k) * dt"),
+    "strang_full_first_half": ("apply_y(psi, g * 0.5 * dt * Py);\n    apply_x",
+                               "apply_y(psi, g * dt * Py);\n    apply_x"),
+    "step_time_not_midpoint": ("double t = t_i + ((double)k + sg[j]) * dt;", "double t = t_i + ((double)k) * dt;"),
     "sin2_A_sign": ("return -E0 * I;", "return E0 * I;"),
     "sin2_A_term_sign": ("- one_minus_cos((w + W) * t) / (4.0 * (w + W))",
                          "+ one_minus_cos((w + W) * t) / (4.0 * (w + W))"),
@@ -31,9 +32,28 @@ MUTANTS = {
     "density_factor": ("return 4.0 * dx * dy / (4.0 * M_PI * M_PI) * s;",
                        "return 2.0 * dx * dy / (4.0 * M_PI * M_PI) * s;"),
     "grid_spacing": ("double d = (p_max - p_min) / (double)n;", "double d = (p_max - p_min) / (double)(n - 1);"),
-    "final_momentum_uses_A_in": ("Px_out = px + A_out;", "Px_out = px + A_in;"),
-    "one_step_short": ("for (long long k = 0; k < f->n_steps; ++k) step(",
-                       "for (long long k = 0; k < f->n_steps - 1; ++k) step("),
+    "final_momentum_uses_A_in": ("double Px_out = px + ax, Py_out = py + ay;",
+                                 "double Px_out = px + t->e.Ax_in, Py_out = py + ay;"),
+    "one_step_short": ("for (long long k = 0; k < k_stop; ++k) full_step(",
+                       "for (long long k = 0; k < k_stop - 1; ++k) full_step("),
+    # fourth-order composition
+    "suzuki_middle_coefficient": ("c[2] = 1.0 - 4.0 * p;", "c[2] = 1.0 - 3.0 * p;"),
+    "suzuki_p_value": ("double p = 1.0 / (4.0 - cbrt(4.0));", "double p = 1.0 / (4.0 - cbrt(2.0));"),
+    "stage_time_at_start": ("sigma[j] = start + 0.5 * c[j];", "sigma[j] = start;"),
+    "stage_coefficient_not_applied": ("step(f->scheme, g, psi, c[j] * dt,", "step(f->scheme, g, psi, dt / S,"),
+    # elliptic polarisation
+    "Ay_sign_in_step": ("double Px = px + Ax, Py = py + Ay;", "double Px = px + Ax, Py = py - Ay;"),
+    "projection_drops_Ay": ("double Px_out = px + ax, Py_out = py + ay;", "double Px_out = px + ax, Py_out = py;"),
+    "initial_state_drops_Ay": ("Py_in = py + t->e.Ay_in;", "Py_in = py;"),
+    "sin2_Ay_term_sign": ("- sin((w + W) * t) / (4.0 * (w + W))", "+ sin((w + W) * t) / (4.0 * (w + W))"),
+    "pulse_Ay_quarter_period": ("return f->ellipticity * pulse_A_phase(f, f->phi - 0.5 * M_PI, t);",
+                                "return f->ellipticity * pulse_A_phase(f, f->phi + 0.5 * M_PI, t);"),
+    "constant_Ay_sign": ("return -f->ellipticity * f->E0 * t;", "return f->ellipticity * f->E0 * t;"),
+    # snapshots
+    "snapshot_time_half_step_late": ("double t = t_i + (double)k * e->dt;",
+                                     "double t = t_i + ((double)k + 0.5) * e->dt;"),
+    "snapshot_projects_on_final_state": ("boundary_A(f, k_stop, t->Ax, t->Ay, &t->e, &ax, &ay);",
+                                         "boundary_A(f, f->n_steps, t->Ax, t->Ay, &t->e, &ax, &ay);"),
 }
 
 
@@ -58,6 +78,17 @@ QUICK_PINS = [
     pins.test_masked_point_at_zero_momentum,
     _py_zero_row,
     pins.test_landau_zener_constant_field,
+    ext.test_composition_order_conditions,
+    lambda: ext.test_fourth_order_convergence("midpoint4"),
+    lambda: ext.test_step_with_Ay_equals_matrix_exponential("strang"),
+    lambda: ext.test_step_with_Ay_equals_matrix_exponential("midpoint"),
+    lambda: ext.test_sin2_Ay_is_minus_integral_of_Ey(1.0),
+    ext.test_pulse_and_constant_Ay,
+    lambda: ext.test_rotation_covariance("midpoint"),
+    lambda: ext.test_y_reflection_symmetry("strang"),
+    ext.test_snapshot_at_start_is_zero,
+    lambda: ext.test_snapshot_adiabatic_perturbation(1.0),
+    lambda: ext.test_snapshot_continuum_dop853(((0.25, 0.125),)),
 ]
 
 
