@@ -34,17 +34,24 @@ ALGO = {(0, "fp64"): (18, 9), (0, "fp32"): (18, 9), (1, "fp64"): (24, 12), (1, "
 
 
 def algo(info: dict, precision: str):
-    """(flop, VALU instructions) per point-step of the solve described by pd_info.
-    Midpoint step with Taylor order J: phase X = dt(px + A_k) (1 add) and x = X^2 + Y^2
+    """(flop, VALU instructions) per point-step of the solve described by pd_info; a
+    fourth-order step is `stages` = 5 second-order stages.
+    Strang stage: three rotations (ALGO), a fourth one (the field part of the y
+    rotation) when the field has a y component.
+    Midpoint stage with Taylor order J: phase X = c dt(px + A) (1 add) and x = X^2 + Y^2
     (1 fma) in FP64; cos - 1 (J - 1 fma + 1 mul) and sin(x)/x (J fma); alpha, beta (2 mul);
     the 2x2 update: FP64 3 fma per component (24 flop, 12 instr), FP32 mul + 2 fma + add
-    per component (24 flop, 16 instr) plus 3 conversions."""
-    if info["scheme"] == 0:
-        return ALGO[(info["rotation_form"], precision)]
+    per component (24 flop, 16 instr) plus 3 conversions; a y component adds Y = Y0 + dy
+    and Y^2 (2 flop, 2 instr)."""
+    stages = info.get("stages", 1) or 1
+    ell = info.get("elliptic", 0)
+    if info["scheme"] in (0, 2):
+        f, i = ALGO[(info["rotation_form"], precision)]
+        return stages * f * (4 if ell else 3) // 3, stages * i * (4 if ell else 3) // 3
     J = info["taylor_order"]
-    flops = 3 + (2 * (J - 1) + 1) + 2 * J + 2 + 24
-    instr = 2 + 2 * J + 2 + (12 if precision == "fp64" else 16 + 3)
-    return flops, instr
+    flops = 3 + (2 * (J - 1) + 1) + 2 * J + 2 + 24 + (2 if ell else 0)
+    instr = 2 + 2 * J + 2 + (12 if precision == "fp64" else 16 + 3) + (2 if ell else 0)
+    return stages * flops, stages * instr
 # MI355X vector peaks from its unit counts and clock (256 CU, 2.4 GHz): FP64
 # issues 64 lanes per clock per CU (78.6 TFLOP/s with FMA); unpacked FP32 with
 # VGPR operands issues 128 lanes per clock per CU (157.3 TFLOP/s with FMA).
@@ -243,7 +250,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--scheme", choices=["strang", "midpoint"], default="strang")
+    ap.add_argument("--scheme", choices=["strang", "midpoint", "strang4", "midpoint4"], default="strang")
+    ap.add_argument("--ellipticity", type=float, default=0.0,
+                    help="give the workload pulse a y component E_y = e E0 sin^2(pi t/T) cos(omega t)")
+    ap.add_argument("--n-steps", type=int, default=0, help="override the workload's 80000 steps")
     ap.add_argument("--ppl", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid", type=int, default=2048)
@@ -272,6 +282,10 @@ def main():
     if args.workload == "serve":
         return run_serve(args)
     c = wl.config3(n=args.grid, precision=args.precision)
+    if args.ellipticity:
+        c["field"]["ellipticity"] = args.ellipticity
+    if args.n_steps:
+        c["n_steps"] = args.n_steps
     npts = c["grid"]["nx"] * c["grid"]["ny"]
     ps_per_solve = npts * c["n_steps"]
 
@@ -289,8 +303,8 @@ def main():
     main_form = time_form(pd, torch, c, args.precision, args.steps, args.warmup, args.ppl, args.block, scheme=sch)
     other = None
     if not args.no_fp64_form and args.precision != "fp64":
-        other = time_form(pd, torch, wl.config3(n=args.grid, precision="fp64"), "fp64", args.steps, args.warmup,
-                          args.ppl, args.block, scheme=sch)
+        c64 = dict(c, field=dict(c["field"]), precision="fp64")
+        other = time_form(pd, torch, c64, "fp64", args.steps, args.warmup, args.ppl, args.block, scheme=sch)
 
     # oracle on the 64 x 64 subsample: n(p) error of each form and the CPU baseline
     n_err = {}
@@ -336,9 +350,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": "%dx%d momentum grid on [-2,2]^2, sin^2 pulse E0=0.1 omega=0.5 30 cycles, "
-                               "%d %s steps, %s form" % (args.grid, args.grid, c["n_steps"],
-                                                         "Strang" if sch == "strang" else "midpoint",
+        "config": {"workload": "%dx%d momentum grid on [-2,2]^2, sin^2 pulse E0=0.1 omega=0.5 30 cycles%s, "
+                               "%d %s steps, %s form" % (args.grid, args.grid,
+                                                         (" ellipticity %g" % args.ellipticity) if args.ellipticity
+                                                         else "", c["n_steps"],
+                                                         {"strang": "Strang", "midpoint": "midpoint",
+                                                          "strang4": "fourth-order Strang",
+                                                          "midpoint4": "fourth-order midpoint"}[sch],
                                                          args.precision.upper()),
                    "n_points": npts, "n_steps": c["n_steps"], "precision": args.precision, "scheme": sch,
                    "points_per_lane": main_form["info"]["points_per_lane"],
@@ -351,7 +369,8 @@ def main():
         "kernel_ms": kern_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": traffic_from_profile(args.precision) if sch == "strang" else None,
+                     "traffic": traffic_from_profile(args.precision) if (sch == "strang" and not args.ellipticity)
+                     else None,
                      "valu_issue_frac": instr * ps_per_solve / (kern_ms * 1e-3) / (
                          CU_CLOCKS_PER_S * LANES_PER_CLK[args.precision])},
         "cpu_baseline": cpu,

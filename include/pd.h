@@ -20,6 +20,8 @@
  *     potential at its midpoint t_i + (k + 1/2) dt (Sec. III, Eqs. (11)-(12)).
  *   - A point where |p + A(t_i)| = 0 or |p + A(t_f)| = 0 has no defined
  *     adiabatic spinor; it gets n = 0 and is counted in pd_info.n_masked.
+ *   - With a y component of the field (elliptic polarisation) P = p + A with
+ *     both components everywhere: steps, spinors, masking, step condition.
  *   - Every call returns a pd_status; nothing crosses the ABI as an exception.
  *     The message of the last failure on the calling thread is returned by
  *     pd_last_error().
@@ -58,13 +60,30 @@ typedef enum {
 } pd_precision;
 
 typedef enum {
-  /* exp(-i dt py sy/2) exp(-i dt (px + A) sx) exp(-i dt py sy/2): the midpoint
-     Hamiltonian of Sec. III split into its sigma_y and sigma_x parts */
+  /* exp(-i dt Py sy/2) exp(-i dt Px sx) exp(-i dt Py sy/2), P = p + A(t_{k+1/2}):
+     the midpoint Hamiltonian of Sec. III split into its sigma_y and sigma_x parts */
   PD_SCHEME_STRANG = 0,
   /* the paper's step, exp(-i dt sigma.P(t_{k+1/2})) in the closed 2x2 form of
      Sec. III, Eq. (13) */
-  PD_SCHEME_MIDPOINT = 1
+  PD_SCHEME_MIDPOINT = 1,
+  /* fourth order: each step is Suzuki's fractal composition of five steps of the
+     second-order scheme, S(c1 dt) ... S(c5 dt), c = (p, p, 1 - 4p, p, p),
+     p = 1/(4 - 4^(1/3)) (the higher-order decompositions Sec. III names after
+     Eq. (12)); stage j samples A at its own sub-interval midpoint
+     t_i + (k + sigma_j) dt, sigma_j = c1 + ... + c_{j-1} + c_j / 2 */
+  PD_SCHEME_STRANG4 = 2,
+  PD_SCHEME_MIDPOINT4 = 3
 } pd_scheme;
+
+typedef enum {
+  /* valley K+ propagated; rho counts both valleys (identical n, Sec. II) and both
+     spins: factor 4 */
+  PD_VALLEYS_BOTH = 0,
+  /* one valley explicitly (K+: H = +sigma.P, K-: H = -sigma.P with the spinors
+     of Sec. II, Eqs. (3)-(4)); rho counts the two spins only: factor 2 */
+  PD_VALLEY_KPLUS = 1,
+  PD_VALLEY_KMINUS = 2
+} pd_valley;
 
 typedef enum {
   PD_FIELD_SIN2 = 0,     /* E(t) = E0 sin^2(pi t/T) sin(omega t), T = cycles 2 pi/omega, t in [0, T] */
@@ -76,9 +95,18 @@ typedef enum {
                             over the last pi/(2 omega_fall), E0 cos(omega t + phi) between */
 } pd_field_kind;
 
-/* A homogeneous field along x in the gauge A_0 = 0, E = -dA/dt
-   (Sec. II, after Eq. (2)); A(t) = -int_{t_i}^{t} E.  Only the members of the
-   chosen kind are read.  The struct and A_mid are copied during the call. */
+/* A homogeneous field in the gauge A_0 = 0, E = -dA/dt (Sec. II, after
+   Eq. (2)); A(t) = -int_{t_i}^{t} E.  Linear along x unless a y component is
+   given (elliptic polarisation, Sec. V): `ellipticity` e adds
+     SIN2:     E_y = e E0 sin^2(pi t/T) cos(omega t)
+     PULSE:    E_y = e E0 env(t) sin(omega t + phi)  (the x carrier a quarter period later)
+     CONSTANT: E_y = e E0
+   and a TABLE field may carry A_y samples.  A TABLE gives A at the sample times
+   the scheme uses: stages * N values (index k * stages + j) at
+   t_i + (k + sigma_j) dt, i.e. the N step midpoints for the second-order
+   schemes and 5 N stage midpoints for the fourth-order ones.  Only the members
+   of the chosen kind are read.  The struct and the arrays are copied during the
+   call. */
 typedef struct {
   int kind;                 /* pd_field_kind */
   double E0, omega;         /* SIN2, PULSE */
@@ -92,6 +120,9 @@ typedef struct {
   double omega_rise;        /* PULSE: > 0 */
   double omega_fall;        /* PULSE: > 0 */
   double duration;          /* PULSE: >= pi/(2 omega_rise) + pi/(2 omega_fall) */
+  double ellipticity;       /* SIN2, PULSE, CONSTANT: E_y amplitude / E0 (0: linear) */
+  const double* Ay_mid;     /* TABLE: NULL (A_y = 0) or n_table values of A_y */
+  double Ay_in, Ay_out;     /* TABLE with Ay_mid: A_y(t_i), A_y(t_f) */
 } pd_field;
 
 typedef struct {
@@ -114,6 +145,10 @@ typedef struct {
   size_t device_bytes;      /* device memory the handle owns */
   size_t solve_bytes;       /* device memory a solve of this field needs, chunk state included:
                                tables + n(p) + density partials + state (for admission control) */
+  int valley;               /* pd_valley */
+  int stages;               /* second-order steps per step: 1, or 5 for the fourth-order schemes */
+  int elliptic;             /* 1 if the field has a y component */
+  double Ay_in, Ay_out;     /* A_y(t_i), A_y(t_f) */
 } pd_info;
 
 /* Create a solver on an nx x ny node grid (1 <= nx, ny <= 65536; finite ranges
@@ -128,11 +163,23 @@ pd_status pd_create_grid(int nx, int ny, double px_min, double px_max, double py
    out of range.  out may be NULL. */
 pd_status pd_check_field(pd_grid g, const pd_field* f, long long n_steps, pd_info* out);
 
-/* Host-only query of the field sampling used by a solve: writes the n_steps
-   values A(t_i + (k + 1/2) dt) to the host array A_mid (may be NULL) and the
-   end values to *t_i, *t_f, *A_in, *A_out (each may be NULL).  No device work. */
+/* Host-only query of the field sampling used by a second-order solve: writes
+   the n_steps values A_x(t_i + (k + 1/2) dt) to the host array A_mid (may be
+   NULL) and the end values to *t_i, *t_f, *A_in, *A_out (each may be NULL).
+   No device work. */
 pd_status pd_sample_field(const pd_field* f, long long n_steps, double* A_mid, double* t_i, double* t_f,
                           double* A_in, double* A_out);
+
+/* The same for any scheme and both components: stages * n_steps samples of A_x
+   and of A_y at t_i + (k + sigma_j) dt (host arrays, each may be NULL), and
+   ends[6] = {t_i, t_f, A_x(t_i), A_x(t_f), A_y(t_i), A_y(t_f)} (may be NULL). */
+pd_status pd_sample_field_xy(const pd_field* f, long long n_steps, int scheme, double* Ax_mid, double* Ay_mid,
+                             double* ends);
+
+/* Choose the valley (pd_valley) before pd_set_field; PD_ERR_STATE once a
+   field is set on the handle, PD_ERR_INVALID for an unknown value.  The default
+   is PD_VALLEYS_BOTH. */
+pd_status pd_set_valley(pd_grid g, int valley);
 
 /* Set the field and the number of steps N >= 1: builds the per-step FP64
    table of the field on the host (A at the step midpoints, Sec. III,
@@ -160,6 +207,20 @@ pd_status pd_propagate(pd_grid g, long long max_steps, void* stream);
    memory), and writes rho to the host double *rho_out (may be NULL).  When
    rho_out or a host n_out is given the call waits for stream. */
 pd_status pd_density(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, void* stream);
+
+/* Time-resolved occupation after the steps done so far (0 <= steps_done <= N,
+   e.g. between chunked pd_propagate calls): the state is projected on the
+   positive-energy eigenvector of the Hamiltonian at the step boundary
+   t_k = t_i + k dt, k = steps_done, n_k(p) = |u(p + A(t_k))^dagger psi_k|^2
+   (the instantaneous adiabatic occupation; equal to n(p) at k = N).  A(t_k)
+   is the field's own value there; for a TABLE field, between two steps, the
+   mean of the last sample of step k - 1 and the first of step k.  Points with
+   |p + A(t_i)| = 0 or |p + A(t_k)| = 0 get 0.  Writes n_k to the handle's n
+   buffer (a later pd_density is only valid after the solve completes again),
+   sums it into rho with the factor of pd_density, copies n_k to n_out and rho
+   to *rho_out like pd_density.  Does not advance the solve.  PD_ERR_STATE
+   before pd_set_field. */
+pd_status pd_snapshot(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, void* stream);
 
 /* Bytes of device state a chunked solve keeps between pd_propagate calls
    (3 FP64 or FP32 values per point for PD_SCHEME_STRANG, 4 for
@@ -227,7 +288,9 @@ typedef struct {
 } pd_batch_info;
 
 pd_status pd_batch_create(pd_batch* out);
-/* Add a Strang grid (PD_ERR_UNSUPPORTED for the midpoint scheme). */
+/* Add a PD_SCHEME_STRANG grid (PD_ERR_UNSUPPORTED for the other schemes; a
+   member whose field has a y component makes pd_batch_run and pd_batch_step
+   return PD_ERR_UNSUPPORTED). */
 pd_status pd_batch_add(pd_batch b, pd_grid g);
 /* Remove one member (PD_ERR_INVALID if it is not one); remove a grid from every
    batch before destroying it.  Neither call touches the grids themselves. */

@@ -12,11 +12,15 @@ LIB_PATH = os.path.join(_PKG, "libpd.so")
 
 PD_OK, PD_ERR_INVALID, PD_ERR_STATE, PD_ERR_NOMEM, PD_ERR_DEVICE, PD_ERR_UNSUPPORTED = range(6)
 PD_FP64, PD_FP32 = 0, 1
-PD_SCHEME_STRANG, PD_SCHEME_MIDPOINT = 0, 1
+PD_SCHEME_STRANG, PD_SCHEME_MIDPOINT, PD_SCHEME_STRANG4, PD_SCHEME_MIDPOINT4 = 0, 1, 2, 3
+PD_VALLEYS_BOTH, PD_VALLEY_KPLUS, PD_VALLEY_KMINUS = 0, 1, 2
 PD_FIELD_SIN2, PD_FIELD_CONSTANT, PD_FIELD_TABLE, PD_FIELD_PULSE = 0, 1, 2, 3
 
 PRECISIONS = {"fp64": PD_FP64, "fp32": PD_FP32}
-SCHEMES = {"strang": PD_SCHEME_STRANG, "midpoint": PD_SCHEME_MIDPOINT}
+SCHEMES = {"strang": PD_SCHEME_STRANG, "midpoint": PD_SCHEME_MIDPOINT, "strang4": PD_SCHEME_STRANG4,
+           "midpoint4": PD_SCHEME_MIDPOINT4}
+STAGES = {"strang": 1, "midpoint": 1, "strang4": 5, "midpoint4": 5}
+VALLEYS = {"both": PD_VALLEYS_BOTH, "K+": PD_VALLEY_KPLUS, "K-": PD_VALLEY_KMINUS}
 FIELD_KINDS = {"sin2": PD_FIELD_SIN2, "constant": PD_FIELD_CONSTANT, "table": PD_FIELD_TABLE,
                "pulse": PD_FIELD_PULSE}
 STATUS_NAMES = {0: "PD_OK", 1: "PD_ERR_INVALID", 2: "PD_ERR_STATE", 3: "PD_ERR_NOMEM", 4: "PD_ERR_DEVICE",
@@ -43,6 +47,10 @@ class pd_field(ctypes.Structure):
         ("omega_rise", ctypes.c_double),
         ("omega_fall", ctypes.c_double),
         ("duration", ctypes.c_double),
+        ("ellipticity", ctypes.c_double),
+        ("Ay_mid", _dp),
+        ("Ay_in", ctypes.c_double),
+        ("Ay_out", ctypes.c_double),
     ]
 
 
@@ -70,6 +78,11 @@ class pd_info(ctypes.Structure):
         ("taylor_order", ctypes.c_int),
         ("device_bytes", ctypes.c_size_t),
         ("solve_bytes", ctypes.c_size_t),
+        ("valley", ctypes.c_int),
+        ("stages", ctypes.c_int),
+        ("elliptic", ctypes.c_int),
+        ("Ay_in", ctypes.c_double),
+        ("Ay_out", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -92,10 +105,14 @@ SIGNATURES = [
                                       ctypes.POINTER(_vp)]),
     ("pd_check_field", ctypes.c_int, [_vp, ctypes.POINTER(pd_field), ctypes.c_longlong, ctypes.POINTER(pd_info)]),
     ("pd_sample_field", ctypes.c_int, [ctypes.POINTER(pd_field), ctypes.c_longlong, _dp, _dp, _dp, _dp, _dp]),
+    ("pd_sample_field_xy", ctypes.c_int, [ctypes.POINTER(pd_field), ctypes.c_longlong, ctypes.c_int, _dp, _dp,
+                                          _dp]),
+    ("pd_set_valley", ctypes.c_int, [_vp, ctypes.c_int]),
     ("pd_set_field", ctypes.c_int, [_vp, ctypes.POINTER(pd_field), ctypes.c_longlong]),
     ("pd_rewind", ctypes.c_int, [_vp]),
     ("pd_propagate", ctypes.c_int, [_vp, ctypes.c_longlong, _vp]),
     ("pd_density", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _vp]),
+    ("pd_snapshot", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _vp]),
     ("pd_state_bytes", ctypes.c_size_t, [_vp]),
     ("pd_solve_bytes", ctypes.c_size_t, [_vp, ctypes.c_longlong]),
     ("pd_bind_state", ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
@@ -169,7 +186,7 @@ def stream_handle(stream) -> int | None:
 def make_field(field: dict, n_steps: int):
     """pd_field from a field dict; returns (struct, keep-alive)."""
     f = pd_field()
-    keep = None
+    keep = []
     kind = field["kind"]
     f.kind = FIELD_KINDS[kind]
     f.E0 = float(field.get("E0", 0.0))
@@ -177,11 +194,20 @@ def make_field(field: dict, n_steps: int):
     f.cycles = int(field.get("cycles", 0))
     f.t_end = float(field.get("t_end", 0.0))
     if kind == "table":
-        keep = np.ascontiguousarray(field["A_mid"], dtype=np.float64)
-        f.A_mid = keep.ctypes.data_as(_dp)
-        f.n_table = keep.shape[0]
+        A = np.ascontiguousarray(field["A_mid"], dtype=np.float64)
+        keep.append(A)
+        f.A_mid = A.ctypes.data_as(_dp)
+        f.n_table = A.shape[0]
         f.t_i, f.t_f = float(field["t_i"]), float(field["t_f"])
         f.A_in, f.A_out = float(field["A_in"]), float(field["A_out"])
+        if field.get("Ay_mid") is not None:
+            Ay = np.ascontiguousarray(field["Ay_mid"], dtype=np.float64)
+            if Ay.shape != A.shape:
+                raise ValueError("Ay_mid must have as many values as A_mid")
+            keep.append(Ay)
+            f.Ay_mid = Ay.ctypes.data_as(_dp)
+            f.Ay_in, f.Ay_out = float(field["Ay_in"]), float(field["Ay_out"])
+    f.ellipticity = float(field.get("ellipticity", 0.0))
     f.phi = float(field.get("phi", 0.0))
     f.omega_rise = float(field.get("omega_rise", 0.0))
     f.omega_fall = float(field.get("omega_fall", 0.0))
@@ -199,6 +225,16 @@ def sample_field(field: dict, n_steps: int):
     return (A,) + tuple(v.value for v in vals)
 
 
+def sample_field_xy(field: dict, n_steps: int, scheme: str = "strang"):
+    """Library sampling for any scheme: (A_x samples, A_y samples, (t_i, t_f, Ax_in, Ax_out, Ay_in, Ay_out))."""
+    f, keep = make_field(field, n_steps)
+    m = STAGES[scheme] * int(n_steps)
+    Ax, Ay, ends = np.zeros(m), np.zeros(m), np.zeros(6)
+    check(load().pd_sample_field_xy(ctypes.byref(f), int(n_steps), SCHEMES[scheme], Ax.ctypes.data_as(_dp),
+                                    Ay.ctypes.data_as(_dp), ends.ctypes.data_as(_dp)), "pd_sample_field_xy")
+    return Ax, Ay, tuple(ends)
+
+
 def _ptr_of(buf):
     """(address, on_device) of a torch tensor or numpy array."""
     if hasattr(buf, "data_ptr"):
@@ -209,7 +245,7 @@ def _ptr_of(buf):
 class Solver:
     """One momentum grid and its solve (pd_grid handle)."""
 
-    def __init__(self, nx, ny, px, py, precision="fp64", scheme="strang"):
+    def __init__(self, nx, ny, px, py, precision="fp64", scheme="strang", valley="both"):
         lib = load()
         h = _vp()
         check(lib.pd_create_grid(int(nx), int(ny), float(px[0]), float(px[1]), float(py[0]), float(py[1]),
@@ -217,10 +253,16 @@ class Solver:
         self._h = h
         self.nx, self.ny = int(nx), int(ny)
         self.precision, self.scheme = precision, scheme
+        if valley != "both":
+            self.set_valley(valley)
 
     @classmethod
-    def for_grid(cls, grid: dict, precision="fp64", scheme="strang"):
-        return cls(grid["nx"], grid["ny"], grid["px"], grid["py"], precision, scheme)
+    def for_grid(cls, grid: dict, precision="fp64", scheme="strang", valley="both"):
+        return cls(grid["nx"], grid["ny"], grid["px"], grid["py"], precision, scheme, valley)
+
+    def set_valley(self, valley: str):
+        check(load().pd_set_valley(self._h, VALLEYS[valley]), "pd_set_valley")
+        return self
 
     @property
     def handle(self):
@@ -251,6 +293,14 @@ class Solver:
         rho = ctypes.c_double()
         check(load().pd_density(self._h, ptr, dev, ctypes.byref(rho) if want_rho else None,
                                 stream_handle(stream)), "pd_density")
+        return rho.value if want_rho else None
+
+    def snapshot(self, n_out=None, want_rho: bool = True, stream=None):
+        """Instantaneous occupation after the steps done so far; rho (float) or None, n_out filled if given."""
+        ptr, dev = (None, 0) if n_out is None else _ptr_of(n_out)
+        rho = ctypes.c_double()
+        check(load().pd_snapshot(self._h, ptr, dev, ctypes.byref(rho) if want_rho else None,
+                                 stream_handle(stream)), "pd_snapshot")
         return rho.value if want_rho else None
 
     def solve(self, stream=None, n_out=None):

@@ -4,7 +4,7 @@
 // first `trial_steps` steps of the grid's own solve (chunked propagation, so the
 // state goes through device memory exactly as in a long solve); the fastest is
 // kept.  Results can be cached in a text file named by PD_AUTOTUNE_CACHE, one
-// line per key "arch precision scheme form size_class" with the chosen
+// line per key "arch precision scheme[-xy] form size_class" with the chosen
 // points_per_lane, block_threads, table_stage and chunk_steps.
 #include <hip/hip_runtime_api.h>
 
@@ -39,8 +39,9 @@ std::string arch_name(int device) {
 std::string cache_key(pd_grid g) {
   int size_class = (int)std::floor(std::log2((double)g->grid.points()));
   std::ostringstream k;
-  k << arch_name(g->device) << " " << (g->precision == PD_FP32 ? "fp32" : "fp64") << " "
-    << (g->scheme == PD_SCHEME_STRANG ? "strang" : "midpoint") << " " << g->form << " " << size_class;
+  static const char* const kSchemes[] = {"strang", "midpoint", "strang4", "midpoint4"};
+  k << arch_name(g->device) << " " << (g->precision == PD_FP32 ? "fp32" : "fp64") << " " << kSchemes[g->scheme]
+    << (g->field.elliptic ? "-xy" : "") << " " << g->form << " " << size_class;
   return k.str();
 }
 
@@ -120,7 +121,7 @@ pd_status pd_autotune(pd_grid g, long long trial_steps, int use_cache, void* str
   for (int ppl : {1, 2, 4})
     for (int block : {64, 256}) {
       cands.push_back({ppl, block, 2, g->chunk_steps});
-      if (g->scheme == PD_SCHEME_STRANG)
+      if (base_scheme(g->scheme) == PD_SCHEME_STRANG)
         for (int chunk : {256, 1024}) cands.push_back({ppl, block, 1, chunk});
     }
   const long long steps = trial_steps < g->field.n_steps ? trial_steps : g->field.n_steps;

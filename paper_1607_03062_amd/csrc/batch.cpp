@@ -196,6 +196,8 @@ pd_status check_members(pd_batch b) {
   if (b->grids.empty()) return set_error(PD_ERR_STATE, "empty batch");
   for (pd_grid g : b->grids) {
     if (!g->field_set) return set_error(PD_ERR_STATE, "a member grid has no field");
+    if (g->field.elliptic)
+      return set_error(PD_ERR_UNSUPPORTED, "batches run linearly polarised fields only (a member has A_y)");
     if (g->device != b->device) return set_error(PD_ERR_INVALID, "member grids are on different devices");
   }
   return PD_OK;

@@ -39,13 +39,6 @@ namespace {
 
 constexpr long long kRenormEvery = 1024;  // FP32 form: renormalise after every 1024th step
 
-// Two coefficients of a plane rotation: (tan(phi/2), sin(phi)) in the shear
-// form, (cos(phi) - 1, sin(phi)) in the versine form.
-template <typename R>
-struct Row {
-  R a, s;
-};
-
 // Rotation of (u, v) by phi: u' = u cos - v sin, v' = u sin + v cos.
 // Shear form, t = tan(phi/2), s = sin(phi): u -= t v; v += s u; u -= t v.
 template <typename R>
@@ -96,20 +89,54 @@ __device__ __forceinline__ PointCoords coords(const SolveParams& p, long long id
   return c;
 }
 
-// The Bloch vectors of a lane's points and their per-point rotations.
-template <typename R, int PPL, int FORM>
-struct BlochLanes {
-  R x[PPL], y[PPL], z[PPL];
-  R aX[PPL], sX[PPL], aY[PPL], sY[PPL];  // rotations by 2 dt px about x and 2 dt py about y
+// Rotation layout of one step of a composition with NS stages.  Stage j applies
+// the x rotation by its field part (table) and by its per-point part (class
+// xcls(j) of the column coefficients), then the y rotation that follows it: its
+// per-point part (class ycls(j) of the row coefficients) and, with a y component
+// of the field (POL), its field part (table).  The y rotations of neighbouring
+// stages, and of the last stage of a step and the first of the next, are merged;
+// the solve opens and closes with a half step (the last row class).
+template <int NS>
+struct Layout;
+template <>
+struct Layout<1> {
+  static constexpr int NX = 1, NY = 2;  // y classes: full, half
+  __device__ static constexpr int xcls(int) { return 0; }
+  __device__ static constexpr int ycls(int) { return 0; }
+};
+template <>
+struct Layout<5> {
+  // c = (p, p, q, p, p): x classes {p, q}; y classes {(p + p)/2, (p + q)/2, half}
+  static constexpr int NX = 2, NY = 3;
+  __device__ static constexpr int xcls(int j) { return j == 2 ? 1 : 0; }
+  __device__ static constexpr int ycls(int j) { return (j == 1 || j == 2) ? 1 : 0; }
+};
 
-  // one merged Strang step: rotation by 2 dt A_k about x (table row), by
-  // 2 dt px about x, and by 2 dt py about y
-  __device__ __forceinline__ void step(R a, R s) {
+// The Bloch vectors of a lane's points and their per-point rotations.
+template <typename R, int PPL, int FORM, int NS, int POL>
+struct BlochLanes {
+  using L = Layout<NS>;
+  static constexpr int kRow = 2 * NS * (1 + POL);  // table values per step
+  R x[PPL], y[PPL], z[PPL];
+  R aX[L::NX][PPL], sX[L::NX][PPL];          // x rotations by 2 c dt px
+  R aY[L::NY - 1][PPL], sY[L::NY - 1][PPL];  // y rotations after the stages, by (c_j + c_j+1) dt py
+
+  // One step; row = the step's table values.  LAST: the y rotation after the
+  // last stage is the closing half step (ha, hs per point).
+  template <bool LAST>
+  __device__ __forceinline__ void step(const R* row, const R* ha, const R* hs) {
 #pragma unroll
-    for (int q = 0; q < PPL; ++q) {
-      rotate<FORM>(y[q], z[q], a, s);
-      rotate<FORM>(y[q], z[q], aX[q], sX[q]);
-      rotate<FORM>(z[q], x[q], aY[q], sY[q]);
+    for (int j = 0; j < NS; ++j) {
+#pragma unroll
+      for (int q = 0; q < PPL; ++q) {
+        rotate<FORM>(y[q], z[q], row[2 * j], row[2 * j + 1]);
+        rotate<FORM>(y[q], z[q], aX[L::xcls(j)][q], sX[L::xcls(j)][q]);
+        if (LAST && j == NS - 1)
+          rotate<FORM>(z[q], x[q], ha[q], hs[q]);
+        else
+          rotate<FORM>(z[q], x[q], aY[L::ycls(j)][q], sY[L::ycls(j)][q]);
+        if (POL) rotate<FORM>(z[q], x[q], row[2 * NS + 2 * j], row[2 * NS + 2 * j + 1]);
+      }
     }
   }
 
@@ -127,27 +154,35 @@ struct BlochLanes {
   }
 };
 
+template <typename R, int W>
+struct RowN {
+  R v[W];
+};
+
 // Steps [k, k_full) with the table rows read by the scalar unit (SGPR operands).
-template <typename R, int PPL, int FORM>
-__device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM>& L, const Row<R>* __restrict__ tab,
+template <typename R, int PPL, int FORM, int NS, int POL>
+__device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM, NS, POL>& L, const R* __restrict__ table,
                                              long long k, long long k_full) {
+  using Lanes = BlochLanes<R, PPL, FORM, NS, POL>;
+  using Row = RowN<R, Lanes::kRow>;
+  const Row* __restrict__ tab = reinterpret_cast<const Row*>(table);
   while (k < k_full) {
     long long seg = k_full;
     if (sizeof(R) == 4) {
       long long next = (k / kRenormEvery + 1) * kRenormEvery;
       seg = next < k_full ? next : k_full;
     }
-    constexpr int kGroup = 8;  // rows fetched together by one scalar load
+    constexpr int kGroup = Lanes::kRow >= 8 ? 1 : 8 / (Lanes::kRow / 2);  // rows fetched together
     for (; k + kGroup <= seg; k += kGroup) {
-      Row<R> r[kGroup];
+      Row r[kGroup];
 #pragma unroll
       for (int u = 0; u < kGroup; ++u) r[u] = tab[k + u];
 #pragma unroll
-      for (int u = 0; u < kGroup; ++u) L.step(r[u].a, r[u].s);
+      for (int u = 0; u < kGroup; ++u) L.template step<false>(r[u].v, nullptr, nullptr);
     }
     for (; k < seg; ++k) {
-      const Row<R> r = tab[k];
-      L.step(r.a, r.s);
+      const Row r = tab[k];
+      L.template step<false>(r.v, nullptr, nullptr);
     }
     if (sizeof(R) == 4 && (k % kRenormEvery) == 0) L.renormalise();
   }
@@ -156,11 +191,14 @@ __device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM>& L, const 
 // Steps [k, k_full) with the table staged through LDS in chunks of `chunk` rows
 // (absolute chunk boundaries; a power of two dividing the renormalisation period
 // in the FP32 form), so every lane reads its rotation from VGPRs.
-template <typename R, int PPL, int FORM>
-__device__ __forceinline__ void steps_lds(BlochLanes<R, PPL, FORM>& L, const Row<R>* __restrict__ tab, long long k,
-                                          long long k_full, long long chunk) {
+template <typename R, int PPL, int FORM, int NS, int POL>
+__device__ __forceinline__ void steps_lds(BlochLanes<R, PPL, FORM, NS, POL>& L, const R* __restrict__ table,
+                                          long long k, long long k_full, long long chunk) {
+  using Lanes = BlochLanes<R, PPL, FORM, NS, POL>;
+  using Row = RowN<R, Lanes::kRow>;
+  const Row* __restrict__ tab = reinterpret_cast<const Row*>(table);
   extern __shared__ unsigned char pd_lds[];
-  Row<R>* rows = reinterpret_cast<Row<R>*>(pd_lds);
+  Row* rows = reinterpret_cast<Row*>(pd_lds);
   while (k < k_full) {
     long long cend = (k / chunk + 1) * chunk;
     if (cend > k_full) cend = k_full;
@@ -170,8 +208,8 @@ __device__ __forceinline__ void steps_lds(BlochLanes<R, PPL, FORM>& L, const Row
     __syncthreads();
 #pragma unroll 8
     for (int t = 0; t < cnt; ++t) {
-      const Row<R> r = rows[t];
-      L.step(r.a, r.s);
+      const Row r = rows[t];
+      L.template step<false>(r.v, nullptr, nullptr);
     }
     k = cend;
     if (sizeof(R) == 4 && (k % kRenormEvery) == 0) L.renormalise();
@@ -180,71 +218,94 @@ __device__ __forceinline__ void steps_lds(BlochLanes<R, PPL, FORM>& L, const Row
 
 // One tile of a Strang solve: the block's lanes own points base + q * blockDim.x,
 // q < PPL; steps [p.k_begin, p.k_end).
-template <typename R, int PPL, int STAGE, int FORM>
+template <typename R, int PPL, int STAGE, int FORM, int NS, int POL>
 __device__ __forceinline__ void strang_tile(const SolveParams& p, const long long base) {
+  using Lanes = BlochLanes<R, PPL, FORM, NS, POL>;
+  using LY = Layout<NS>;
+  constexpr int CX = 2 * LY::NX, CY = 2 * LY::NY;  // coefficient values per column / row
+  constexpr int HALF = 2 * (LY::NY - 1);           // offset of the half-step pair in a row
   const R* __restrict__ colc = static_cast<const R*>(p.col_coef);
   const R* __restrict__ rowc = static_cast<const R*>(p.row_coef);
-  BlochLanes<R, PPL, FORM> L;
+  const R* __restrict__ table = static_cast<const R*>(p.table);
+  Lanes L;
 
 #pragma unroll
   for (int q = 0; q < PPL; ++q) {
     long long idx = base + (long long)q * blockDim.x;
     if (idx >= p.npts) idx = p.npts - 1;  // tail lanes recompute a valid point and store nothing
     PointCoords c = coords(p, idx);
-    L.aX[q] = colc[2 * c.i];
-    L.sX[q] = colc[2 * c.i + 1];
-    L.aY[q] = rowc[4 * c.j];
-    L.sY[q] = rowc[4 * c.j + 1];
+#pragma unroll
+    for (int m = 0; m < LY::NX; ++m) {
+      L.aX[m][q] = colc[CX * c.i + 2 * m];
+      L.sX[m][q] = colc[CX * c.i + 2 * m + 1];
+    }
+#pragma unroll
+    for (int m = 0; m < LY::NY - 1; ++m) {
+      L.aY[m][q] = rowc[CY * c.j + 2 * m];
+      L.sY[m][q] = rowc[CY * c.j + 2 * m + 1];
+    }
     if (p.load_state) {
       const R* st = static_cast<const R*>(p.state);
       L.x[q] = st[idx];
       L.y[q] = st[p.npts + idx];
       L.z[q] = st[2 * p.npts + idx];
     } else {
-      // v_in: negative-energy eigenvector of sigma.P_in, Bloch vector -P_in/|P_in|
-      double Px = c.px + p.A_in;
-      double E = sqrt(Px * Px + c.py * c.py);
+      // v_in: negative-energy eigenvector of the valley Hamiltonian vsign sigma.P_in,
+      // Bloch vector -vsign P_in/|P_in|
+      double Px = c.px + p.A_in, Py = c.py + p.Ay_in;
+      double E = sqrt(Px * Px + Py * Py);
       double rx = 0.0, ry = 0.0;
       if (E > 0.0) {
-        rx = -Px / E;
-        ry = -c.py / E;
+        rx = -p.vsign * Px / E;
+        ry = -p.vsign * Py / E;
       }
       L.x[q] = (R)rx;
       L.y[q] = (R)ry;
       L.z[q] = (R)0;
-      // first half step exp(-i dt py sy / 2): rotation by dt py about y
-      rotate<FORM>(L.z[q], L.x[q], rowc[4 * c.j + 2], rowc[4 * c.j + 3]);
+      // opening half step about y: per-point part, then (POL) the field part
+      rotate<FORM>(L.z[q], L.x[q], rowc[CY * c.j + HALF], rowc[CY * c.j + HALF + 1]);
+      if (POL) {
+        const R* open = table + (size_t)p.n_steps * Lanes::kRow + 2 * NS;
+        rotate<FORM>(L.z[q], L.x[q], open[0], open[1]);
+      }
     }
   }
 
-  const Row<R>* __restrict__ tab = static_cast<const Row<R>*>(p.table);
   const long long k_full = p.k_end < p.n_steps ? p.k_end : p.n_steps - 1;
   if (STAGE == 1)
-    steps_lds(L, tab, p.k_begin, k_full, p.chunk_steps);
+    steps_lds(L, table, p.k_begin, k_full, p.chunk_steps);
   else
-    steps_scalar(L, tab, p.k_begin, k_full);
+    steps_scalar(L, table, p.k_begin, k_full);
 
   if (p.k_end == p.n_steps) {
-    // last step: full sigma_x factor, then the closing half step about y
-    const Row<R> r = tab[p.n_steps - 1];
+    // last step: its y rotation after the last stage is the closing half step
+    R ha[PPL], hs[PPL];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      long long idx = base + (long long)q * blockDim.x;
+      if (idx >= p.npts) idx = p.npts - 1;
+      PointCoords c = coords(p, idx);
+      ha[q] = rowc[CY * c.j + HALF];
+      hs[q] = rowc[CY * c.j + HALF + 1];
+    }
+    const R* last = table + (size_t)(p.n_steps - 1) * Lanes::kRow;
+    L.template step<true>(last, ha, hs);
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
       long long idx = base + (long long)q * blockDim.x;
       bool valid = idx < p.npts;
       if (!valid) idx = p.npts - 1;
       PointCoords c = coords(p, idx);
-      rotate<FORM>(L.y[q], L.z[q], r.a, r.s);
-      rotate<FORM>(L.y[q], L.z[q], L.aX[q], L.sX[q]);
-      rotate<FORM>(L.z[q], L.x[q], rowc[4 * c.j + 2], rowc[4 * c.j + 3]);
-      // projection on u_out: n = (1 + r.P_out / |P_out|) / 2 with r normalised
-      double Pxi = c.px + p.A_in, Pxo = c.px + p.A_out;
-      double Ei = sqrt(Pxi * Pxi + c.py * c.py), Eo = sqrt(Pxo * Pxo + c.py * c.py);
+      // projection on u_out: n = (1 + vsign r.P_out / |P_out|) / 2 with r normalised
+      double Pxi = c.px + p.A_in, Pyi = c.py + p.Ay_in;
+      double Pxo = c.px + p.A_out, Pyo = c.py + p.Ay_out;
+      double Ei = sqrt(Pxi * Pxi + Pyi * Pyi), Eo = sqrt(Pxo * Pxo + Pyo * Pyo);
       double X = L.x[q], Y = L.y[q], Z = L.z[q];
       double nr = sqrt(X * X + Y * Y + Z * Z);
       double n = 0.0;
       if (Ei > 0.0 && Eo > 0.0 && nr > 0.0) {
-        double dot = (Pxo * X + c.py * Y) / nr;
-        n = (Eo + dot) / (2.0 * Eo);
+        double dot = (Pxo * X + Pyo * Y) / nr;
+        n = (Eo + p.vsign * dot) / (2.0 * Eo);
       }
       if (valid) p.n_out[idx] = n;
     }
@@ -262,9 +323,9 @@ __device__ __forceinline__ void strang_tile(const SolveParams& p, const long lon
   }
 }
 
-template <typename R, int PPL, int STAGE, int FORM>
+template <typename R, int PPL, int STAGE, int FORM, int NS, int POL>
 __global__ void __launch_bounds__(256) strang_kernel(const SolveParams p) {
-  strang_tile<R, PPL, STAGE, FORM>(p, (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x);
+  strang_tile<R, PPL, STAGE, FORM, NS, POL>(p, (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -294,14 +355,14 @@ __global__ void __launch_bounds__(256) batch_kernel(const BatchSolve* __restrict
     const long long base = w.base + threadIdx.x;
     if (s.precision == PD_FP32) {
       if (s.form == kFormShear)
-        strang_tile<float, PPL, 0, kFormShear>(s.p, base);
+        strang_tile<float, PPL, 0, kFormShear, 1, 0>(s.p, base);
       else
-        strang_tile<float, PPL, 0, kFormVersine>(s.p, base);
+        strang_tile<float, PPL, 0, kFormVersine, 1, 0>(s.p, base);
     } else {
       if (s.form == kFormShear)
-        strang_tile<double, PPL, 0, kFormShear>(s.p, base);
+        strang_tile<double, PPL, 0, kFormShear, 1, 0>(s.p, base);
       else
-        strang_tile<double, PPL, 0, kFormVersine>(s.p, base);
+        strang_tile<double, PPL, 0, kFormVersine, 1, 0>(s.p, base);
     }
   }
 }
@@ -374,19 +435,31 @@ __device__ __forceinline__ void midpoint_update(float& a1, float& b1, float& a2,
   b2 += db2;
 }
 
-template <typename R, int J, int PPL>
+// Stage layout of the midpoint kernel: stage j of a step of the NS-stage
+// composition uses the per-point phase of class mcls(j) (c = p or q).
+template <int NS>
+__device__ __forceinline__ constexpr int mcls(int j) {
+  return NS == 5 && j == 2 ? 1 : 0;
+}
+
+template <typename R, int J, int PPL, int NS, int POL>
 __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
+  constexpr int NC = NS == 5 ? 2 : 1;  // distinct stage coefficients
+  constexpr int W = NS * (1 + POL);    // table values per step
   const long long base = (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x;
   R a1[PPL], b1[PPL], a2[PPL], b2[PPL];
-  double X0[PPL], Y[PPL], Y2[PPL];
+  double X0[NC][PPL], Y0[NC][PPL], Y2[NC][PPL];
 #pragma unroll
   for (int q = 0; q < PPL; ++q) {
     long long idx = base + (long long)q * blockDim.x;
     if (idx >= p.npts) idx = p.npts - 1;
     PointCoords c = coords(p, idx);
-    X0[q] = p.dt * c.px;
-    Y[q] = p.dt * c.py;
-    Y2[q] = Y[q] * Y[q];
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+      X0[m][q] = p.hx[m] * c.px;  // vsign c dt px
+      Y0[m][q] = p.hx[m] * c.py;
+      Y2[m][q] = Y0[m][q] * Y0[m][q];
+    }
     if (p.load_state) {
       const R* st = static_cast<const R*>(p.state);
       a1[q] = st[idx];
@@ -394,13 +467,14 @@ __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
       a2[q] = st[2 * p.npts + idx];
       b2[q] = st[3 * p.npts + idx];
     } else {
-      // v_in = (-Px + i py, E) / (sqrt(2) E)   (Sec. II, Eq. (3), unit norm)
-      double Px = c.px + p.A_in;
-      double E = sqrt(Px * Px + c.py * c.py);
+      // v_in = (-Px + i Py, E) / (sqrt(2) E) (Sec. II, Eq. (3), unit norm); the K-
+      // spinor of Eq. (4) is the same with P -> -P
+      double Px = p.vsign * (c.px + p.A_in), Py = p.vsign * (c.py + p.Ay_in);
+      double E = sqrt(Px * Px + Py * Py);
       double d = 1.4142135623730951 * E;
       bool ok = E > 0.0;
       a1[q] = ok ? (R)(-Px / d) : (R)0;
-      b1[q] = ok ? (R)(c.py / d) : (R)0;
+      b1[q] = ok ? (R)(Py / d) : (R)0;
       a2[q] = ok ? (R)(E / d) : (R)0;
       b2[q] = (R)0;
     }
@@ -413,18 +487,24 @@ __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
       long long next = (k / kRenormEvery + 1) * kRenormEvery;
       seg = next < p.k_end ? next : p.k_end;
     }
-#pragma unroll 4
+#pragma unroll(NS == 1 ? 4 : 1)
     for (; k < seg; ++k) {
-      const double d = tab[k];
+      const double* row = tab + k * W;
 #pragma unroll
-      for (int q = 0; q < PPL; ++q) {
-        double X = X0[q] + d;           // dt (px + A_k), FP64 in both forms
-        double x = fma(X, X, Y2[q]);    // (dt E)^2
-        R xr = (R)x;
-        R h = Taylor<J>::h(xr);
-        R sp = Taylor<J>::s(xr);        // sin(dt E) / (dt E)
-        R al = sp * (R)X, be = sp * (R)Y[q];
-        midpoint_update(a1[q], b1[q], a2[q], b2[q], h, al, be);
+      for (int j = 0; j < NS; ++j) {
+        const double d = row[j];
+        const double dy = POL ? row[NS + j] : 0.0;
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+          double X = X0[mcls<NS>(j)][q] + d;  // vsign c dt (px + A_x), FP64 in both forms
+          double Y = POL ? Y0[mcls<NS>(j)][q] + dy : Y0[mcls<NS>(j)][q];
+          double x = POL ? fma(X, X, Y * Y) : fma(X, X, Y2[mcls<NS>(j)][q]);  // (c dt E)^2
+          R xr = (R)x;
+          R h = Taylor<J>::h(xr);
+          R sp = Taylor<J>::s(xr);  // sin(c dt E) / (c dt E)
+          R al = sp * (R)X, be = sp * (R)Y;
+          midpoint_update(a1[q], b1[q], a2[q], b2[q], h, al, be);
+        }
       }
     }
     if (sizeof(R) == 4 && (k % kRenormEvery) == 0 && k < p.n_steps) {
@@ -448,14 +528,15 @@ __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
       bool valid = idx < p.npts;
       if (!valid) idx = p.npts - 1;
       PointCoords c = coords(p, idx);
-      double Pxi = c.px + p.A_in, Pxo = c.px + p.A_out;
-      double Ei = sqrt(Pxi * Pxi + c.py * c.py), Eo = sqrt(Pxo * Pxo + c.py * c.py);
+      double Pxi = c.px + p.A_in, Pyi = c.py + p.Ay_in;
+      double Pxo = p.vsign * (c.px + p.A_out), Pyo = p.vsign * (c.py + p.Ay_out);
+      double Ei = sqrt(Pxi * Pxi + Pyi * Pyi), Eo = sqrt(Pxo * Pxo + Pyo * Pyo);
       double A1 = a1[q], B1 = b1[q], A2 = a2[q], B2 = b2[q];
       double n = 0.0;
       if (Ei > 0.0 && Eo > 0.0) {
-        // u_out = (E, Px + i py) / (sqrt(2) E):  sqrt(2) E amp = (E a1 + Px a2 + py b2) + i (E b1 + Px b2 - py a2)
-        double re = (Eo * A1 + Pxo * A2) + c.py * B2;
-        double im = (Eo * B1 + Pxo * B2) - c.py * A2;
+        // u_out = (E, Px + i Py) / (sqrt(2) E):  sqrt(2) E amp = (E a1 + Px a2 + Py b2) + i (E b1 + Px b2 - Py a2)
+        double re = (Eo * A1 + Pxo * A2) + Pyo * B2;
+        double im = (Eo * B1 + Pxo * B2) - Pyo * A2;
         n = (re * re + im * im) / (2.0 * Eo * Eo);
         if (sizeof(R) == 4) n = n / (A1 * A1 + B1 * B1 + A2 * A2 + B2 * B2);
       }
@@ -474,6 +555,84 @@ __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Snapshots: the state after k steps (in the state buffer, or v_in at k = 0)
+// projected on the positive-energy state of sigma.(p + A(t_k)).
+
+template <typename R, int POL>
+__global__ void __launch_bounds__(256) strang_snapshot_kernel(const SolveParams p, const SnapshotParams s,
+                                                              int half_offset, int row_stride) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= p.npts) return;
+  PointCoords c = coords(p, idx);
+  double Pxi = c.px + p.A_in, Pyi = c.py + p.Ay_in;
+  double Px = c.px + s.Ax, Py = c.py + s.Ay;
+  double Ei = sqrt(Pxi * Pxi + Pyi * Pyi), E = sqrt(Px * Px + Py * Py);
+  double n = 0.0;
+  if (Ei > 0.0 && E > 0.0) {
+    double X, Y, Z;
+    if (p.load_state) {
+      const R* st = static_cast<const R*>(p.state);
+      R x = st[idx], y = st[p.npts + idx], z = st[2 * p.npts + idx];
+      // the stored state is ahead by the opening half step of step k: undo it
+      // (field part first, then the per-point part, each by its inverse rotation)
+      const R* rowc = static_cast<const R*>(p.row_coef);
+      R ha = rowc[(size_t)row_stride * c.j + half_offset], hs = rowc[(size_t)row_stride * c.j + half_offset + 1];
+      if (POL) {
+        if (p.form == kFormShear)
+          rotate_shear(z, x, (R)s.undo_a, (R)s.undo_s);
+        else
+          rotate_versine(z, x, (R)s.undo_a, (R)s.undo_s);
+      }
+      if (p.form == kFormShear)
+        rotate_shear(z, x, -ha, -hs);
+      else
+        rotate_versine(z, x, ha, -hs);
+      X = x;
+      Y = y;
+      Z = z;
+    } else {
+      X = -p.vsign * Pxi / Ei;
+      Y = -p.vsign * Pyi / Ei;
+      Z = 0.0;
+    }
+    double nr = sqrt(X * X + Y * Y + Z * Z);
+    if (nr > 0.0) n = (E + p.vsign * (Px * X + Py * Y) / nr) / (2.0 * E);
+  }
+  p.n_out[idx] = n;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) midpoint_snapshot_kernel(const SolveParams p, const SnapshotParams s) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= p.npts) return;
+  PointCoords c = coords(p, idx);
+  double Pxi = p.vsign * (c.px + p.A_in), Pyi = p.vsign * (c.py + p.Ay_in);
+  double Px = p.vsign * (c.px + s.Ax), Py = p.vsign * (c.py + s.Ay);
+  double Ei = sqrt(Pxi * Pxi + Pyi * Pyi), E = sqrt(Px * Px + Py * Py);
+  double n = 0.0;
+  if (Ei > 0.0 && E > 0.0) {
+    double A1, B1, A2, B2;
+    if (p.load_state) {
+      const R* st = static_cast<const R*>(p.state);
+      A1 = st[idx];
+      B1 = st[p.npts + idx];
+      A2 = st[2 * p.npts + idx];
+      B2 = st[3 * p.npts + idx];
+    } else {
+      double d = 1.4142135623730951 * Ei;
+      A1 = -Pxi / d;
+      B1 = Pyi / d;
+      A2 = Ei / d;
+      B2 = 0.0;
+    }
+    double re = (E * A1 + Px * A2) + Py * B2;
+    double im = (E * B1 + Px * B2) - Py * A2;
+    n = (re * re + im * im) / (2.0 * E * E) / (A1 * A1 + B1 * B1 + A2 * A2 + B2 * B2);
+  }
+  p.n_out[idx] = n;
 }
 
 // ---------------------------------------------------------------------------
@@ -556,72 +715,117 @@ __global__ void __launch_bounds__(kRedThreads) batch_density_finish(const Densit
   }
 }
 
-template <typename R, int PPL, int FORM>
+template <typename R, int PPL, int FORM, int NS, int POL>
 hipError_t launch_strang(int block, const SolveParams& p, hipStream_t stream) {
   long long per_block = (long long)block * PPL;
   long long blocks = (p.npts + per_block - 1) / per_block;
   if (p.stage == 1) {
-    size_t lds = (size_t)p.chunk_steps * sizeof(Row<R>);
-    hipLaunchKernelGGL((strang_kernel<R, PPL, 1, FORM>), dim3((unsigned)blocks), dim3(block), lds, stream, p);
+    size_t lds = (size_t)p.chunk_steps * BlochLanes<R, PPL, FORM, NS, POL>::kRow * sizeof(R);
+    hipLaunchKernelGGL((strang_kernel<R, PPL, 1, FORM, NS, POL>), dim3((unsigned)blocks), dim3(block), lds, stream,
+                       p);
   } else {
-    hipLaunchKernelGGL((strang_kernel<R, PPL, 0, FORM>), dim3((unsigned)blocks), dim3(block), 0, stream, p);
+    hipLaunchKernelGGL((strang_kernel<R, PPL, 0, FORM, NS, POL>), dim3((unsigned)blocks), dim3(block), 0, stream, p);
   }
   return hipGetLastError();
+}
+
+template <typename R, int FORM, int NS, int POL>
+hipError_t strang_ppl(int ppl, int block, const SolveParams& p, hipStream_t stream) {
+  switch (ppl) {
+    case 1: return launch_strang<R, 1, FORM, NS, POL>(block, p, stream);
+    case 2: return launch_strang<R, 2, FORM, NS, POL>(block, p, stream);
+    default: return launch_strang<R, 4, FORM, NS, POL>(block, p, stream);
+  }
 }
 
 template <typename R, int FORM>
-hipError_t strang_ppl(int ppl, int block, const SolveParams& p, hipStream_t stream) {
-  switch (ppl) {
-    case 1: return launch_strang<R, 1, FORM>(block, p, stream);
-    case 2: return launch_strang<R, 2, FORM>(block, p, stream);
-    default: return launch_strang<R, 4, FORM>(block, p, stream);
-  }
+hipError_t strang_variant(int stages, int elliptic, int ppl, int block, const SolveParams& p, hipStream_t stream) {
+  if (stages == 5)
+    return elliptic ? strang_ppl<R, FORM, 5, 1>(ppl, block, p, stream) : strang_ppl<R, FORM, 5, 0>(ppl, block, p, stream);
+  return elliptic ? strang_ppl<R, FORM, 1, 1>(ppl, block, p, stream) : strang_ppl<R, FORM, 1, 0>(ppl, block, p, stream);
 }
 
-template <typename R, int J, int PPL>
+template <typename R, int J, int PPL, int NS, int POL>
 hipError_t launch_midpoint(int block, const SolveParams& p, hipStream_t stream) {
   long long per_block = (long long)block * PPL;
   long long blocks = (p.npts + per_block - 1) / per_block;
-  hipLaunchKernelGGL((midpoint_kernel<R, J, PPL>), dim3((unsigned)blocks), dim3(block), 0, stream, p);
+  hipLaunchKernelGGL((midpoint_kernel<R, J, PPL, NS, POL>), dim3((unsigned)blocks), dim3(block), 0, stream, p);
   return hipGetLastError();
 }
 
-template <typename R, int J>
+template <typename R, int J, int NS, int POL>
 hipError_t midpoint_ppl(int ppl, int block, const SolveParams& p, hipStream_t stream) {
   switch (ppl) {
-    case 1: return launch_midpoint<R, J, 1>(block, p, stream);
-    case 2: return launch_midpoint<R, J, 2>(block, p, stream);
-    default: return launch_midpoint<R, J, 4>(block, p, stream);
+    case 1: return launch_midpoint<R, J, 1, NS, POL>(block, p, stream);
+    case 2: return launch_midpoint<R, J, 2, NS, POL>(block, p, stream);
+    default: return launch_midpoint<R, J, 4, NS, POL>(block, p, stream);
   }
+}
+
+template <typename R, int J>
+hipError_t midpoint_variant(int stages, int elliptic, int ppl, int block, const SolveParams& p, hipStream_t stream) {
+  if (stages == 5)
+    return elliptic ? midpoint_ppl<R, J, 5, 1>(ppl, block, p, stream) : midpoint_ppl<R, J, 5, 0>(ppl, block, p, stream);
+  return elliptic ? midpoint_ppl<R, J, 1, 1>(ppl, block, p, stream) : midpoint_ppl<R, J, 1, 0>(ppl, block, p, stream);
 }
 
 }  // namespace
 
-size_t state_values_per_point(int scheme) { return scheme == PD_SCHEME_MIDPOINT ? 4 : 3; }
+size_t state_values_per_point(int scheme) { return base_scheme(scheme) == PD_SCHEME_MIDPOINT ? 4 : 3; }
 
 long long density_partials(long long npts) { return (npts + kRedTile - 1) / kRedTile; }
 
-hipError_t launch_propagate(int scheme, int precision, int ppl, int block, int taylor, const SolveParams& p,
-                            hipStream_t stream) {
-  if (scheme == PD_SCHEME_STRANG) {
+hipError_t launch_propagate(int scheme, int precision, int ppl, int block, int taylor, int elliptic,
+                            const SolveParams& p, hipStream_t stream) {
+  const int S = (scheme == PD_SCHEME_STRANG4 || scheme == PD_SCHEME_MIDPOINT4) ? 5 : 1;
+  if (base_scheme(scheme) == PD_SCHEME_STRANG) {
     if (precision == PD_FP32)
-      return p.form == kFormShear ? strang_ppl<float, kFormShear>(ppl, block, p, stream)
-                                  : strang_ppl<float, kFormVersine>(ppl, block, p, stream);
-    return p.form == kFormShear ? strang_ppl<double, kFormShear>(ppl, block, p, stream)
-                                : strang_ppl<double, kFormVersine>(ppl, block, p, stream);
+      return p.form == kFormShear ? strang_variant<float, kFormShear>(S, elliptic, ppl, block, p, stream)
+                                  : strang_variant<float, kFormVersine>(S, elliptic, ppl, block, p, stream);
+    return p.form == kFormShear ? strang_variant<double, kFormShear>(S, elliptic, ppl, block, p, stream)
+                                : strang_variant<double, kFormVersine>(S, elliptic, ppl, block, p, stream);
   }
   if (precision == PD_FP32) {
     switch (taylor) {
-      case 3: return midpoint_ppl<float, 3>(ppl, block, p, stream);
-      case 5: return midpoint_ppl<float, 5>(ppl, block, p, stream);
-      default: return midpoint_ppl<float, 9>(ppl, block, p, stream);
+      case 3: return midpoint_variant<float, 3>(S, elliptic, ppl, block, p, stream);
+      case 5: return midpoint_variant<float, 5>(S, elliptic, ppl, block, p, stream);
+      default: return midpoint_variant<float, 9>(S, elliptic, ppl, block, p, stream);
     }
   }
   switch (taylor) {
-    case 5: return midpoint_ppl<double, 5>(ppl, block, p, stream);
-    case 8: return midpoint_ppl<double, 8>(ppl, block, p, stream);
-    default: return midpoint_ppl<double, 14>(ppl, block, p, stream);
+    case 5: return midpoint_variant<double, 5>(S, elliptic, ppl, block, p, stream);
+    case 8: return midpoint_variant<double, 8>(S, elliptic, ppl, block, p, stream);
+    default: return midpoint_variant<double, 14>(S, elliptic, ppl, block, p, stream);
   }
+}
+
+hipError_t launch_snapshot(int scheme, int precision, int elliptic, const SolveParams& p, const SnapshotParams& q,
+                           hipStream_t stream) {
+  const long long blocks = (p.npts + 255) / 256;
+  if (base_scheme(scheme) == PD_SCHEME_STRANG) {
+    const bool four = scheme == PD_SCHEME_STRANG4;
+    const int row_stride = four ? 6 : 4, half_offset = four ? 4 : 2;
+    if (precision == PD_FP32) {
+      if (elliptic)
+        hipLaunchKernelGGL((strang_snapshot_kernel<float, 1>), dim3((unsigned)blocks), dim3(256), 0, stream, p, q,
+                           half_offset, row_stride);
+      else
+        hipLaunchKernelGGL((strang_snapshot_kernel<float, 0>), dim3((unsigned)blocks), dim3(256), 0, stream, p, q,
+                           half_offset, row_stride);
+    } else {
+      if (elliptic)
+        hipLaunchKernelGGL((strang_snapshot_kernel<double, 1>), dim3((unsigned)blocks), dim3(256), 0, stream, p, q,
+                           half_offset, row_stride);
+      else
+        hipLaunchKernelGGL((strang_snapshot_kernel<double, 0>), dim3((unsigned)blocks), dim3(256), 0, stream, p, q,
+                           half_offset, row_stride);
+    }
+  } else if (precision == PD_FP32) {
+    hipLaunchKernelGGL((midpoint_snapshot_kernel<float>), dim3((unsigned)blocks), dim3(256), 0, stream, p, q);
+  } else {
+    hipLaunchKernelGGL((midpoint_snapshot_kernel<double>), dim3((unsigned)blocks), dim3(256), 0, stream, p, q);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_density(const double* n, long long npts, double scale, double* partial, double* rho,

@@ -56,7 +56,12 @@ pd_status grid_state_buffer(pd_grid g, void** out) {
 
 }  // namespace pdx
 
-double pd_grid_s::density_scale() const { return 4.0 * grid.dx * grid.dy / (4.0 * kPi * kPi); }
+// rho = g dx dy / (2 pi)^2 sum n: g = 4 (2 spins x 2 valleys, the K- valley giving
+// the same n as K+) unless one valley is solved explicitly (g = 2, spins only).
+double pd_grid_s::density_scale() const {
+  const double g = valley == PD_VALLEYS_BOTH ? 4.0 : 2.0;
+  return g * grid.dx * grid.dy / (4.0 * kPi * kPi);
+}
 
 SolveParams pd_grid_s::solve_params(long long k_begin, long long k_end, void* state) const {
   SolveParams p{};
@@ -69,6 +74,12 @@ SolveParams pd_grid_s::solve_params(long long k_begin, long long k_end, void* st
   p.A_in = field.A_in;
   p.A_out = field.A_out;
   p.dt = field.dt;
+  p.Ay_in = field.Ay_in;
+  p.Ay_out = field.Ay_out;
+  p.vsign = vsign();
+  // midpoint: per-point phase multipliers vsign c dt of the distinct stage coefficients
+  p.hx[0] = vsign() * (field.comp.c[0] * field.dt);
+  p.hx[1] = vsign() * (field.comp.c[2] * field.dt);
   p.n_steps = field.n_steps;
   p.k_begin = k_begin;
   p.k_end = k_end;
@@ -79,7 +90,9 @@ SolveParams pd_grid_s::solve_params(long long k_begin, long long k_end, void* st
   p.load_state = k_begin > 0;
   p.store_state = k_end < field.n_steps;
   p.state = (p.load_state || p.store_state) ? state : nullptr;
-  p.stage = table_stage == 1 ? 1 : 0;
+  // LDS staging holds chunk_steps rows in at most 64 KiB; larger rows use the scalar path
+  const size_t row_bytes = table_row_bytes(scheme, precision, field.elliptic ? 1 : 0);
+  p.stage = (table_stage == 1 && (size_t)chunk_steps * row_bytes <= 65536) ? 1 : 0;
   p.chunk_steps = chunk_steps;
   p.form = form;
   return p;
@@ -112,16 +125,16 @@ pd_status prepare_field(pd_grid g, const pd_field* f, long long n_steps, FieldTa
   if (!g) return fail(PD_ERR_INVALID, "null handle");
   if (!f) return fail(PD_ERR_INVALID, "null field");
   std::string err;
-  if (!sample_field(*f, n_steps, t, &err)) return fail(PD_ERR_INVALID, "%s", err.c_str());
+  if (!sample_field(*f, n_steps, composition_of(g->scheme), t, &err)) return fail(PD_ERR_INVALID, "%s", err.c_str());
   field_extent(g->grid, t);
   // Step-size condition of Sec. III (last paragraph): dt <= pi / max E.
   if (t->dt * t->E_max > kPi)
     return fail(PD_ERR_INVALID, "dt * E_max = %.6g exceeds pi (dt = %.6g, E_max = %.6g): use more steps",
                 t->dt * t->E_max, t->dt, t->E_max);
-  *masked = count_masked(g->grid, t->A_in, t->A_out);
+  *masked = count_masked(g->grid, *t);
   *taylor = 0;
-  if (g->scheme == PD_SCHEME_MIDPOINT) {
-    double xm = t->dt * t->E_max;
+  if (base_scheme(g->scheme) == PD_SCHEME_MIDPOINT) {
+    double xm = t->comp.cmax * t->dt * t->E_max;  // largest stage phase
     *taylor = taylor_order(xm * xm, g->precision);
     if (*taylor < 0) return fail(PD_ERR_UNSUPPORTED, "midpoint step too large for the compiled Taylor orders");
   }
@@ -149,12 +162,17 @@ void fill_info(pd_grid g, const FieldTables& t, long long masked, long long step
   out->table_stage = g->table_stage;
   out->chunk_steps = g->chunk_steps;
   out->rotation_form = t.n_steps > 0 ? strang_form(g->grid, t) : kFormShear;
-  if (g->scheme == PD_SCHEME_MIDPOINT && t.n_steps > 0) {
-    double xm = t.dt * t.E_max;
+  if (base_scheme(g->scheme) == PD_SCHEME_MIDPOINT && t.n_steps > 0) {
+    double xm = t.comp.cmax * t.dt * t.E_max;
     out->taylor_order = taylor_order(xm * xm, g->precision);
   }
   out->device_bytes = g->device_bytes();
   if (t.n_steps > 0) out->solve_bytes = pd_solve_bytes(g, t.n_steps);
+  out->valley = g->valley;
+  out->stages = composition_of(g->scheme).stages;
+  out->elliptic = t.elliptic ? 1 : 0;
+  out->Ay_in = t.Ay_in;
+  out->Ay_out = t.Ay_out;
 }
 
 }  // namespace
@@ -174,7 +192,8 @@ pd_status pd_create_grid(int nx, int ny, double px_min, double px_max, double py
       !(px_max > px_min) || !(py_max > py_min))
     return fail(PD_ERR_INVALID, "momentum ranges must be finite with max > min");
   if (precision != PD_FP64 && precision != PD_FP32) return fail(PD_ERR_INVALID, "unknown precision %d", precision);
-  if (scheme != PD_SCHEME_STRANG && scheme != PD_SCHEME_MIDPOINT)
+  if (scheme != PD_SCHEME_STRANG && scheme != PD_SCHEME_MIDPOINT && scheme != PD_SCHEME_STRANG4 &&
+      scheme != PD_SCHEME_MIDPOINT4)
     return fail(PD_ERR_INVALID, "unknown scheme %d", scheme);
   pd_grid g = new (std::nothrow) pd_grid_s();
   if (!g) return fail(PD_ERR_NOMEM, "host allocation failed");
@@ -213,12 +232,48 @@ pd_status pd_sample_field(const pd_field* f, long long n_steps, double* A_mid, d
   if (!f) return fail(PD_ERR_INVALID, "null field");
   FieldTables t;
   std::string err;
-  if (!sample_field(*f, n_steps, &t, &err)) return fail(PD_ERR_INVALID, "%s", err.c_str());
+  if (!sample_field(*f, n_steps, composition_of(PD_SCHEME_STRANG), &t, &err))
+    return fail(PD_ERR_INVALID, "%s", err.c_str());
   if (A_mid) std::memcpy(A_mid, t.A_mid.data(), (size_t)n_steps * sizeof(double));
   if (t_i) *t_i = t.t_i;
   if (t_f) *t_f = t.t_f;
   if (A_in) *A_in = t.A_in;
   if (A_out) *A_out = t.A_out;
+  return ok();
+}
+
+pd_status pd_sample_field_xy(const pd_field* f, long long n_steps, int scheme, double* Ax_mid, double* Ay_mid,
+                             double* ends) {
+  if (!f) return fail(PD_ERR_INVALID, "null field");
+  if (scheme < PD_SCHEME_STRANG || scheme > PD_SCHEME_MIDPOINT4) return fail(PD_ERR_INVALID, "unknown scheme %d", scheme);
+  FieldTables t;
+  std::string err;
+  if (!sample_field(*f, n_steps, composition_of(scheme), &t, &err)) return fail(PD_ERR_INVALID, "%s", err.c_str());
+  const size_t n = t.A_mid.size();
+  if (Ax_mid) std::memcpy(Ax_mid, t.A_mid.data(), n * sizeof(double));
+  if (Ay_mid) {
+    if (t.elliptic)
+      std::memcpy(Ay_mid, t.Ay_mid.data(), n * sizeof(double));
+    else
+      std::memset(Ay_mid, 0, n * sizeof(double));
+  }
+  if (ends) {
+    ends[0] = t.t_i;
+    ends[1] = t.t_f;
+    ends[2] = t.A_in;
+    ends[3] = t.A_out;
+    ends[4] = t.Ay_in;
+    ends[5] = t.Ay_out;
+  }
+  return ok();
+}
+
+pd_status pd_set_valley(pd_grid g, int valley) {
+  if (!g) return fail(PD_ERR_INVALID, "null handle");
+  if (valley != PD_VALLEYS_BOTH && valley != PD_VALLEY_KPLUS && valley != PD_VALLEY_KMINUS)
+    return fail(PD_ERR_INVALID, "unknown valley %d", valley);
+  if (g->field_set) return fail(PD_ERR_STATE, "pd_set_valley after pd_set_field");
+  g->valley = valley;
   return ok();
 }
 
@@ -230,10 +285,10 @@ pd_status pd_set_field(pd_grid g, const pd_field* f, long long n_steps) {
   if (s != PD_OK) return s;
   std::vector<unsigned char> rows;
   const int form = strang_form(g->grid, t);
-  build_step_table(t, g->scheme, g->precision, form, &rows);
+  build_step_table(t, g->scheme, g->precision, form, g->vsign(), &rows);
   size_t col_offset = 0, row_offset = 0;
-  if (g->scheme == PD_SCHEME_STRANG)
-    build_point_coefficients(g->grid, t.dt, g->precision, form, &rows, &col_offset, &row_offset);
+  if (base_scheme(g->scheme) == PD_SCHEME_STRANG)
+    build_point_coefficients(g->grid, t, g->scheme, g->precision, form, g->vsign(), &rows, &col_offset, &row_offset);
 
   if (g->device < 0) {
     int dev = -1;
@@ -287,12 +342,12 @@ size_t pd_state_bytes(pd_grid g) { return g ? g->state_bytes() : 0; }
 size_t pd_solve_bytes(pd_grid g, long long n_steps) {
   if (!g || n_steps < 1) return 0;
   auto align = [](size_t n) { return (n + 255) / 256 * 256; };
-  size_t table = (size_t)n_steps * table_row_bytes(g->scheme, g->precision);
-  if (g->scheme == PD_SCHEME_STRANG) {
+  size_t table = (size_t)table_rows(g->scheme, 0, n_steps) * table_row_bytes(g->scheme, g->precision, 0);
+  if (base_scheme(g->scheme) == PD_SCHEME_STRANG) {
     const size_t v = g->precision == PD_FP32 ? sizeof(float) : sizeof(double);
     size_t col = align(table);
-    size_t row = align(col + 2 * v * (size_t)g->grid.nx);
-    table = align(row + 4 * v * (size_t)g->grid.ny);
+    size_t row = align(col + 2 * point_coefficient_pairs_x(g->scheme) * v * (size_t)g->grid.nx);
+    table = align(row + 2 * point_coefficient_pairs_y(g->scheme) * v * (size_t)g->grid.ny);
   }
   const size_t npts = (size_t)g->grid.points();
   return table + npts * sizeof(double) + (size_t)density_partials((long long)npts) * sizeof(double) +
@@ -360,21 +415,17 @@ pd_status pd_propagate(pd_grid g, long long max_steps, void* stream) {
     if (s != PD_OK) return s;
   }
   const SolveParams p = g->solve_params(k_begin, k_end, st);
-  hipError_t e = launch_propagate(g->scheme, g->precision, g->points_per_lane, g->block_threads, g->taylor, p,
-                                  static_cast<hipStream_t>(stream));
+  hipError_t e = launch_propagate(g->scheme, g->precision, g->points_per_lane, g->block_threads, g->taylor,
+                                  g->field.elliptic ? 1 : 0, p, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "propagate launch");
   g->steps_done = p.k_end;
   return ok();
 }
 
-pd_status pd_density(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, void* stream) {
-  if (!g) return fail(PD_ERR_INVALID, "null handle");
-  if (!g->field_set || g->steps_done != g->field.n_steps)
-    return fail(PD_ERR_STATE, "pd_density before the last step (%lld of %lld done)", g->steps_done,
-                g->field_set ? g->field.n_steps : 0LL);
-  DeviceScope scope(g->device);
-  if (!scope.ok) return fail(PD_ERR_DEVICE, "cannot select device %d", g->device);
-  hipStream_t s = static_cast<hipStream_t>(stream);
+namespace {
+
+// Reduce the handle's n buffer into rho and copy the results out (pd_density, pd_snapshot).
+pd_status reduce_and_copy(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, hipStream_t s) {
   const long long npts = g->grid.points();
   hipError_t e = launch_density(g->d_n, npts, g->density_scale(), g->d_partial, g->d_rho, s);
   if (e != hipSuccess) return hip_fail(e, "density launch");
@@ -397,6 +448,49 @@ pd_status pd_density(pd_grid g, double* n_out, int n_out_on_device, double* rho_
   }
   if (rho_out) *rho_out = rho;
   return ok();
+}
+
+}  // namespace
+
+pd_status pd_density(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, void* stream) {
+  if (!g) return fail(PD_ERR_INVALID, "null handle");
+  if (!g->field_set || g->steps_done != g->field.n_steps)
+    return fail(PD_ERR_STATE, "pd_density before the last step (%lld of %lld done)", g->steps_done,
+                g->field_set ? g->field.n_steps : 0LL);
+  DeviceScope scope(g->device);
+  if (!scope.ok) return fail(PD_ERR_DEVICE, "cannot select device %d", g->device);
+  return reduce_and_copy(g, n_out, n_out_on_device, rho_out, static_cast<hipStream_t>(stream));
+}
+
+pd_status pd_snapshot(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, void* stream) {
+  if (!g) return fail(PD_ERR_INVALID, "null handle");
+  if (!g->field_set) return fail(PD_ERR_STATE, "pd_snapshot before pd_set_field");
+  DeviceScope scope(g->device);
+  if (!scope.ok) return fail(PD_ERR_DEVICE, "cannot select device %d", g->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long k = g->steps_done, N = g->field.n_steps;
+  if (k < N) {
+    // k = 0: v_in is rebuilt in the kernel; 0 < k < N: the state buffer holds step k
+    void* st = nullptr;
+    if (k > 0) {
+      pd_status r = grid_state_buffer(g, &st);
+      if (r != PD_OK) return r;
+    }
+    SolveParams p = g->solve_params(k, k, st);
+    p.load_state = k > 0;
+    SnapshotParams q{};
+    boundary_A(g->field, k, &q.Ax, &q.Ay);
+    if (base_scheme(g->scheme) == PD_SCHEME_STRANG && g->field.elliptic && k > 0) {
+      // the stored Bloch vector is ahead by the opening half step of step k; its
+      // field part has half angle vsign c_1 dt A_y(k, stage 0) / 2
+      const int S = g->field.comp.stages;
+      double half = g->vsign() * 0.5 * g->field.dt * (g->field.comp.c[0] * g->field.Ay_mid[(size_t)(k * S)]);
+      rotation_coefficients(-half, g->form, &q.undo_a, &q.undo_s);
+    }
+    hipError_t e = launch_snapshot(g->scheme, g->precision, g->field.elliptic ? 1 : 0, p, q, s);
+    if (e != hipSuccess) return hip_fail(e, "snapshot launch");
+  }
+  return reduce_and_copy(g, n_out, n_out_on_device, rho_out, s);
 }
 
 pd_status pd_get_info(pd_grid g, pd_info* out) {

@@ -10,13 +10,31 @@
 
 namespace pdx {
 
+// Stages of a step: 1 for the second-order schemes, 5 for Suzuki's fourth-order
+// composition S(c1 dt) ... S(c5 dt), c = (p, p, 1 - 4p, p, p), p = 1/(4 - 4^(1/3));
+// stage j samples the field at t_i + (k + sigma[j]) dt.
+struct Composition {
+  int stages = 1;
+  double c[5] = {1, 0, 0, 0, 0};
+  double sigma[5] = {0.5, 0, 0, 0, 0};
+  double cmax = 1;  // max |c_j|
+};
+Composition composition_of(int scheme);
+// PD_SCHEME_STRANG / STRANG4 -> PD_SCHEME_STRANG, MIDPOINT / MIDPOINT4 -> PD_SCHEME_MIDPOINT
+inline int base_scheme(int scheme) { return scheme == PD_SCHEME_MIDPOINT || scheme == PD_SCHEME_MIDPOINT4 ? PD_SCHEME_MIDPOINT : PD_SCHEME_STRANG; }
+
 // Host-side description of a field sampled for one solve.
 struct FieldTables {
   double t_i = 0, t_f = 0, dt = 0;
-  double A_in = 0, A_out = 0, A_min = 0, A_max = 0;
+  double A_in = 0, A_out = 0, A_min = 0, A_max = 0;      // x component
+  double Ay_in = 0, Ay_out = 0, Ay_min = 0, Ay_max = 0;  // y component (0 when linear)
+  bool elliptic = false;
   double E_max = 0;
   long long n_steps = 0;
-  std::vector<double> A_mid;  // A(t_i + (k + 1/2) dt), k < n_steps
+  Composition comp;
+  std::vector<double> A_mid;   // A_x at t_i + (k + sigma_j) dt, index k * stages + j
+  std::vector<double> Ay_mid;  // A_y at the same times (empty when linear)
+  pd_field spec{};             // the description (array pointers cleared), for A at other times
 };
 
 struct Grid {
@@ -30,25 +48,41 @@ struct Grid {
 };
 
 // field.cpp
-bool sample_field(const pd_field& f, long long n_steps, FieldTables* out, std::string* err);
-void field_extent(const Grid& g, FieldTables* t);      // E_max over the grid
-long long count_masked(const Grid& g, double A_in, double A_out);
+bool sample_field(const pd_field& f, long long n_steps, const Composition& comp, FieldTables* out,
+                  std::string* err);
+void field_extent(const Grid& g, FieldTables* t);  // E_max over the grid
+long long count_masked(const Grid& g, const FieldTables& t);
+// (A_x, A_y) at the step boundary t_i + k dt (k = 0: the start values, k = N: the
+// end values; a table field between two steps: mean of the neighbouring samples).
+void boundary_A(const FieldTables& t, long long k, double* ax, double* ay);
 
-// Per-step rows of the field table, as the kernels read them.
-//   Strang: the two coefficients of the rotation by 2 dt A_k about x in the
-//           solve's rotation form, FP64 (16 bytes) or rounded to FP32 (8 bytes)
-//   Midpoint: dt * A_k in FP64, 8 bytes
-size_t table_row_bytes(int scheme, int precision);
-void build_step_table(const FieldTables& t, int scheme, int precision, int form, std::vector<unsigned char>* rows);
+// Per-step rows of the field table, as the kernels read them (`stages` S).
+//   Strang: per stage the two coefficients of the x rotation by 2 c_j dt A_x;
+//           with a y component, then per stage the two coefficients of the y
+//           rotation that follows it (its field part); in the solve's rotation
+//           form, FP64 or rounded to FP32.  With a y component one more row
+//           holds (in its first y slot) the opening half step's field part.
+//   Midpoint: per stage c_j dt A_x, then (y component) per stage c_j dt A_y, FP64.
+// All angles carry the valley sign.
+size_t table_row_values(int scheme, int elliptic);
+size_t table_row_bytes(int scheme, int precision, int elliptic);
+long long table_rows(int scheme, int elliptic, long long n_steps);
+void build_step_table(const FieldTables& t, int scheme, int precision, int form, double vsign,
+                      std::vector<unsigned char>* rows);
 // Rotation form of a Strang solve: shears when every rotation angle is small enough.
 int strang_form(const Grid& g, const FieldTables& t);
 // Per-point rotation coefficients of a Strang solve, which depend on one grid
-// coordinate each: per column i the rotation by 2 dt px_i about x (2 values),
-// per row j the rotations by 2 dt py_j and by dt py_j about y (4 values), in the
-// solve's form and precision, appended to `bytes` (each block 256-byte aligned).
-// Returns the byte offsets of the column and row blocks.
-void build_point_coefficients(const Grid& g, double dt, int precision, int form, std::vector<unsigned char>* bytes,
-                              size_t* col_offset, size_t* row_offset);
+// coordinate each: per column i the x rotations by 2 c dt px_i for each distinct
+// stage coefficient (1 pair, or 2 for the fourth-order composition), per row j
+// the y rotations that follow the stages (1 or 2 pairs) and the opening / closing
+// half step (1 pair), in the solve's form and precision, appended to `bytes`
+// (each block 256-byte aligned).  Returns the byte offsets of the two blocks.
+void build_point_coefficients(const Grid& g, const FieldTables& t, int scheme, int precision, int form, double vsign,
+                              std::vector<unsigned char>* bytes, size_t* col_offset, size_t* row_offset);
+size_t point_coefficient_pairs_x(int scheme);
+size_t point_coefficient_pairs_y(int scheme);  // including the half step
+// Coefficients (a, s) of the rotation by phi = 2 * half in a rotation form.
+void rotation_coefficients(double half, int form, double* a, double* s);
 
 // Smallest Taylor order (terms of cos - 1 and of sin(x)/x in x = (dt E)^2) whose
 // truncation stays below the precision's rounding for x <= x_max.
@@ -66,6 +100,9 @@ struct SolveParams {
   int nx;
   double px_min, dx, py_min, dy;
   double A_in, A_out, dt;
+  double Ay_in, Ay_out;
+  double vsign;      // +1: valley K+, -1: K- (H = -sigma.P)
+  double hx[2];      // midpoint: vsign * c dt for the distinct stage coefficients
   long long n_steps, k_begin, k_end;
   const void* table;
   const void* col_coef;  // Strang: per column (a, s) of the rotation by 2 dt px about x
@@ -77,6 +114,14 @@ struct SolveParams {
   int stage;         // Strang table path: 0 scalar-unit loads, 1 LDS chunks
   int form;          // Strang rotation form: kFormShear or kFormVersine
   long long chunk_steps;  // LDS chunk length in steps (power of two; divides 1024 in FP32)
+};
+
+// Projection of a stored state at step k on the positive-energy state of
+// sigma.(p + A(t_k)) (pd_snapshot).
+struct SnapshotParams {
+  double Ax, Ay;        // A(t_k)
+  double undo_a, undo_s;  // Strang with a y component: the inverse of the field part of
+                          // the half step the stored state is ahead by
 };
 
 // One solve of a batched launch (device descriptor).
@@ -108,7 +153,9 @@ struct DensityJob {
 
 // kernels.hip
 hipError_t launch_propagate(int scheme, int precision, int points_per_lane, int block_threads, int taylor,
-                            const SolveParams& p, hipStream_t stream);
+                            int elliptic, const SolveParams& p, hipStream_t stream);
+hipError_t launch_snapshot(int scheme, int precision, int elliptic, const SolveParams& p, const SnapshotParams& q,
+                           hipStream_t stream);
 hipError_t launch_density(const double* n, long long npts, double scale, double* partial, double* rho,
                           hipStream_t stream);
 hipError_t launch_batch(int points_per_lane, int block_threads, int grid_blocks, const BatchSolve* solves,
@@ -137,6 +184,8 @@ struct pd_grid_s {
   long long steps_done = 0;
   int taylor = 0;
   int form = pdx::kFormShear;  // Strang rotation form of the current field
+  int valley = PD_VALLEYS_BOTH;
+  double vsign() const { return valley == PD_VALLEY_KMINUS ? -1.0 : 1.0; }
 
   int device = -1;
   void* d_table = nullptr;

@@ -197,3 +197,101 @@ def test_state_bytes():
     s = pd.Solver(10, 7, (-1, 1), (-1, 1), "fp32", "midpoint")
     assert s.state_bytes() == 70 * 4 * 4
     s.close()
+
+
+# ---------------------------------------------------------------------------
+# Fourth-order composition, y component of the field, valley (host side)
+
+ELLIPTIC_FIELDS = {
+    "sin2": (wl.sin2(0.16772546041219238, 0.25, 20, 0.7), 4000),
+    "constant": (wl.constant(0.2, 200.0, -0.5), 4000),
+    "pulse": ({"kind": "pulse", "E0": 1.0, "omega": 0.4876, "phi": 0.7, "omega_rise": 0.0609,
+               "omega_fall": 0.0609, "duration": 70.9, "ellipticity": 0.8}, 3000),
+}
+
+
+@pytest.mark.parametrize("scheme", ["strang", "strang4", "midpoint4"])
+@pytest.mark.parametrize("kind", sorted(ELLIPTIC_FIELDS))
+def test_field_sampling_xy_matches_oracle(kind, scheme):
+    """Both components at every stage sample time equal the oracle's (independent code)."""
+    f, N = ELLIPTIC_FIELDS[kind]
+    Ax, Ay, ends = _lib.sample_field_xy(f, N, scheme)
+    Ao, ax_in, ax_out, dt_o = oracle.field_table(f, N, scheme)
+    Ayo, ay_in, ay_out = oracle.field_table_y(f, N, scheme)
+    assert Ax.shape == Ao.shape == Ay.shape == Ayo.shape == (N * _lib.STAGES[scheme],)
+    scale = max(1.0, np.abs(Ao).max(), np.abs(Ayo).max())
+    assert np.max(np.abs(Ax - Ao)) <= 4e-15 * scale
+    assert np.max(np.abs(Ay - Ayo)) <= 4e-15 * scale
+    assert np.max(np.abs(Ay)) > 0.01  # the y component is there
+    t_i, t_f, a_in, a_out, b_in, b_out = ends
+    assert abs(a_in - ax_in) <= 1e-16 and abs(a_out - ax_out) <= 1e-14 * scale
+    assert abs(b_in - ay_in) <= 1e-16 and abs(b_out - ay_out) <= 1e-14 * scale
+
+
+def test_check_field_fourth_order_and_elliptic():
+    """info reports the stages and the y component; E_max includes A_y; the step bound and
+    masking use both components."""
+    g = wl.grid(32, 2.0)
+    f = wl.sin2(0.1, 0.5, 8, 0.6)
+    s = pd.Solver.for_grid(g, "fp64", "strang4")
+    info = s.check_field(f, 1000)
+    assert info["stages"] == 5 and info["elliptic"] == 1 and info["valley"] == _lib.PD_VALLEYS_BOTH
+    Ax, Ay, _ = _lib.sample_field_xy(f, 1000, "strang4")
+    X = max(abs(-2 + Ax.min()), abs(-2 + Ax.max()), abs(1.875 + Ax.min()), abs(1.875 + Ax.max()))
+    Y = max(abs(-2 + Ay.min()), abs(-2 + Ay.max()), abs(1.875 + Ay.min()), abs(1.875 + Ay.max()))
+    assert abs(info["E_max"] - math.hypot(X, Y)) <= 1e-14
+    s.close()
+    s = pd.Solver.for_grid(g, "fp64", "midpoint")
+    assert s.check_field(wl.sin2(0.1, 0.5, 8), 1000)["elliptic"] == 0
+    s.close()
+
+
+def test_fourth_order_table_needs_stage_samples():
+    s = pd.Solver(8, 8, (-1, 1), (-1, 1), "fp64", "midpoint4")
+    f = {"kind": "table", "A_mid": np.zeros(10), "t_i": 0.0, "t_f": 1.0, "A_in": 0.0, "A_out": 0.0}
+    with pytest.raises(pd.PDError) as e:
+        s.check_field(f, 10)
+    assert "5 * n_steps" in e.value.message
+    f["A_mid"] = np.zeros(50)
+    assert s.check_field(f, 10)["stages"] == 5
+    f["Ay_mid"], f["Ay_in"], f["Ay_out"] = np.zeros(49), 0.0, 0.0
+    with pytest.raises(ValueError):
+        s.check_field(f, 10)
+    s.close()
+
+
+def test_masked_count_with_Ay():
+    """A table field with A_y(t_i) = 0.25 masks the point p = (-A_x(t_i), -0.25)."""
+    s = pd.Solver(8, 8, (-1.0, 1.0), (-1.0, 1.0))  # nodes -1, -0.75, ..., 0.75
+    f = {"kind": "table", "A_mid": np.full(10, 0.5), "t_i": 0.0, "t_f": 1.0, "A_in": 0.5, "A_out": 0.3,
+         "Ay_mid": np.full(10, 0.25), "Ay_in": 0.25, "Ay_out": 0.0}
+    info = s.check_field(f, 10)
+    # E_in = 0 at (-0.5, -0.25); E_out = 0 at (-0.3, 0) is not a node (-0.25 and -0.5 are)
+    assert info["n_masked"] == 1 and info["Ay_in"] == 0.25
+    f["A_out"] = 0.25
+    assert s.check_field(f, 10)["n_masked"] == 2  # and (-0.25, 0)
+    s.close()
+
+
+def test_valley_selection():
+    s = pd.Solver(8, 8, (-1, 1), (-1, 1))
+    with pytest.raises(pd.PDError) as e:
+        load_status = _lib.load().pd_set_valley(s.handle, 7)
+        _lib.check(load_status, "pd_set_valley")
+    assert e.value.status == _lib.PD_ERR_INVALID
+    s.set_valley("K-")
+    assert s.info()["valley"] == _lib.PD_VALLEY_KMINUS
+    s.set_valley("both")
+    s.close()
+    h = _lib._vp()
+    assert _lib.load().pd_create_grid(8, 8, -1.0, 1.0, -1.0, 1.0, 0, 4, ctypes.byref(h)) == _lib.PD_ERR_INVALID
+    for scheme in ("strang4", "midpoint4"):
+        pd.Solver(8, 8, (-1, 1), (-1, 1), "fp32", scheme).close()
+
+
+def test_snapshot_and_valley_state_errors_without_device():
+    s = pd.Solver(8, 8, (-1, 1), (-1, 1))
+    with pytest.raises(pd.PDError) as e:
+        s.snapshot()
+    assert e.value.status == _lib.PD_ERR_STATE
+    s.close()

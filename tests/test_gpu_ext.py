@@ -1,0 +1,269 @@
+"""GPU parity of the extensions against the FP64 CPU oracle: the fourth-order
+composition, fields with a y component (elliptic polarisation), the explicit K-
+valley and instantaneous-occupation snapshots.
+
+Tolerances are those of test_gpu_parity (FP64: 1e-12 per point and 1e-12
+relative in rho; FP32 form: 1e-5 per point); launch shape and chunking stay
+bit-identical.  For the explicit K- valley the Strang kernel's rotations are
+exact negations of the K+ ones (round-to-nearest is sign-symmetric), so its n is
+bit-identical to K+, and the valley-resolved densities add up to the
+both-valley density exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1607_03062_amd import workloads as wl
+
+from .test_gpu_parity import FP32_N_ABS, FP64_N_ABS, FP64_RHO_REL, RAGGED
+
+pytestmark = pytest.mark.gpu
+
+SCHEMES = ["strang", "midpoint", "strang4", "midpoint4"]
+F1 = wl.config1()["field"]
+ELL = wl.sin2(0.1, 0.5, 8, 0.7)
+PULSE_ELL = {"kind": "pulse", "E0": 0.5, "omega": 0.4876, "phi": 0.3, "omega_rise": 0.0609, "omega_fall": 0.0609,
+             "duration": 70.9, "ellipticity": -0.8}
+
+
+def solve(pd, grid, field, N, precision="fp64", scheme="strang", valley="both", chunks=None, ppl=0, block=0,
+          stage=0, chunk_steps=0):
+    print("gpu solve: grid %dx%d N=%d %s %s valley=%s ppl=%s block=%s stage=%s chunks=%s field=%s" % (
+        grid["nx"], grid["ny"], N, precision, scheme, valley, ppl, block, stage, chunks, field["kind"]), flush=True)
+    s = pd.Solver.for_grid(grid, precision, scheme, valley)
+    s.set_launch(ppl, block, stage, chunk_steps)
+    s.set_field(field, N)
+    for c in (chunks or [-1]):
+        s.propagate(c)
+    n = np.empty(grid["nx"] * grid["ny"])
+    rho = s.density(n_out=n)
+    info = s.info()
+    s.close()
+    return n, rho, info
+
+
+def check_parity(n, rho, n_o, grid, precision, valley_factor=4.0):
+    if precision == "fp64":
+        assert np.max(np.abs(n - n_o)) <= FP64_N_ABS, np.max(np.abs(n - n_o))
+        rho_o = oracle.density(grid, n_o) * valley_factor / 4.0
+        assert abs(rho / rho_o - 1) <= FP64_RHO_REL
+    else:
+        assert np.max(np.abs(n - n_o)) <= FP32_N_ABS, np.max(np.abs(n - n_o))
+
+
+# ---------------------------------------------------------------------------
+# Fourth order
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("scheme", ["strang4", "midpoint4"])
+def test_fourth_order_parity(gpu, scheme, precision):
+    """Ragged 37 x 53 grid, 1500 steps of five stages (crosses the FP32 renormalisation step 1024)."""
+    N = 1500
+    n, rho, info = solve(gpu, RAGGED, F1, N, precision, scheme)
+    assert info["stages"] == 5
+    n_o = oracle.solve_grid(F1, RAGGED, N, scheme)[0]
+    check_parity(n, rho, n_o, RAGGED, precision)
+
+
+@pytest.mark.parametrize("scheme", ["strang4", "midpoint4"])
+def test_fourth_order_config1(gpu, scheme):
+    """Config-1 grid at N = 1000 (64 x 64, symmetric): oracle parity, the p_y = 0 row exactly 0 and
+    one masked point (p = 0)."""
+    c = wl.config1()
+    n, rho, info = solve(gpu, c["grid"], c["field"], 1000, "fp64", scheme)
+    n_o = oracle.solve_grid(c["field"], c["grid"], 1000, scheme)[0]
+    check_parity(n, rho, n_o, c["grid"], "fp64")
+    assert np.all(n.reshape(64, 64)[32] == 0.0) and info["n_masked"] == 1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("scheme", ["strang4", "midpoint4"])
+def test_fourth_order_shapes_and_chunks(gpu, scheme, precision):
+    """Every launch shape and a chunked solve give the same bits."""
+    N = 1100
+    ref = solve(gpu, RAGGED, F1, N, precision, scheme)
+    shapes = [(1, 64, 0, 0), (2, 256, 0, 0), (4, 128, 0, 0)]
+    if scheme == "strang4":
+        shapes += [(2, 256, 1, 256), (1, 64, 1, 64)]
+    for ppl, block, stage, chunk in shapes:
+        n, rho, _ = solve(gpu, RAGGED, F1, N, precision, scheme, ppl=ppl, block=block, stage=stage,
+                          chunk_steps=chunk)
+        assert np.array_equal(n, ref[0]) and rho == ref[1], (ppl, block, stage, chunk)
+    n, rho, _ = solve(gpu, RAGGED, F1, N, precision, scheme, chunks=[1, 300, 723, 1, 75])
+    assert np.array_equal(n, ref[0]) and rho == ref[1]
+
+
+def test_fourth_order_versine_form(gpu):
+    """Few large steps (dt = 0.25, dt E_max = 2.3 <= pi): the largest stage rotation, 2 c dt |A|
+    = 2.0, exceeds pi/2, so the versine form is used."""
+    g = {"nx": 24, "ny": 20, "px": (-3.0, 3.0), "py": (-2.5, 2.5)}
+    f = wl.constant(0.3, 20.0)
+    N = 80
+    n, rho, info = solve(gpu, g, f, N, "fp64", "strang4")
+    assert info["rotation_form"] == 1
+    check_parity(n, rho, oracle.solve_grid(f, g, N, "strang4")[0], g, "fp64")
+
+
+# ---------------------------------------------------------------------------
+# Elliptic polarisation
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_elliptic_sin2_parity(gpu, scheme, precision):
+    N = 1300 if scheme.endswith("4") else 2600
+    n, rho, info = solve(gpu, RAGGED, ELL, N, precision, scheme)
+    assert info["elliptic"] == 1
+    check_parity(n, rho, oracle.solve_grid(ELL, RAGGED, N, scheme)[0], RAGGED, precision)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_elliptic_paper_pulse_parity(gpu, scheme):
+    g = {"nx": 40, "ny": 44, "px": (-2.5, 2.5), "py": (-2.2, 2.6)}
+    N = 1000 if scheme.endswith("4") else 3000
+    n, rho, info = solve(gpu, g, PULSE_ELL, N, "fp64", scheme)
+    assert abs(info["Ay_out"]) > 1e-3  # the pulse leaves A_y(t_f) != 0
+    check_parity(n, rho, oracle.solve_grid(PULSE_ELL, g, N, scheme)[0], g, "fp64")
+
+
+@pytest.mark.parametrize("scheme", ["strang", "midpoint4"])
+def test_elliptic_table_with_offsets(gpu, scheme):
+    """A caller table with both components and A(t_i) != 0 (the sin^2 pulse turned by 0.9 rad and
+    shifted by 0.3), on the ragged grid."""
+    N = 1200
+    A, a_in, a_out, dt = oracle.field_table(F1, N, scheme)
+    t_i, t_f = oracle.times(F1)
+    c, s = math.cos(0.9), math.sin(0.9)
+    f = {"kind": "table", "t_i": t_i, "t_f": t_f, "A_mid": c * (A + 0.3), "A_in": c * (a_in + 0.3),
+         "A_out": c * (a_out + 0.3), "Ay_mid": s * (A + 0.3), "Ay_in": s * (a_in + 0.3),
+         "Ay_out": s * (a_out + 0.3)}
+    n, rho, info = solve(gpu, RAGGED, f, N, "fp64", scheme)
+    check_parity(n, rho, oracle.solve_grid(f, RAGGED, N, scheme)[0], RAGGED, "fp64")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_elliptic_strang_shapes_lds_and_chunks(gpu, precision):
+    N = 2100
+    ref = solve(gpu, RAGGED, ELL, N, precision, "strang")
+    for ppl, block, stage, chunk in [(1, 64, 0, 0), (4, 256, 0, 0), (2, 128, 1, 256), (4, 256, 1, 1024)]:
+        n, rho, _ = solve(gpu, RAGGED, ELL, N, precision, "strang", ppl=ppl, block=block, stage=stage,
+                          chunk_steps=chunk)
+        assert np.array_equal(n, ref[0]) and rho == ref[1], (ppl, block, stage, chunk)
+    n, rho, _ = solve(gpu, RAGGED, ELL, N, precision, "strang", chunks=[1, 1023, 1, 1000, 75])
+    assert np.array_equal(n, ref[0]) and rho == ref[1]
+
+
+def test_batch_rejects_elliptic_member(gpu):
+    s = gpu.Solver.for_grid(RAGGED, "fp32", "strang")
+    s.set_field(ELL, 500)
+    b = gpu.Batch([s])
+    with pytest.raises(gpu.PDError) as e:
+        b.run()
+    assert e.value.status == 5
+    b.close()
+    s.close()
+    s4 = gpu.Solver.for_grid(RAGGED, "fp32", "strang4")
+    b = gpu.Batch()
+    with pytest.raises(gpu.PDError):
+        b.add(s4)
+    b.close()
+    s4.close()
+
+
+# ---------------------------------------------------------------------------
+# Valley K-
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("field", ["linear", "elliptic"])
+def test_kminus_strang_bitwise_equals_kplus(gpu, precision, field):
+    f = F1 if field == "linear" else ELL
+    N = 2100
+    nb, rb, _ = solve(gpu, RAGGED, f, N, precision, "strang", "both")
+    npl, rp, ip = solve(gpu, RAGGED, f, N, precision, "strang", "K+")
+    nm, rm, im = solve(gpu, RAGGED, f, N, precision, "strang", "K-")
+    assert ip["valley"] == 1 and im["valley"] == 2
+    assert np.array_equal(nb, npl) and np.array_equal(nb, nm)
+    assert rp == rm and rp + rm == rb  # factor 2 per valley, 4 for both
+    if precision == "fp64":
+        n_o = oracle.solve_grid(f, RAGGED, N, "strang", valley=-1)[0]
+        check_parity(nm, rm, n_o, RAGGED, "fp64", valley_factor=2.0)
+
+
+@pytest.mark.parametrize("scheme", ["midpoint", "midpoint4", "strang4"])
+def test_kminus_other_schemes_match_oracle(gpu, scheme):
+    N = 1000 if scheme.endswith("4") else 2000
+    for f in (F1, ELL):
+        n, rho, _ = solve(gpu, RAGGED, f, N, "fp64", scheme, "K-")
+        n_o = oracle.solve_grid(f, RAGGED, N, scheme, valley=-1)[0]
+        check_parity(n, rho, n_o, RAGGED, "fp64", valley_factor=2.0)
+
+
+def test_kminus_batch_member(gpu):
+    """A K- grid in a batch gives the same bits as alone."""
+    alone = solve(gpu, RAGGED, F1, 1500, "fp32", "strang", "K-")
+    s = gpu.Solver.for_grid(RAGGED, "fp32", "strang", "K-")
+    s.set_field(F1, 1500)
+    b = gpu.Batch([s])
+    rho = b.run()
+    n = np.empty(RAGGED["nx"] * RAGGED["ny"])
+    s.density(n_out=n, want_rho=False)
+    assert np.array_equal(n, alone[0]) and rho[0] == alone[1]
+    b.close()
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# Snapshots
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("field", ["linear", "elliptic"])
+def test_snapshots_match_oracle(gpu, scheme, precision, field):
+    """Snapshots at k = 0, after chunks, and at k = N (where they equal pd_density)."""
+    f = F1 if field == "linear" else ELL
+    N = 1200 if scheme.endswith("4") else 2400
+    s = gpu.Solver.for_grid(RAGGED, precision, scheme)
+    s.set_field(f, N)
+    npts = RAGGED["nx"] * RAGGED["ny"]
+    tol = 5e-12 if precision == "fp64" else FP32_N_ABS
+    k = 0
+    for step in (0, 1, 397, 402, N - 800, N - k):
+        step = min(step, N - k)
+        if step:
+            s.propagate(step)
+            k += step
+        print("snapshot %s %s %s k=%d" % (scheme, precision, field, k), flush=True)
+        n = np.empty(npts)
+        rho = s.snapshot(n_out=n)
+        n_o = oracle.snapshot_grid(f, RAGGED, N, k, scheme)[0]
+        assert np.max(np.abs(n - n_o)) <= tol, (k, np.max(np.abs(n - n_o)))
+        if k == 0:
+            assert np.max(np.abs(n)) <= 1e-12
+        if k == N:
+            n2 = np.empty(npts)
+            rho2 = s.density(n_out=n2)
+            assert np.array_equal(n, n2) and rho == rho2
+        if k == N:
+            break
+    s.close()
+
+
+def test_snapshot_landau_zener(gpu):
+    """Constant field E0 = 0.2: the instantaneous occupation at t = 150 is already the Landau-Zener
+    value for 2 <= p_x < 4."""
+    g = {"nx": 32, "ny": 16, "px": (2.0, 4.0), "py": (0.0, 1.0)}
+    f = wl.constant(0.2, 200.0)
+    N = 40000
+    s = gpu.Solver.for_grid(g, "fp64", "strang")
+    s.set_field(f, N)
+    s.propagate(30000)
+    n = np.empty(32 * 16)
+    s.snapshot(n_out=n)
+    s.close()
+    py = np.repeat(np.arange(16) / 16.0, 32)
+    assert np.max(np.abs(n - np.exp(-math.pi * py ** 2 / 0.2))) <= 2e-3
