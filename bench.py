@@ -116,10 +116,15 @@ def time_form(pd, torch, c, precision, steps, warmup, ppl, block, stage=0, chunk
     import numpy as np
 
     n = np.empty(c["grid"]["nx"] * c["grid"]["ny"])
-    s.density(n_out=n, stream=st)
+    copy_s = []
+    for _ in range(2):  # reduction + copy of n(p) to (pageable) host memory; the first pass touches the pages
+        w0 = time.perf_counter()
+        s.density(n_out=n, stream=st)
+        copy_s.append(time.perf_counter() - w0)
     info = s.info()
     s.close()
-    return {"t_total": t1 - t0, "wall": wall, "kernel_ms": kern_ms, "rho": rho, "n": n, "info": info}
+    return {"t_total": t1 - t0, "wall": wall, "kernel_ms": kern_ms, "rho": rho, "n": n, "info": info,
+            "n_to_host_ms": copy_s[-1] * 1e3}
 
 
 def run_batch(args):
@@ -367,6 +372,8 @@ def main():
         "p50_ms": float(np.percentile(wall_ms, 50)),
         "p99_ms": float(np.percentile(wall_ms, 99)),
         "kernel_ms": kern_ms,
+        "n_to_host_ms": main_form["n_to_host_ms"],
+        "value_with_n_to_host": ps_per_solve / (t / K + main_form["n_to_host_ms"] * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      "traffic": traffic_from_profile(args.precision) if (sch == "strang" and not args.ellipticity)

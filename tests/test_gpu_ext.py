@@ -267,3 +267,25 @@ def test_snapshot_landau_zener(gpu):
     s.close()
     py = np.repeat(np.arange(16) / 16.0, 32)
     assert np.max(np.abs(n - np.exp(-math.pi * py ** 2 / 0.2))) <= 2e-3
+
+
+# ---------------------------------------------------------------------------
+# Full size
+
+
+def test_config3_fourth_order_precision_form(gpu):
+    """2048^2 on [-2,2]^2, 16000 fourth-order Strang steps (the work of 80000 second-order steps):
+    the 64 x 64 subsample within 1e-5 of the oracle per point in the FP32 form and 1e-12 in the FP64
+    form; the p_y = 0 row exactly 0; both forms' densities within 1e-5."""
+    c = wl.config3()
+    N = 16000
+    idx = wl.subsample_indices(2048, 64)
+    n_o = oracle.solve_grid(c["field"], c["grid"], N, "strang4", idx=idx)[0]
+    n32, rho32, _ = solve(gpu, c["grid"], c["field"], N, "fp32", "strang4")
+    err32 = np.max(np.abs(n32[idx] - n_o))
+    print("config3 strang4 fp32 max |dn| on subsample = %.3e" % err32, flush=True)
+    assert err32 <= FP32_N_ABS
+    n64, rho64, _ = solve(gpu, c["grid"], c["field"], N, "fp64", "strang4")
+    assert np.max(np.abs(n64[idx] - n_o)) <= FP64_N_ABS
+    assert abs(rho32 / rho64 - 1) <= 1e-5
+    assert np.all(n32.reshape(2048, 2048)[1024] == 0.0)
