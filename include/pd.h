@@ -119,7 +119,8 @@ typedef struct {
   double phi;               /* PULSE: carrier phase */
   double omega_rise;        /* PULSE: > 0 */
   double omega_fall;        /* PULSE: > 0 */
-  double duration;          /* PULSE: >= pi/(2 omega_rise) + pi/(2 omega_fall) */
+  double duration;          /* PULSE: >= pi/(2 omega_rise) + pi/(2 omega_fall) (equality up to rounding
+                               allowed: no flat part) */
   double ellipticity;       /* SIN2, PULSE, CONSTANT: E_y amplitude / E0 (0: linear) */
   const double* Ay_mid;     /* TABLE: NULL (A_y = 0) or n_table values of A_y */
   double Ay_in, Ay_out;     /* TABLE with Ay_mid: A_y(t_i), A_y(t_f) */

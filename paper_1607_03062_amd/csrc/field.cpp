@@ -175,7 +175,8 @@ bool sample_field(const pd_field& f, long long n_steps, const Composition& comp,
         *err = "pulse field needs finite E0, phi, duration and omega, omega_rise, omega_fall > 0";
         return false;
       }
-      if (p.ta() < p.tr()) {
+      // a pulse with no flat part (duration = rise + fall window) is valid: allow rounding
+      if (p.ta() < p.tr() - 1e-12 * std::fabs(f.duration)) {
         *err = "pulse duration shorter than its rise plus fall windows";
         return false;
       }

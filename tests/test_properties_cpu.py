@@ -93,3 +93,14 @@ def test_masked_count_matches_oracle(nx, ny, k_in, k_out, j_in, j_out, ell):
     s.close()
     m_or = oracle.solve_grid(f, g, 1, "strang")[2]
     assert m_lib == m_or
+
+
+def test_pulse_without_flat_part_is_accepted():
+    """duration = pi/(2 W_r) + pi/(2 W_f) exactly (no flat part) is a valid pulse even when the
+    rounding of duration - pi/(2 W_f) lands below pi/(2 W_r); the samples still match the oracle."""
+    wr, wf = 0.2, 0.0609  # D - pi/(2 wf) rounds 1.8e-15 below pi/(2 wr)
+    f = {"kind": "pulse", "E0": 1.0, "omega": 0.7, "phi": 0.1, "omega_rise": wr, "omega_fall": wf,
+         "duration": math.pi / (2 * wr) + math.pi / (2 * wf)}
+    Ax, Ay, ends = _lib.sample_field_xy(f, 200, "strang")
+    Ao = oracle.field_table(f, 200)[0]
+    assert np.max(np.abs(Ax - Ao)) <= 1e-13
