@@ -1,0 +1,107 @@
+"""Seeded random configurations on the GPU against the oracle: grid shapes down to
+1 x 1, every field kind with and without a y component, all schemes, both
+precisions and valleys, random launch shapes, chunked solves and snapshots.
+Each case prints its parameters before it runs.  Tolerances as in
+test_gpu_parity (FP64 1e-12, FP32 1e-5 per point)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+from .test_gpu_parity import FP32_N_ABS, FP64_N_ABS
+
+pytestmark = pytest.mark.gpu
+
+N_CASES = 40
+
+
+def draw_case(seed):
+    rng = np.random.default_rng(1000 + seed)
+    nx, ny = int(rng.integers(1, 70)), int(rng.integers(1, 70))
+    if rng.random() < 0.15:
+        nx = 1
+    if rng.random() < 0.15:
+        ny = 1
+    w = float(rng.uniform(0.5, 3.0))
+    grid = {"nx": nx, "ny": ny, "px": (-w, w * rng.uniform(0.3, 1.5)), "py": (-w * rng.uniform(0.3, 1.5), w)}
+    scheme = str(rng.choice(["strang", "midpoint", "strang4", "midpoint4"]))
+    stages = 5 if scheme.endswith("4") else 1
+    e = float(rng.choice([0.0, rng.uniform(-1, 1)]))
+    kind = str(rng.choice(["sin2", "pulse", "constant", "table"]))
+    if kind == "sin2":
+        field = {"kind": "sin2", "E0": float(rng.uniform(0.05, 0.8)), "omega": float(rng.uniform(0.2, 1.5)),
+                 "cycles": int(rng.integers(2, 6)), "ellipticity": e}
+    elif kind == "pulse":
+        wr, wf = float(rng.uniform(0.1, 0.5)), float(rng.uniform(0.1, 0.5))
+        field = {"kind": "pulse", "E0": float(rng.uniform(0.1, 1.0)), "omega": float(rng.uniform(0.3, 1.5)),
+                 "phi": float(rng.uniform(-3, 3)), "omega_rise": wr, "omega_fall": wf,
+                 "duration": math.pi / (2 * wr) + math.pi / (2 * wf) + float(rng.uniform(0, 10)), "ellipticity": e}
+    elif kind == "constant":
+        field = {"kind": "constant", "E0": float(rng.uniform(-0.5, 0.5)), "t_end": float(rng.uniform(2, 30)),
+                 "ellipticity": e}
+    else:
+        field = None  # filled once N is known
+    N = int(rng.integers(1, 3000 // stages + 2))
+    if kind == "table":
+        m = N * stages
+        t = np.linspace(0, 1, m)
+        field = {"kind": "table", "t_i": -1.0, "t_f": float(rng.uniform(1, 20)),
+                 "A_mid": 0.4 * np.sin(7 * t + rng.uniform(0, 6)) + float(rng.uniform(-0.5, 0.5)),
+                 "A_in": float(rng.uniform(-0.5, 0.5)), "A_out": float(rng.uniform(-0.5, 0.5))}
+        if e:
+            field.update({"Ay_mid": 0.3 * np.cos(5 * t), "Ay_in": float(rng.uniform(-0.5, 0.5)),
+                          "Ay_out": float(rng.uniform(-0.5, 0.5))})
+    precision = str(rng.choice(["fp64", "fp32"]))
+    valley = str(rng.choice(["both", "K+", "K-"]))
+    ppl = int(rng.choice([1, 2, 4]))
+    block = int(rng.choice([64, 128, 256]))
+    stage = int(rng.choice([2, 1])) if scheme.startswith("strang") else 2
+    chunk = int(rng.choice([64, 256, 1024]))
+    n_chunks = int(rng.integers(1, 4))
+    cuts = sorted(set(int(c) for c in rng.integers(1, N + 1, size=n_chunks - 1))) if N > 1 else []
+    chunks = [b - a for a, b in zip([0] + cuts, cuts + [N]) if b > a]
+    return dict(grid=grid, field=field, N=N, scheme=scheme, precision=precision, valley=valley, ppl=ppl,
+                block=block, stage=stage, chunk=chunk, chunks=chunks)
+
+
+@pytest.mark.parametrize("seed", range(N_CASES))
+def test_random_case(gpu, seed):
+    c = draw_case(seed)
+    g, f, N = c["grid"], c["field"], c["N"]
+    s = gpu.Solver.for_grid(g, c["precision"], c["scheme"], c["valley"])
+    try:
+        s.check_field(f, N)
+    except gpu.PDError as err:
+        s.close()
+        assert err.status == 1 and "pi" in err.message  # only the step condition refuses these draws
+        pytest.skip("step condition: %s" % err.message)
+    print("case %d: grid %dx%d %s N=%d %s %s valley=%s ppl=%d block=%d stage=%d chunk=%d chunks=%s" % (
+        seed, g["nx"], g["ny"], f["kind"], N, c["scheme"], c["precision"], c["valley"], c["ppl"], c["block"],
+        c["stage"], c["chunk"], c["chunks"]), flush=True)
+    s.set_launch(c["ppl"], c["block"], c["stage"], c["chunk"])
+    s.set_field(f, N)
+    npts = g["nx"] * g["ny"]
+    ov = -1 if c["valley"] == "K-" else 1
+    tol = FP64_N_ABS if c["precision"] == "fp64" else FP32_N_ABS
+    done = 0
+    for i, m in enumerate(c["chunks"]):
+        s.propagate(m)
+        done += m
+        if done < N and i == 0:
+            n = np.empty(npts)
+            s.snapshot(n_out=n)
+            n_o = oracle.snapshot_grid(f, g, N, done, c["scheme"], valley=ov)[0]
+            assert np.max(np.abs(n - n_o)) <= (5e-12 if c["precision"] == "fp64" else tol), ("snapshot", done)
+    n = np.empty(npts)
+    rho = s.density(n_out=n)
+    info = s.info()
+    s.close()
+    n_o, _, masked = oracle.solve_grid(f, g, N, c["scheme"], valley=ov)
+    assert info["n_masked"] == masked
+    assert np.max(np.abs(n - n_o)) <= tol
+    factor = 4.0 if c["valley"] == "both" else 2.0
+    rho_o = oracle.density(g, n_o) * factor / 4.0
+    assert abs(rho - rho_o) <= 1e-11 * max(abs(rho_o), 1e-300) + tol * factor * abs(
+        (g["px"][1] - g["px"][0]) * (g["py"][1] - g["py"][0])) / (4 * math.pi ** 2)
