@@ -260,6 +260,8 @@ def main():
                     help="give the workload pulse a y component E_y = e E0 sin^2(pi t/T) cos(omega t)")
     ap.add_argument("--n-steps", type=int, default=0, help="override the workload's 80000 steps")
     ap.add_argument("--ppl", type=int, default=0)
+    ap.add_argument("--table-stage", type=int, default=0, help="1: LDS field rows, 2: scalar-unit rows (0: default)")
+    ap.add_argument("--chunk-steps", type=int, default=0, help="LDS chunk length (0: default)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -305,11 +307,13 @@ def main():
         print("copy calibration: %d bytes read, %d bytes written" % (nb, nb), file=sys.stderr)
 
     sch = args.scheme
-    main_form = time_form(pd, torch, c, args.precision, args.steps, args.warmup, args.ppl, args.block, scheme=sch)
+    main_form = time_form(pd, torch, c, args.precision, args.steps, args.warmup, args.ppl, args.block,
+                          args.table_stage, args.chunk_steps, scheme=sch)
     other = None
     if not args.no_fp64_form and args.precision != "fp64":
         c64 = dict(c, field=dict(c["field"]), precision="fp64")
-        other = time_form(pd, torch, c64, "fp64", args.steps, args.warmup, args.ppl, args.block, scheme=sch)
+        other = time_form(pd, torch, c64, "fp64", args.steps, args.warmup, args.ppl, args.block, args.table_stage,
+                          args.chunk_steps, scheme=sch)
 
     # oracle on the 64 x 64 subsample: n(p) error of each form and the CPU baseline
     n_err = {}
