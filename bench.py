@@ -61,9 +61,17 @@ PEAK_TFLOPS = {p: CU_CLOCKS_PER_S * l * 2 / 1e12 for p, l in LANES_PER_CLK.items
 KERNEL_SRC = os.path.join(ROOT, "paper_1607_03062_amd", "csrc", "kernels.hip")
 
 
-def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+def kernel_hash(path: str = KERNEL_SRC) -> str:
+    """Hash of the kernel source's code: comments and whitespace removed, so that a
+    profile stays valid across edits that do not change the code."""
+    import re
+
+    with open(path) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    code = "".join(text.split())
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def traffic_from_profile(precision: str):
@@ -77,7 +85,7 @@ def traffic_from_profile(precision: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_hash():
+    if vals.get("kernel_code_sha256_16") != kernel_hash():
         return None
     try:
         return float(vals["hbm_bytes_per_dispatch"])

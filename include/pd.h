@@ -6,18 +6,22 @@
  * What a solve computes (Sec. II, Eq. (1); Sec. III, Eqs. (9)-(13)):
  *   for every point p of a uniform momentum grid, the negative-energy state
  *   v_in(p) of sigma.(p + A(t_i)) is advanced by N short-time steps of the
- *   equation i d/dt psi = sigma.(p + A(t)) psi (Sec. II, Eq. (2), valley K+,
+ *   equation i d/dt psi = sigma.(p + A(t)) psi (Sec. II, Eq. (2), valley K+
+ *   unless pd_set_valley chooses K-, where H = -sigma.(p + A);
  *   hbar = v_F = e = 1), then projected on the positive-energy state
- *   u_out(p) of sigma.(p + A(t_f)):  n(p) = |u_out^dagger psi(t_f)|^2  (unit
- *   spinors, so 0 <= n <= 1), and the pair density is
+ *   u_out(p) of the Hamiltonian at t_f:  n(p) = |u_out^dagger psi(t_f)|^2
+ *   (unit spinors, so 0 <= n <= 1), and the pair density is
  *   rho = 4 * dx * dy / (2 pi)^2 * sum_p n(p)  (rectangle rule on the grid;
- *   the factor 4 counts spin and valley).
+ *   the factor 4 counts spin and valley; 2 when one valley is solved
+ *   explicitly).
  *
  * Conventions shared by every entry point:
  *   - Grid: p_x[i] = px_min + i * (px_max - px_min) / nx, i < nx (same for y);
  *     point index k = j * nx + i (x fastest); n(p) is laid out [ny][nx].
  *   - Steps: dt = (t_f - t_i) / N; step k (0 <= k < N) uses the vector
- *     potential at its midpoint t_i + (k + 1/2) dt (Sec. III, Eqs. (11)-(12)).
+ *     potential at its midpoint t_i + (k + 1/2) dt (Sec. III, Eqs. (11)-(12));
+ *     a fourth-order step is five second-order stages, each with the potential
+ *     at its own sub-interval midpoint (see pd_scheme).
  *   - A point where |p + A(t_i)| = 0 or |p + A(t_f)| = 0 has no defined
  *     adiabatic spinor; it gets n = 0 and is counted in pd_info.n_masked.
  *   - With a y component of the field (elliptic polarisation) P = p + A with
@@ -224,12 +228,13 @@ pd_status pd_density(pd_grid g, double* n_out, int n_out_on_device, double* rho_
 pd_status pd_snapshot(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, void* stream);
 
 /* Bytes of device state a chunked solve keeps between pd_propagate calls
-   (3 FP64 or FP32 values per point for PD_SCHEME_STRANG, 4 for
-   PD_SCHEME_MIDPOINT). */
+   (3 FP64 or FP32 values per point for the Strang schemes, 4 for the midpoint
+   schemes). */
 size_t pd_state_bytes(pd_grid g);
 
 /* Device memory a solve of n_steps steps on g needs, chunk state included
-   (field table and rotation tables, n(p), density partials, state); closed form,
+   (field table and rotation tables, n(p), density partials, state), for a field
+   without a y component (a y component doubles the step table); closed form,
    no field sampling, no device work (0 for a null handle or n_steps < 1).  Used
    for admission control. */
 size_t pd_solve_bytes(pd_grid g, long long n_steps);

@@ -1,8 +1,10 @@
 // Host side of the field: the vector potential A(t) of each supported field
-// kind, sampled at the step midpoints, and the per-step rows the kernels read.
+// kind (both components), sampled at the times the scheme uses, and the per-step
+// rows and per-point rotation coefficients the kernels read.
 //
 // Gauge A_0 = 0, E = -dA/dt, A(t) = -int_{t_i}^{t} E (Sec. II, after Eq. (2));
-// A is sampled at t_i + (k + 1/2) dt (Sec. III, Eqs. (11)-(12)).
+// A is sampled at the step midpoints t_i + (k + 1/2) dt (Sec. III, Eqs. (11)-(12)),
+// or for the fourth-order composition at the stage midpoints t_i + (k + sigma_j) dt.
 #include <cmath>
 #include <cstring>
 

@@ -30,6 +30,14 @@
 //   U = cos(dt E) I - i sigma.P sin(dt E) / E,  P = p + A_k,
 // acting on the spinor (a1 + i b1, a2 + i b2); cos - 1 and sin(x)/x are even
 // Taylor series in x = (dt E)^2 of an order chosen by the host.
+//
+// Both kernels are templated on the composition (NS = 1 second-order step, or
+// NS = 5 stages of Suzuki's fourth-order composition, each a second-order step
+// over c_j dt with the field at its own sub-interval midpoint) and on a y
+// component of the field (POL: sigma_y (p_y + A_y) in place of sigma_y p_y; the
+// Strang kernel then adds the field part of each y rotation from the table).
+// The K- valley (H = -sigma.P) arrives as negated table and coefficient angles
+// plus the sign vsign of the initial state and of the projection.
 #include <hip/hip_runtime.h>
 
 #include "pd_internal.h"

@@ -105,8 +105,8 @@ struct SolveParams {
   double hx[2];      // midpoint: vsign * c dt for the distinct stage coefficients
   long long n_steps, k_begin, k_end;
   const void* table;
-  const void* col_coef;  // Strang: per column (a, s) of the rotation by 2 dt px about x
-  const void* row_coef;  // Strang: per row (a, s) of the rotations by 2 dt py and dt py about y
+  const void* col_coef;  // Strang: per column the (a, s) pairs of the x rotations by 2 c dt px
+  const void* row_coef;  // Strang: per row the (a, s) pairs of the y rotations, then the half step
   void* state;       // chunk state, structure of arrays; nullptr if not used
   double* n_out;     // written by the launch that reaches n_steps
   int load_state;    // 1: resume from state; 0: start from v_in
