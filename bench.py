@@ -378,8 +378,12 @@ def main():
                    "n_points": npts, "n_steps": c["n_steps"], "precision": args.precision, "scheme": sch,
                    "points_per_lane": main_form["info"]["points_per_lane"],
                    "block_threads": main_form["info"]["block_threads"]},
-        "n_error_max_abs": n_err.get(args.precision),
-        "n_error_max_abs_64x64": n_err.get(args.precision + "_64"),
+        # the workload's error is defined on the 64 x 64 subsample; the larger sample the CPU
+        # baseline runs on is reported beside it
+        "n_error_max_abs": n_err.get(args.precision + "_64"),
+        "n_error_sample": "64x64 subsample (stride %d) vs the FP64 oracle" % (args.grid // 64),
+        "n_error_max_abs_cpu_sample": n_err.get(args.precision),
+        "cpu_sample_points": (min(args.cpu_sample, args.grid) ** 2) if not args.no_cpu_baseline else None,
         "rho": main_form["rho"],
         "p50_ms": float(np.percentile(wall_ms, 50)),
         "p99_ms": float(np.percentile(wall_ms, 99)),
