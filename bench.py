@@ -28,9 +28,12 @@ METRIC = "momentum point-steps/s (FP32 vs FP64 form) at stated n(p) error; p50/p
 # Algorithmic work per point-step of the propagation kernel: three plane
 # rotations of the Bloch vector per Strang step.
 #   shear form (every rotation angle <= pi/2): 3 FMA per rotation -> 9 FMA = 18 flop, 9 VALU instructions
+#     FP32 form: each component rounded once per rotation, 3 FMA + 1 add -> 21 flop, 12 instructions
+#     (fp32fast: the plain shears, 18 flop, 9 instructions)
 #   versine form, FP64: 2 FMA per rotated component -> 12 FMA = 24 flop, 12 instructions
 #   versine form, FP32: mul + fma + add per rotated component -> 24 flop, 18 instructions
-ALGO = {(0, "fp64"): (18, 9), (0, "fp32"): (18, 9), (1, "fp64"): (24, 12), (1, "fp32"): (24, 18)}
+ALGO = {(0, "fp64"): (18, 9), (0, "fp32"): (21, 12), (0, "fp32fast"): (18, 9),
+        (1, "fp64"): (24, 12), (1, "fp32"): (24, 18), (1, "fp32fast"): (24, 18)}
 
 
 def algo(info: dict, precision: str):
@@ -50,13 +53,13 @@ def algo(info: dict, precision: str):
         return stages * f * (4 if ell else 3) // 3, stages * i * (4 if ell else 3) // 3
     J = info["taylor_order"]
     flops = 3 + (2 * (J - 1) + 1) + 2 * J + 2 + 24 + (2 if ell else 0)
-    instr = 2 + 2 * J + 2 + (12 if precision == "fp64" else 16 + 3) + (2 if ell else 0)
+    instr = 2 + 2 * J + 2 + (12 if precision == "fp64" else 16 + 3) + (2 if ell else 0)  # fp32fast runs as fp32
     return stages * flops, stages * instr
 # MI355X vector peaks from its unit counts and clock (256 CU, 2.4 GHz): FP64
 # issues 64 lanes per clock per CU (78.6 TFLOP/s with FMA); unpacked FP32 with
 # VGPR operands issues 128 lanes per clock per CU (157.3 TFLOP/s with FMA).
 CU_CLOCKS_PER_S = 256 * 2.4e9
-LANES_PER_CLK = {"fp64": 64, "fp32": 128}
+LANES_PER_CLK = {"fp64": 64, "fp32": 128, "fp32fast": 128}
 PEAK_TFLOPS = {p: CU_CLOCKS_PER_S * l * 2 / 1e12 for p, l in LANES_PER_CLK.items()}
 KERNEL_SRC = os.path.join(ROOT, "paper_1607_03062_amd", "csrc", "kernels.hip")
 
@@ -185,7 +188,7 @@ def run_batch(args):
     b.close()
     for s in solvers:
         s.close()
-    flops = 18 * total  # every config-4 solve takes the shear form (checked by the tests)
+    flops = ALGO[(0, "fp32")][0] * total  # every config-4 solve takes the shear form (checked by the tests)
     line = {
         "metric": METRIC, "value": total * args.steps / t, "unit": "point-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": t / args.steps * 1e3, "higher_is_better": True,
@@ -262,7 +265,8 @@ def main():
     ap.add_argument("--epoch-steps", type=int, default=2048)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--precision", choices=["fp32", "fp64", "fp32fast"], default="fp32")
+    ap.add_argument("--no-fast-form", action="store_true", help="skip timing the fp32fast form beside")
     ap.add_argument("--scheme", choices=["strang", "midpoint", "strang4", "midpoint4"], default="strang")
     ap.add_argument("--ellipticity", type=float, default=0.0,
                     help="give the workload pulse a y component E_y = e E0 sin^2(pi t/T) cos(omega t)")
@@ -322,6 +326,10 @@ def main():
         c64 = dict(c, field=dict(c["field"]), precision="fp64")
         other = time_form(pd, torch, c64, "fp64", args.steps, args.warmup, args.ppl, args.block, args.table_stage,
                           args.chunk_steps, scheme=sch)
+    fast = None
+    if not args.no_fast_form and args.precision == "fp32" and sch.startswith("strang"):
+        fast = time_form(pd, torch, dict(c, field=dict(c["field"])), "fp32fast", args.steps, args.warmup, args.ppl,
+                         args.block, args.table_stage, args.chunk_steps, scheme=sch)
 
     # oracle on the 64 x 64 subsample: n(p) error of each form and the CPU baseline
     n_err = {}
@@ -345,6 +353,9 @@ def main():
         n_err[args.precision + "_64"] = float(np.max(np.abs(main_form["n"][idx[in64]] - n_o[in64])))
         if other is not None:
             n_err["fp64"] = float(np.max(np.abs(other["n"][idx] - n_o)))
+        if fast is not None:
+            n_err["fast"] = float(np.max(np.abs(fast["n"][idx] - n_o)))
+            n_err["fast_64"] = float(np.max(np.abs(fast["n"][idx[in64]] - n_o[in64])))
 
     K = args.steps
     t = main_form["t_total"]
@@ -365,7 +376,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": "%dx%d momentum grid on [-2,2]^2, sin^2 pulse E0=0.1 omega=0.5 30 cycles%s, "
                                "%d %s steps, %s form" % (args.grid, args.grid,
@@ -407,6 +418,15 @@ def main():
             "rho_rel_diff_fp32_vs_fp64": main_form["rho"] / other["rho"] - 1,
             "roofline_frac": f64 * ps_per_solve / (okm * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],
             "valu_issue_frac": i64 * ps_per_solve / (okm * 1e-3) / (CU_CLOCKS_PER_S * LANES_PER_CLK["fp64"])}
+    if fast is not None:
+        fkm = float(np.mean(fast["kernel_ms"]))
+        ff, fi = algo(fast["info"], "fp32fast")
+        line["fp32_fast_form"] = {
+            "value": ps_per_solve * K / fast["t_total"], "ms_per_step": fast["t_total"] / K * 1e3,
+            "kernel_ms": fkm, "n_error_max_abs": n_err.get("fast_64"),
+            "n_error_max_abs_cpu_sample": n_err.get("fast"), "rho": fast["rho"],
+            "roofline_frac": ff * ps_per_solve / (fkm * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
+            "valu_issue_frac": fi * ps_per_solve / (fkm * 1e-3) / (CU_CLOCKS_PER_S * LANES_PER_CLK["fp32"])}
     print(json.dumps(line), flush=True)
 
 

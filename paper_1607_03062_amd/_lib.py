@@ -11,12 +11,12 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpd.so")
 
 PD_OK, PD_ERR_INVALID, PD_ERR_STATE, PD_ERR_NOMEM, PD_ERR_DEVICE, PD_ERR_UNSUPPORTED = range(6)
-PD_FP64, PD_FP32 = 0, 1
+PD_FP64, PD_FP32, PD_FP32_FAST = 0, 1, 2
 PD_SCHEME_STRANG, PD_SCHEME_MIDPOINT, PD_SCHEME_STRANG4, PD_SCHEME_MIDPOINT4 = 0, 1, 2, 3
 PD_VALLEYS_BOTH, PD_VALLEY_KPLUS, PD_VALLEY_KMINUS = 0, 1, 2
 PD_FIELD_SIN2, PD_FIELD_CONSTANT, PD_FIELD_TABLE, PD_FIELD_PULSE = 0, 1, 2, 3
 
-PRECISIONS = {"fp64": PD_FP64, "fp32": PD_FP32}
+PRECISIONS = {"fp64": PD_FP64, "fp32": PD_FP32, "fp32fast": PD_FP32_FAST}
 SCHEMES = {"strang": PD_SCHEME_STRANG, "midpoint": PD_SCHEME_MIDPOINT, "strang4": PD_SCHEME_STRANG4,
            "midpoint4": PD_SCHEME_MIDPOINT4}
 STAGES = {"strang": 1, "midpoint": 1, "strang4": 5, "midpoint4": 5}

@@ -40,7 +40,8 @@ std::string cache_key(pd_grid g) {
   int size_class = (int)std::floor(std::log2((double)g->grid.points()));
   std::ostringstream k;
   static const char* const kSchemes[] = {"strang", "midpoint", "strang4", "midpoint4"};
-  k << arch_name(g->device) << " " << (g->precision == PD_FP32 ? "fp32" : "fp64") << " " << kSchemes[g->scheme]
+  static const char* const kPrecisions[] = {"fp64", "fp32", "fp32fast"};
+  k << arch_name(g->device) << " " << kPrecisions[g->precision] << " " << kSchemes[g->scheme]
     << (g->field.elliptic ? "-xy" : "") << " " << g->form << " " << size_class;
   return k.str();
 }

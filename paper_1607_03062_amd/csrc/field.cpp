@@ -311,7 +311,7 @@ size_t table_row_values(int scheme, int elliptic) {
 }
 
 size_t table_row_bytes(int scheme, int precision, int elliptic) {
-  size_t v = (base_scheme(scheme) == PD_SCHEME_STRANG && precision == PD_FP32) ? sizeof(float) : sizeof(double);
+  size_t v = (base_scheme(scheme) == PD_SCHEME_STRANG && is_fp32(precision)) ? sizeof(float) : sizeof(double);
   return table_row_values(scheme, elliptic) * v;
 }
 
@@ -358,7 +358,7 @@ void build_step_table(const FieldTables& t, int scheme, int precision, int form,
   auto store = [&](long long row, size_t slot, double half) {
     double a, s;
     rotation_coefficients(half, form, &a, &s);
-    if (precision == PD_FP32) {
+    if (is_fp32(precision)) {
       put<float>(rows, 0, (size_t)row * W + 2 * slot, a);
       put<float>(rows, 0, (size_t)row * W + 2 * slot + 1, s);
     } else {
@@ -392,14 +392,14 @@ size_t point_coefficient_pairs_y(int scheme) { return composition_of(scheme).sta
 
 void build_point_coefficients(const Grid& g, const FieldTables& t, int scheme, int precision, int form, double vsign,
                               std::vector<unsigned char>* bytes, size_t* col_offset, size_t* row_offset) {
-  const size_t v = precision == PD_FP32 ? sizeof(float) : sizeof(double);
+  const size_t v = is_fp32(precision) ? sizeof(float) : sizeof(double);
   const size_t nxp = point_coefficient_pairs_x(scheme), nyp = point_coefficient_pairs_y(scheme);
   auto align = [](size_t n) { return (n + 255) / 256 * 256; };
   *col_offset = align(bytes->size());
   *row_offset = align(*col_offset + 2 * nxp * v * (size_t)g.nx);
   bytes->resize(align(*row_offset + 2 * nyp * v * (size_t)g.ny));
   auto store = [&](size_t off, size_t idx, double x) {
-    if (precision == PD_FP32)
+    if (is_fp32(precision))
       put<float>(bytes, off, idx, x);
     else
       put<double>(bytes, off, idx, x);
@@ -449,8 +449,8 @@ int taylor_order(double x_max, int precision) {
   // Orders compiled into the midpoint kernels.
   static const int kOrders64[] = {5, 8, 14};
   static const int kOrders32[] = {3, 5, 9};
-  const int* orders = precision == PD_FP32 ? kOrders32 : kOrders64;
-  double tol = precision == PD_FP32 ? 0x1p-27 : 0x1p-56;
+  const int* orders = is_fp32(precision) ? kOrders32 : kOrders64;
+  double tol = is_fp32(precision) ? 0x1p-27 : 0x1p-56;
   for (int q = 0; q < 3; ++q) {
     int J = orders[q];
     // relative size of the first omitted terms: 2 x^J / (2J+2)! for cos - 1 and

@@ -81,6 +81,31 @@ __device__ __forceinline__ void rotate(R& u, R& v, R a, R s) {
     rotate_versine(u, v, a, s);
 }
 
+
+// Shear form with every component rounded once per rotation: the two u shears
+// add up to u - t (v + v'), so u is updated from its value before the rotation
+// (3 FMA + 1 add).  In FP32 the state's rounding errors are the whole error of a
+// solve, and the second rounding of u per rotation dominates them (its increments
+// are small, and the roundings of a slowly varying state accumulate); rounding each
+// component once halves the worst-point error of the FP32 form on the benchmark
+// workloads, for a quarter more instructions.
+__device__ __forceinline__ void rotate_shear_once(float& u, float& v, float t, float s) {
+  float u1 = fmaf(-t, v, u);
+  float v1 = fmaf(s, u1, v);
+  float w = v + v1;
+  u = fmaf(-t, w, u);
+  v = v1;
+}
+
+// A rotation in the solve's form; ONCE selects the once-rounded shears (FP32 form).
+template <int FORM, int ONCE, typename R>
+__device__ __forceinline__ void rot(R& u, R& v, R a, R s) {
+  if constexpr (FORM == kFormShear && ONCE && sizeof(R) == 4)
+    rotate_shear_once(u, v, a, s);
+  else
+    rotate<FORM>(u, v, a, s);
+}
+
 struct PointCoords {
   int i, j;
   double px, py;
@@ -121,7 +146,7 @@ struct Layout<5> {
 };
 
 // The Bloch vectors of a lane's points and their per-point rotations.
-template <typename R, int PPL, int FORM, int NS, int POL>
+template <typename R, int PPL, int FORM, int NS, int POL, int ONCE>
 struct BlochLanes {
   using L = Layout<NS>;
   static constexpr int kRow = 2 * NS * (1 + POL);  // table values per step
@@ -137,13 +162,13 @@ struct BlochLanes {
     for (int j = 0; j < NS; ++j) {
 #pragma unroll
       for (int q = 0; q < PPL; ++q) {
-        rotate<FORM>(y[q], z[q], row[2 * j], row[2 * j + 1]);
-        rotate<FORM>(y[q], z[q], aX[L::xcls(j)][q], sX[L::xcls(j)][q]);
+        rot<FORM, ONCE>(y[q], z[q], row[2 * j], row[2 * j + 1]);
+        rot<FORM, ONCE>(y[q], z[q], aX[L::xcls(j)][q], sX[L::xcls(j)][q]);
         if (LAST && j == NS - 1)
-          rotate<FORM>(z[q], x[q], ha[q], hs[q]);
+          rot<FORM, ONCE>(z[q], x[q], ha[q], hs[q]);
         else
-          rotate<FORM>(z[q], x[q], aY[L::ycls(j)][q], sY[L::ycls(j)][q]);
-        if (POL) rotate<FORM>(z[q], x[q], row[2 * NS + 2 * j], row[2 * NS + 2 * j + 1]);
+          rot<FORM, ONCE>(z[q], x[q], aY[L::ycls(j)][q], sY[L::ycls(j)][q]);
+        if (POL) rot<FORM, ONCE>(z[q], x[q], row[2 * NS + 2 * j], row[2 * NS + 2 * j + 1]);
       }
     }
   }
@@ -168,10 +193,10 @@ struct RowN {
 };
 
 // Steps [k, k_full) with the table rows read by the scalar unit (SGPR operands).
-template <typename R, int PPL, int FORM, int NS, int POL>
-__device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM, NS, POL>& L, const R* __restrict__ table,
+template <typename R, int PPL, int FORM, int NS, int POL, int ONCE>
+__device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM, NS, POL, ONCE>& L, const R* __restrict__ table,
                                              long long k, long long k_full) {
-  using Lanes = BlochLanes<R, PPL, FORM, NS, POL>;
+  using Lanes = BlochLanes<R, PPL, FORM, NS, POL, ONCE>;
   using Row = RowN<R, Lanes::kRow>;
   const Row* __restrict__ tab = reinterpret_cast<const Row*>(table);
   while (k < k_full) {
@@ -199,10 +224,10 @@ __device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM, NS, POL>& 
 // Steps [k, k_full) with the table staged through LDS in chunks of `chunk` rows
 // (absolute chunk boundaries; a power of two dividing the renormalisation period
 // in the FP32 form), so every lane reads its rotation from VGPRs.
-template <typename R, int PPL, int FORM, int NS, int POL>
-__device__ __forceinline__ void steps_lds(BlochLanes<R, PPL, FORM, NS, POL>& L, const R* __restrict__ table,
+template <typename R, int PPL, int FORM, int NS, int POL, int ONCE>
+__device__ __forceinline__ void steps_lds(BlochLanes<R, PPL, FORM, NS, POL, ONCE>& L, const R* __restrict__ table,
                                           long long k, long long k_full, long long chunk) {
-  using Lanes = BlochLanes<R, PPL, FORM, NS, POL>;
+  using Lanes = BlochLanes<R, PPL, FORM, NS, POL, ONCE>;
   using Row = RowN<R, Lanes::kRow>;
   const Row* __restrict__ tab = reinterpret_cast<const Row*>(table);
   extern __shared__ unsigned char pd_lds[];
@@ -226,9 +251,9 @@ __device__ __forceinline__ void steps_lds(BlochLanes<R, PPL, FORM, NS, POL>& L, 
 
 // One tile of a Strang solve: the block's lanes own points base + q * blockDim.x,
 // q < PPL; steps [p.k_begin, p.k_end).
-template <typename R, int PPL, int STAGE, int FORM, int NS, int POL>
+template <typename R, int PPL, int STAGE, int FORM, int NS, int POL, int ONCE>
 __device__ __forceinline__ void strang_tile(const SolveParams& p, const long long base) {
-  using Lanes = BlochLanes<R, PPL, FORM, NS, POL>;
+  using Lanes = BlochLanes<R, PPL, FORM, NS, POL, ONCE>;
   using LY = Layout<NS>;
   constexpr int CX = 2 * LY::NX, CY = 2 * LY::NY;  // coefficient values per column / row
   constexpr int HALF = 2 * (LY::NY - 1);           // offset of the half-step pair in a row
@@ -271,10 +296,10 @@ __device__ __forceinline__ void strang_tile(const SolveParams& p, const long lon
       L.y[q] = (R)ry;
       L.z[q] = (R)0;
       // opening half step about y: per-point part, then (POL) the field part
-      rotate<FORM>(L.z[q], L.x[q], rowc[CY * c.j + HALF], rowc[CY * c.j + HALF + 1]);
+      rot<FORM, ONCE>(L.z[q], L.x[q], rowc[CY * c.j + HALF], rowc[CY * c.j + HALF + 1]);
       if (POL) {
         const R* open = table + (size_t)p.n_steps * Lanes::kRow + 2 * NS;
-        rotate<FORM>(L.z[q], L.x[q], open[0], open[1]);
+        rot<FORM, ONCE>(L.z[q], L.x[q], open[0], open[1]);
       }
     }
   }
@@ -331,9 +356,9 @@ __device__ __forceinline__ void strang_tile(const SolveParams& p, const long lon
   }
 }
 
-template <typename R, int PPL, int STAGE, int FORM, int NS, int POL>
+template <typename R, int PPL, int STAGE, int FORM, int NS, int POL, int ONCE>
 __global__ void __launch_bounds__(256) strang_kernel(const SolveParams p) {
-  strang_tile<R, PPL, STAGE, FORM, NS, POL>(p, (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x);
+  strang_tile<R, PPL, STAGE, FORM, NS, POL, ONCE>(p, (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -363,14 +388,19 @@ __global__ void __launch_bounds__(256) batch_kernel(const BatchSolve* __restrict
     const long long base = w.base + threadIdx.x;
     if (s.precision == PD_FP32) {
       if (s.form == kFormShear)
-        strang_tile<float, PPL, 0, kFormShear, 1, 0>(s.p, base);
+        strang_tile<float, PPL, 0, kFormShear, 1, 0, 1>(s.p, base);
       else
-        strang_tile<float, PPL, 0, kFormVersine, 1, 0>(s.p, base);
+        strang_tile<float, PPL, 0, kFormVersine, 1, 0, 1>(s.p, base);
+    } else if (s.precision == PD_FP32_FAST) {
+      if (s.form == kFormShear)
+        strang_tile<float, PPL, 0, kFormShear, 1, 0, 0>(s.p, base);
+      else
+        strang_tile<float, PPL, 0, kFormVersine, 1, 0, 0>(s.p, base);
     } else {
       if (s.form == kFormShear)
-        strang_tile<double, PPL, 0, kFormShear, 1, 0>(s.p, base);
+        strang_tile<double, PPL, 0, kFormShear, 1, 0, 0>(s.p, base);
       else
-        strang_tile<double, PPL, 0, kFormVersine, 1, 0>(s.p, base);
+        strang_tile<double, PPL, 0, kFormVersine, 1, 0, 0>(s.p, base);
     }
   }
 }
@@ -723,34 +753,37 @@ __global__ void __launch_bounds__(kRedThreads) batch_density_finish(const Densit
   }
 }
 
-template <typename R, int PPL, int FORM, int NS, int POL>
+template <typename R, int PPL, int FORM, int NS, int POL, int ONCE>
 hipError_t launch_strang(int block, const SolveParams& p, hipStream_t stream) {
   long long per_block = (long long)block * PPL;
   long long blocks = (p.npts + per_block - 1) / per_block;
   if (p.stage == 1) {
-    size_t lds = (size_t)p.chunk_steps * BlochLanes<R, PPL, FORM, NS, POL>::kRow * sizeof(R);
-    hipLaunchKernelGGL((strang_kernel<R, PPL, 1, FORM, NS, POL>), dim3((unsigned)blocks), dim3(block), lds, stream,
-                       p);
+    size_t lds = (size_t)p.chunk_steps * BlochLanes<R, PPL, FORM, NS, POL, ONCE>::kRow * sizeof(R);
+    hipLaunchKernelGGL((strang_kernel<R, PPL, 1, FORM, NS, POL, ONCE>), dim3((unsigned)blocks), dim3(block), lds,
+                       stream, p);
   } else {
-    hipLaunchKernelGGL((strang_kernel<R, PPL, 0, FORM, NS, POL>), dim3((unsigned)blocks), dim3(block), 0, stream, p);
+    hipLaunchKernelGGL((strang_kernel<R, PPL, 0, FORM, NS, POL, ONCE>), dim3((unsigned)blocks), dim3(block), 0,
+                       stream, p);
   }
   return hipGetLastError();
 }
 
-template <typename R, int FORM, int NS, int POL>
+template <typename R, int FORM, int NS, int POL, int ONCE>
 hipError_t strang_ppl(int ppl, int block, const SolveParams& p, hipStream_t stream) {
   switch (ppl) {
-    case 1: return launch_strang<R, 1, FORM, NS, POL>(block, p, stream);
-    case 2: return launch_strang<R, 2, FORM, NS, POL>(block, p, stream);
-    default: return launch_strang<R, 4, FORM, NS, POL>(block, p, stream);
+    case 1: return launch_strang<R, 1, FORM, NS, POL, ONCE>(block, p, stream);
+    case 2: return launch_strang<R, 2, FORM, NS, POL, ONCE>(block, p, stream);
+    default: return launch_strang<R, 4, FORM, NS, POL, ONCE>(block, p, stream);
   }
 }
 
-template <typename R, int FORM>
+template <typename R, int FORM, int ONCE>
 hipError_t strang_variant(int stages, int elliptic, int ppl, int block, const SolveParams& p, hipStream_t stream) {
   if (stages == 5)
-    return elliptic ? strang_ppl<R, FORM, 5, 1>(ppl, block, p, stream) : strang_ppl<R, FORM, 5, 0>(ppl, block, p, stream);
-  return elliptic ? strang_ppl<R, FORM, 1, 1>(ppl, block, p, stream) : strang_ppl<R, FORM, 1, 0>(ppl, block, p, stream);
+    return elliptic ? strang_ppl<R, FORM, 5, 1, ONCE>(ppl, block, p, stream)
+                    : strang_ppl<R, FORM, 5, 0, ONCE>(ppl, block, p, stream);
+  return elliptic ? strang_ppl<R, FORM, 1, 1, ONCE>(ppl, block, p, stream)
+                  : strang_ppl<R, FORM, 1, 0, ONCE>(ppl, block, p, stream);
 }
 
 template <typename R, int J, int PPL, int NS, int POL>
@@ -788,12 +821,15 @@ hipError_t launch_propagate(int scheme, int precision, int ppl, int block, int t
   const int S = (scheme == PD_SCHEME_STRANG4 || scheme == PD_SCHEME_MIDPOINT4) ? 5 : 1;
   if (base_scheme(scheme) == PD_SCHEME_STRANG) {
     if (precision == PD_FP32)
-      return p.form == kFormShear ? strang_variant<float, kFormShear>(S, elliptic, ppl, block, p, stream)
-                                  : strang_variant<float, kFormVersine>(S, elliptic, ppl, block, p, stream);
-    return p.form == kFormShear ? strang_variant<double, kFormShear>(S, elliptic, ppl, block, p, stream)
-                                : strang_variant<double, kFormVersine>(S, elliptic, ppl, block, p, stream);
+      return p.form == kFormShear ? strang_variant<float, kFormShear, 1>(S, elliptic, ppl, block, p, stream)
+                                  : strang_variant<float, kFormVersine, 0>(S, elliptic, ppl, block, p, stream);
+    if (precision == PD_FP32_FAST)
+      return p.form == kFormShear ? strang_variant<float, kFormShear, 0>(S, elliptic, ppl, block, p, stream)
+                                  : strang_variant<float, kFormVersine, 0>(S, elliptic, ppl, block, p, stream);
+    return p.form == kFormShear ? strang_variant<double, kFormShear, 0>(S, elliptic, ppl, block, p, stream)
+                                : strang_variant<double, kFormVersine, 0>(S, elliptic, ppl, block, p, stream);
   }
-  if (precision == PD_FP32) {
+  if (is_fp32(precision)) {
     switch (taylor) {
       case 3: return midpoint_variant<float, 3>(S, elliptic, ppl, block, p, stream);
       case 5: return midpoint_variant<float, 5>(S, elliptic, ppl, block, p, stream);
@@ -813,7 +849,7 @@ hipError_t launch_snapshot(int scheme, int precision, int elliptic, const SolveP
   if (base_scheme(scheme) == PD_SCHEME_STRANG) {
     const bool four = scheme == PD_SCHEME_STRANG4;
     const int row_stride = four ? 6 : 4, half_offset = four ? 4 : 2;
-    if (precision == PD_FP32) {
+    if (is_fp32(precision)) {
       if (elliptic)
         hipLaunchKernelGGL((strang_snapshot_kernel<float, 1>), dim3((unsigned)blocks), dim3(256), 0, stream, p, q,
                            half_offset, row_stride);
@@ -828,7 +864,7 @@ hipError_t launch_snapshot(int scheme, int precision, int elliptic, const SolveP
         hipLaunchKernelGGL((strang_snapshot_kernel<double, 0>), dim3((unsigned)blocks), dim3(256), 0, stream, p, q,
                            half_offset, row_stride);
     }
-  } else if (precision == PD_FP32) {
+  } else if (is_fp32(precision)) {
     hipLaunchKernelGGL((midpoint_snapshot_kernel<float>), dim3((unsigned)blocks), dim3(256), 0, stream, p, q);
   } else {
     hipLaunchKernelGGL((midpoint_snapshot_kernel<double>), dim3((unsigned)blocks), dim3(256), 0, stream, p, q);

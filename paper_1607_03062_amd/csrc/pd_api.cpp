@@ -191,7 +191,8 @@ pd_status pd_create_grid(int nx, int ny, double px_min, double px_max, double py
   if (!std::isfinite(px_min) || !std::isfinite(px_max) || !std::isfinite(py_min) || !std::isfinite(py_max) ||
       !(px_max > px_min) || !(py_max > py_min))
     return fail(PD_ERR_INVALID, "momentum ranges must be finite with max > min");
-  if (precision != PD_FP64 && precision != PD_FP32) return fail(PD_ERR_INVALID, "unknown precision %d", precision);
+  if (precision != PD_FP64 && precision != PD_FP32 && precision != PD_FP32_FAST)
+    return fail(PD_ERR_INVALID, "unknown precision %d", precision);
   if (scheme != PD_SCHEME_STRANG && scheme != PD_SCHEME_MIDPOINT && scheme != PD_SCHEME_STRANG4 &&
       scheme != PD_SCHEME_MIDPOINT4)
     return fail(PD_ERR_INVALID, "unknown scheme %d", scheme);
@@ -210,7 +211,7 @@ pd_status pd_create_grid(int nx, int ny, double px_min, double px_max, double py
   // Default launch shape (fastest measured on MI355X for the 2048^2 x 80000
   // workload): field rows read by the scalar unit, 256-thread blocks, one point
   // per lane in FP32 and four in FP64.
-  g->points_per_lane = precision == PD_FP32 ? 1 : 4;
+  g->points_per_lane = is_fp32(precision) ? 1 : 4;
   g->block_threads = 256;
   g->table_stage = 2;
   g->chunk_steps = 512;
@@ -344,7 +345,7 @@ size_t pd_solve_bytes(pd_grid g, long long n_steps) {
   auto align = [](size_t n) { return (n + 255) / 256 * 256; };
   size_t table = (size_t)table_rows(g->scheme, 0, n_steps) * table_row_bytes(g->scheme, g->precision, 0);
   if (base_scheme(g->scheme) == PD_SCHEME_STRANG) {
-    const size_t v = g->precision == PD_FP32 ? sizeof(float) : sizeof(double);
+    const size_t v = is_fp32(g->precision) ? sizeof(float) : sizeof(double);
     size_t col = align(table);
     size_t row = align(col + 2 * point_coefficient_pairs_x(g->scheme) * v * (size_t)g->grid.nx);
     table = align(row + 2 * point_coefficient_pairs_y(g->scheme) * v * (size_t)g->grid.ny);
@@ -378,7 +379,7 @@ pd_status pd_set_launch(pd_grid g, int points_per_lane, int block_threads, int t
   if (table_stage != 0 && table_stage != 1 && table_stage != 2)
     return fail(PD_ERR_INVALID, "table_stage must be 1 (LDS) or 2 (scalar)");
   if (chunk_steps != 0) {
-    int max_chunk = g->precision == PD_FP32 ? 1024 : 4096;
+    int max_chunk = is_fp32(g->precision) ? 1024 : 4096;
     if (chunk_steps < 64 || chunk_steps > max_chunk || (chunk_steps & (chunk_steps - 1)) != 0)
       return fail(PD_ERR_INVALID, "chunk_steps must be a power of two in [64, %d]", max_chunk);
   }

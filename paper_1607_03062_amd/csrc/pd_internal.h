@@ -20,6 +20,8 @@ struct Composition {
   double cmax = 1;  // max |c_j|
 };
 Composition composition_of(int scheme);
+// FP32 state (PD_FP32 or PD_FP32_FAST)
+inline bool is_fp32(int precision) { return precision == PD_FP32 || precision == PD_FP32_FAST; }
 // PD_SCHEME_STRANG / STRANG4 -> PD_SCHEME_STRANG, MIDPOINT / MIDPOINT4 -> PD_SCHEME_MIDPOINT
 inline int base_scheme(int scheme) { return scheme == PD_SCHEME_MIDPOINT || scheme == PD_SCHEME_MIDPOINT4 ? PD_SCHEME_MIDPOINT : PD_SCHEME_STRANG; }
 
@@ -206,7 +208,7 @@ struct pd_grid_s {
     return b;
   }
   size_t state_bytes() const {
-    size_t v = precision == PD_FP32 ? sizeof(float) : sizeof(double);
+    size_t v = pdx::is_fp32(precision) ? sizeof(float) : sizeof(double);
     return (size_t)grid.points() * pdx::state_values_per_point(scheme) * v;
   }
   double density_scale() const;

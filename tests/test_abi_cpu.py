@@ -295,3 +295,14 @@ def test_snapshot_and_valley_state_errors_without_device():
         s.snapshot()
     assert e.value.status == _lib.PD_ERR_STATE
     s.close()
+
+
+def test_precision_values():
+    """PD_FP32_FAST is an FP32 form (4-byte state); anything past it is rejected."""
+    for prec, size in (("fp64", 8), ("fp32", 4), ("fp32fast", 4)):
+        s = pd.Solver(10, 7, (-1, 1), (-1, 1), prec)
+        assert s.state_bytes() == 10 * 7 * 3 * size
+        assert s.info()["precision"] == _lib.PRECISIONS[prec] and s.info()["points_per_lane"] == (4 if size == 8 else 1)
+        s.close()
+    h = _lib._vp()
+    assert _lib.load().pd_create_grid(8, 8, -1.0, 1.0, -1.0, 1.0, 3, 0, ctypes.byref(h)) == _lib.PD_ERR_INVALID

@@ -22,7 +22,7 @@ def members(pd, mix_precision=True, count=10):
     cfgs.append(extra)
     solvers = []
     for q, c in enumerate(cfgs):
-        prec = ("fp32" if q % 2 else "fp64") if mix_precision else c["precision"]
+        prec = ("fp64", "fp32", "fp32fast")[q % 3] if mix_precision else c["precision"]
         s = pd.Solver.for_grid(c["grid"], prec)
         s.set_field(c["field"], c["n_steps"])
         solvers.append((c, s))
@@ -166,3 +166,36 @@ def test_single_grid_autotune_and_cache(gpu, tmp_path, monkeypatch):
         shape["points_per_lane"], shape["block_threads"], shape["table_stage"], shape["chunk_steps"])
     s.close()
     s2.close()
+
+
+def test_config4_full_batch(gpu):
+    """The 64 seeded solves of the batch workload (grids 256^2..2048^2, 5k-80k steps, FP32 form,
+    autotuned), one graph-captured launch: every member equals its solve alone bit for bit and
+    matches the FP64 oracle on its own 64 x 64 subsample within 1e-5."""
+    cfgs = wl.config4()
+    solvers = []
+    for c in cfgs:
+        s = gpu.Solver.for_grid(c["grid"], c["precision"])
+        s.set_field(c["field"], c["n_steps"])
+        solvers.append(s)
+    b = gpu.Batch(solvers)
+    b.autotune()
+    print("config4: %d solves, %.3e point-steps, launch %s" % (len(b), b.info()["point_steps"], b.info()),
+          flush=True)
+    rho = b.run()
+    in_batch = [member_n(s) for s in solvers]
+    worst = 0.0
+    for q, (c, s) in enumerate(zip(cfgs, solvers)):
+        n0, r0 = alone(s)
+        assert np.array_equal(in_batch[q][0], n0) and rho[q] == r0, c["name"]
+        idx = wl.subsample_indices(c["grid"]["nx"], 64)
+        n_o = oracle.solve_grid(c["field"], c["grid"], c["n_steps"], idx=idx)[0]
+        err = float(np.max(np.abs(n0[idx] - n_o)))
+        worst = max(worst, err)
+        assert err <= 1e-5, (c["name"], err)
+        if q % 16 == 15:
+            print("config4: %d members checked, worst %.3e" % (q + 1, worst), flush=True)
+    print("config4: worst per-point error on the subsamples %.3e" % worst, flush=True)
+    b.close()
+    for s in solvers:
+        s.close()
