@@ -273,15 +273,18 @@ void pd_destroy_grid(pd_grid g);
    applied without timing, and a newly timed one is appended. */
 pd_status pd_autotune(pd_grid g, long long trial_steps, int use_cache, void* stream);
 
-/* ---- Batches: many Strang solves in one persistent launch ----------------
+/* ---- Batches: many solves in one launch sequence ---------------------------
 
-   A batch holds grids (any sizes, fields, step counts and precisions, each with
-   its field set).  Its launch is one persistent kernel: each block takes the
-   next work item -- one tile of block_threads * points_per_lane points of one
-   grid -- from a device counter until none is left; the items of the grids with
-   the most steps come first.  Every item does the same arithmetic as the
-   single-grid kernel with the scalar-unit table path, so each grid's n(p) and
-   rho are bit-identical to its solve alone.  Densities of the grids that finish
+   A batch holds grids (any sizes, schemes, fields, step counts, precisions and
+   valleys, each with its field set).  Its second-order Strang members with
+   fields along x share one persistent kernel: each block takes the next work
+   item -- one tile of block_threads * points_per_lane points of one grid -- from
+   a device counter until none is left; the items of the grids with the most
+   steps come first.  Every item does the same arithmetic as the single-grid
+   kernel with the scalar-unit table path.  The other members (fourth-order or
+   midpoint schemes, fields with a y component) run their own single-solve
+   launches, with their own launch shapes, right after it in the same sequence.
+   Each grid's n(p) and rho are therefore bit-identical to its solve alone.  Densities of the grids that finish
    are reduced in the same launch sequence (per grid, same fixed order as
    pd_density).  Grids must stay alive while they are members and must not be
    used with pd_propagate while a batch call on them is in flight. */
@@ -293,14 +296,13 @@ typedef struct {
   int block_threads;
   int graph_captured;     /* 1 if the whole-solve launch is captured and current */
   int work_items;         /* items of the last launch */
+  int separate_launches;  /* members of the last launch run by their own kernel */
   long long n_points;     /* sum over members */
   double point_steps;     /* sum over members of points x N */
 } pd_batch_info;
 
 pd_status pd_batch_create(pd_batch* out);
-/* Add a PD_SCHEME_STRANG grid (PD_ERR_UNSUPPORTED for the other schemes; a
-   member whose field has a y component makes pd_batch_run and pd_batch_step
-   return PD_ERR_UNSUPPORTED). */
+/* Add a grid (any scheme); PD_ERR_INVALID if it is already a member. */
 pd_status pd_batch_add(pd_batch b, pd_grid g);
 /* Remove one member (PD_ERR_INVALID if it is not one); remove a grid from every
    batch before destroying it.  Neither call touches the grids themselves. */

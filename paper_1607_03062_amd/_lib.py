@@ -144,6 +144,7 @@ class pd_batch_info(ctypes.Structure):
         ("block_threads", ctypes.c_int),
         ("graph_captured", ctypes.c_int),
         ("work_items", ctypes.c_int),
+        ("separate_launches", ctypes.c_int),
         ("n_points", ctypes.c_longlong),
         ("point_steps", ctypes.c_double),
     ]
@@ -358,7 +359,8 @@ class Solver:
 
 
 class Batch:
-    """Many Strang solves in one persistent launch (pd_batch handle).  Member
+    """Many solves in one launch sequence (pd_batch handle): second-order Strang
+    members share a persistent kernel, the others run their own launches.  Member
     Solvers must stay alive while they are in the batch."""
 
     def __init__(self, solvers=()):

@@ -1,5 +1,7 @@
-// Batched Strang solves (declared and documented in include/pd.h): many grids,
-// of any size, field, step count and precision, in one persistent launch.
+// Batched solves (declared and documented in include/pd.h): many grids, of any
+// size, field, step count and precision.  Second-order Strang solves of fields
+// without a y component share one persistent launch; every other member runs its
+// own single-solve launch in the same enqueued (and captured) sequence.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -44,6 +46,7 @@ struct pd_batch_s {
   std::vector<long long> graph_versions;
   int graph_ppl = 0, graph_block = 0;
   int n_items_last = 0;
+  int n_separate_last = 0;
 };
 
 namespace {
@@ -99,8 +102,12 @@ struct Plan {
   std::vector<BatchSolve> solves;
   std::vector<BatchItem> items;
   std::vector<DensityJob> jobs;
+  std::vector<std::pair<size_t, SolveParams>> separate;  // members run by their own launch
   long long density_tiles = 0;
 };
+
+// Members the persistent kernel runs: second-order Strang, no y component.
+bool persistent_member(pd_grid g) { return g->scheme == PD_SCHEME_STRANG && !g->field.elliptic; }
 
 // Descriptors for advancing member i over steps [begin[i], end[i]) (no work
 // where begin == end); jobs for the members whose end reaches their last step.
@@ -119,7 +126,12 @@ pd_status make_plan(pd_batch b, const std::vector<long long>& begin, const std::
     plan->solves[i].p.stage = 0;  // the persistent kernel reads field rows with the scalar unit
     plan->solves[i].precision = g->precision;
     plan->solves[i].form = g->form;
-    if (begin[i] < end[i]) order.push_back(i);
+    if (begin[i] < end[i]) {
+      if (persistent_member(g))
+        order.push_back(i);
+      else
+        plan->separate.emplace_back(i, g->solve_params(begin[i], end[i], st));  // its own launch shape
+    }
   }
   // Longest first: every tile of a solve costs (end - begin) steps per point.
   std::stable_sort(order.begin(), order.end(),
@@ -187,6 +199,13 @@ pd_status enqueue(pd_batch b, const Plan& plan, hipStream_t stream) {
                      (int)plan.items.size(), b->d_counter, stream);
     if (e != hipSuccess) return hip_error(e, "batch launch");
   }
+  // the other members: the single-solve kernels, exactly as a solve alone
+  for (const auto& m : plan.separate) {
+    pd_grid g = b->grids[m.first];
+    e = launch_propagate(g->scheme, g->precision, g->points_per_lane, g->block_threads, g->taylor,
+                         g->field.elliptic ? 1 : 0, m.second, stream);
+    if (e != hipSuccess) return hip_error(e, "member launch");
+  }
   e = launch_batch_density(b->d_jobs, (int)plan.jobs.size(), plan.density_tiles, stream);
   if (e != hipSuccess) return hip_error(e, "batch density launch");
   return PD_OK;
@@ -196,8 +215,6 @@ pd_status check_members(pd_batch b) {
   if (b->grids.empty()) return set_error(PD_ERR_STATE, "empty batch");
   for (pd_grid g : b->grids) {
     if (!g->field_set) return set_error(PD_ERR_STATE, "a member grid has no field");
-    if (g->field.elliptic)
-      return set_error(PD_ERR_UNSUPPORTED, "batches run linearly polarised fields only (a member has A_y)");
     if (g->device != b->device) return set_error(PD_ERR_INVALID, "member grids are on different devices");
   }
   return PD_OK;
@@ -245,7 +262,6 @@ pd_status pd_batch_create(pd_batch* out) {
 
 pd_status pd_batch_add(pd_batch b, pd_grid g) {
   if (!b || !g) return set_error(PD_ERR_INVALID, "null handle");
-  if (g->scheme != PD_SCHEME_STRANG) return set_error(PD_ERR_UNSUPPORTED, "batches run Strang solves only");
   if (std::find(b->grids.begin(), b->grids.end(), g) != b->grids.end())
     return set_error(PD_ERR_INVALID, "grid already in the batch");
   b->grids.push_back(g);
@@ -336,6 +352,7 @@ pd_status pd_batch_run(pd_batch b, double* rho_out, void* stream) {
     b->graph_ppl = b->points_per_lane;
     b->graph_block = b->block_threads;
     b->n_items_last = (int)plan.items.size();
+    b->n_separate_last = (int)plan.separate.size();
   }
   hipError_t e = hipGraphLaunch(b->exec, st);
   if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
@@ -365,6 +382,7 @@ pd_status pd_batch_step(pd_batch b, long long max_steps, double* rho_out, int* f
   if ((s = upload(b, plan, st)) != PD_OK) return s;
   if ((s = enqueue(b, plan, st)) != PD_OK) return s;
   b->n_items_last = (int)plan.items.size();
+  b->n_separate_last = (int)plan.separate.size();
   std::vector<char> completed(n, 0);
   for (size_t i = 0; i < n; ++i) {
     completed[i] = begin[i] < end[i] && end[i] == b->grids[i]->field.n_steps;
@@ -383,6 +401,7 @@ pd_status pd_batch_get_info(pd_batch b, pd_batch_info* out) {
   out->block_threads = b->block_threads;
   out->graph_captured = graph_current(b) ? 1 : 0;
   out->work_items = b->n_items_last;
+  out->separate_launches = b->n_separate_last;
   for (pd_grid g : b->grids) {
     out->n_points += g->grid.points();
     out->point_steps += (double)g->grid.points() * (double)g->field.n_steps;

@@ -156,21 +156,52 @@ def test_elliptic_strang_shapes_lds_and_chunks(gpu, precision):
     assert np.array_equal(n, ref[0]) and rho == ref[1]
 
 
-def test_batch_rejects_elliptic_member(gpu):
-    s = gpu.Solver.for_grid(RAGGED, "fp32", "strang")
-    s.set_field(ELL, 500)
-    b = gpu.Batch([s])
-    with pytest.raises(gpu.PDError) as e:
-        b.run()
-    assert e.value.status == 5
+def test_batch_runs_every_variant(gpu):
+    """A batch of every scheme, field polarisation, precision and valley: the second-order
+    linear-field Strang members share the persistent kernel, the others run their own launches;
+    every member equals its solve alone bit for bit, for a whole run and for epochs."""
+    specs = [("strang", "fp32", "both", F1, 1500), ("strang", "fp64", "K-", F1, 1300),
+             ("strang", "fp32", "both", ELL, 1400), ("strang4", "fp32", "both", F1, 500),
+             ("midpoint", "fp64", "both", F1, 1200), ("midpoint4", "fp64", "K-", ELL, 400),
+             ("strang4", "fp32fast", "K+", ELL, 450), ("midpoint", "fp32", "both", PULSE_ELL, 1700)]
+    members = []
+    for scheme, prec, valley, field, N in specs:
+        s = gpu.Solver.for_grid(RAGGED, prec, scheme, valley)
+        s.set_field(field, N)
+        members.append(s)
+    npts = RAGGED["nx"] * RAGGED["ny"]
+
+    def alone(s):
+        s.rewind()
+        s.propagate(-1)
+        n = np.empty(npts)
+        return n, s.density(n_out=n)
+
+    ref = [alone(s) for s in members]
+    b = gpu.Batch(members)
+    rho = b.run()
+    info = b.info()
+    assert info["separate_launches"] == 6 and info["work_items"] > 0
+    for q, s in enumerate(members):
+        n = np.empty(npts)
+        r = s.density(n_out=n)
+        assert np.array_equal(n, ref[q][0]) and r == ref[q][1] == rho[q], specs[q][:3]
+    # epochs of 333 steps
+    for s in members:
+        s.rewind()
+    done = np.zeros(len(members), dtype=bool)
+    got = np.full(len(members), np.nan)
+    while not done.all():
+        r, fin = b.step(333)
+        got[~np.isnan(r)] = r[~np.isnan(r)]
+        done = fin
+    for q, s in enumerate(members):
+        n = np.empty(npts)
+        s.density(n_out=n)
+        assert np.array_equal(n, ref[q][0]) and got[q] == ref[q][1], ("epochs", specs[q][:3])
     b.close()
-    s.close()
-    s4 = gpu.Solver.for_grid(RAGGED, "fp32", "strang4")
-    b = gpu.Batch()
-    with pytest.raises(gpu.PDError):
-        b.add(s4)
-    b.close()
-    s4.close()
+    for s in members:
+        s.close()
 
 
 # ---------------------------------------------------------------------------
