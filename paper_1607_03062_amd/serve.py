@@ -1,10 +1,11 @@
 """Continuous-batching solve server.
 
-Requests (a grid, a field, a step count and a precision) arrive over time.  The
-server keeps a set of active solves on the device and runs them in epochs: each
-epoch advances every active solve by up to `epoch_steps` steps in one batched
-persistent launch (pd_batch_step), with every solve's state resident in device
-memory between epochs.  Solves that reach their last step are projected and
+Requests (a grid, a field, a step count, a precision, a scheme and a valley)
+arrive over time.  The server keeps a set of active solves on the device and runs
+them in epochs: each epoch advances every active solve by up to `epoch_steps`
+steps in one batched launch sequence (pd_batch_step: one persistent kernel for
+the second-order Strang solves of fields along x, the others' own launches after
+it), with every solve's state resident in device memory between epochs.  Solves that reach their last step are projected and
 reduced in the same epoch and leave the set; arrivals are admitted between
 epochs, in arrival order, while their device footprint (tables, state, n(p),
 partials; pd_info.solve_bytes) fits in the memory budget.  A request larger than
@@ -34,6 +35,7 @@ class Request:
     n_steps: int
     precision: str = "fp32"
     scheme: str = "strang"
+    valley: str = "both"
     # filled by the server
     admitted_s: float = float("nan")
     done_s: float = float("nan")
@@ -57,13 +59,16 @@ class Request:
     @classmethod
     def from_workload(cls, w: dict) -> "Request":
         return cls(name=w["name"], arrival_s=float(w.get("arrival_s", 0.0)), grid=w["grid"], field=w["field"],
-                   n_steps=int(w["n_steps"]), precision=w.get("precision", "fp32"), scheme=w.get("scheme", "strang"))
+                   n_steps=int(w["n_steps"]), precision=w.get("precision", "fp32"), scheme=w.get("scheme", "strang"),
+                   valley=w.get("valley", "both"))
 
 
 class GpuExecutor:
     """Active solves as pd_grid handles in one pd_batch."""
 
     def __init__(self, pd, stream=None, points_per_lane: int = 0, block_threads: int = 0, keep_n: bool = False):
+        """Every scheme, precision, field and valley is served; second-order Strang requests
+        with fields along x share the batch's persistent kernel (see pd_batch)."""
         self.pd = pd
         self.stream = stream
         self.batch = pd.Batch()
@@ -76,7 +81,7 @@ class GpuExecutor:
         self.n_results = {}
 
     def footprint(self, req: Request) -> int:
-        s = self.pd.Solver.for_grid(req.grid, req.precision, req.scheme)
+        s = self.pd.Solver.for_grid(req.grid, req.precision, req.scheme, req.valley)
         try:
             return s.solve_bytes(req.n_steps)
         finally:
@@ -84,7 +89,7 @@ class GpuExecutor:
 
     def admit(self, req: Request):
         """Raises PDError if the library refuses the request (e.g. the step-size condition)."""
-        s = self.pd.Solver.for_grid(req.grid, req.precision, req.scheme)
+        s = self.pd.Solver.for_grid(req.grid, req.precision, req.scheme, req.valley)
         try:
             s.set_field(req.field, req.n_steps)
         except Exception:

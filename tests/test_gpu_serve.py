@@ -12,6 +12,14 @@ pytestmark = pytest.mark.gpu
 
 def test_results_in_the_mix_equal_alone(gpu):
     ws = wl.config5(count=14, seed=5, rate_per_s=400.0, sizes=(64, 96, 128, 192), step_range=(800, 5000))
+    # a few requests of the other schemes, precisions, polarisations and valleys in the stream
+    extras = [("strang4", "fp32", "both", 0.0), ("midpoint", "fp64", "K-", 0.6), ("strang", "fp32fast", "K+", 0.8),
+              ("midpoint4", "fp32", "both", 0.0)]
+    for q, (scheme, prec, valley, e) in enumerate(extras):
+        w = ws[3 * q + 1]
+        w.update(scheme=scheme, precision=prec, valley=valley, field=dict(w["field"], ellipticity=e))
+        if scheme.endswith("4"):
+            w["n_steps"] = max(200, w["n_steps"] // 5)
     reqs = [serve.Request.from_workload(w) for w in ws]
     ex = serve.GpuExecutor(gpu, keep_n=True)
     fp = [ex.footprint(r) for r in reqs]
@@ -21,7 +29,7 @@ def test_results_in_the_mix_equal_alone(gpu):
     assert st.completed == len(reqs) and st.peak_bytes <= budget
     assert any(r.admitted_s > r.arrival_s + 1e-4 for r in reqs)
     for r in reqs:
-        s = gpu.Solver.for_grid(r.grid, r.precision)
+        s = gpu.Solver.for_grid(r.grid, r.precision, r.scheme, r.valley)
         s.set_field(r.field, r.n_steps)
         s.propagate(-1)
         n = np.empty(s.nx * s.ny)
