@@ -254,8 +254,10 @@ pd_status pd_bind_state(pd_grid g, void* dev_ptr, size_t bytes);
    field rows are staged through LDS in time chunks (read from VGPRs), 2 = read
    directly by the scalar unit (SGPR operands); chunk_steps = LDS chunk length,
    a power of two in [64, 4096] (at most 1024 in the FP32 form, whose
-   renormalisation period it must divide).  0 keeps the current value.  Results
-   do not depend on the launch shape (bit for bit). */
+   renormalisation period it must divide); a solve whose chunk of rows would
+   exceed 64 KiB of LDS (long rows: fourth order, y component) reads them with the
+   scalar unit instead.  0 keeps the current value.  Results do not depend on the
+   launch shape (bit for bit). */
 pd_status pd_set_launch(pd_grid g, int points_per_lane, int block_threads, int table_stage, int chunk_steps);
 
 pd_status pd_get_info(pd_grid g, pd_info* out);

@@ -284,6 +284,26 @@ def test_snapshots_match_oracle(gpu, scheme, precision, field):
     s.close()
 
 
+def test_snapshot_of_batch_members_between_epochs(gpu):
+    """Batch epochs keep each member's state in its own buffer, so a member's snapshot between
+    epochs is the oracle's occupation at that step (persistent-kernel and own-launch members)."""
+    members = []
+    for scheme, prec, field, N in (("strang", "fp64", F1, 1800), ("midpoint4", "fp64", ELL, 500)):
+        s = gpu.Solver.for_grid(RAGGED, prec, scheme)
+        s.set_field(field, N)
+        members.append((s, scheme, field, N))
+    b = gpu.Batch([m[0] for m in members])
+    b.step(333)
+    for s, scheme, field, N in members:
+        n = np.empty(RAGGED["nx"] * RAGGED["ny"])
+        s.snapshot(n_out=n)
+        n_o = oracle.snapshot_grid(field, RAGGED, N, 333, scheme)[0]
+        assert np.max(np.abs(n - n_o)) <= 5e-12, scheme
+    b.close()
+    for m in members:
+        m[0].close()
+
+
 def test_snapshot_landau_zener(gpu):
     """Constant field E0 = 0.2: the instantaneous occupation at t = 150 is already the Landau-Zener
     value for 2 <= p_x < 4."""
