@@ -5,9 +5,10 @@ momentum grid on [-2,2]^2 under the sin^2 pulse (E0 = 0.1, omega = 0.5, 30
 cycles), 80000 Strang steps (state init, propagation, projection on u_out,
 density reduction and the copy of rho to the host).  The field table is
 resident in HBM before the timed region (pd_set_field once, pd_rewind per
-step).  The FP64 form of the same workload is timed beside it, and both are
-checked against the FP64 CPU oracle on the 64 x 64 subsample (stride 32),
-whose run is also the CPU baseline.
+step).  The FP64 form and the fast FP32 form (plain shears, PD_FP32_FAST) of the
+same workload are timed beside it, and all are checked against the FP64 CPU
+oracle on the 64 x 64 subsample (stride 32) and on the larger sample whose
+oracle run is also the CPU baseline.
 
     python bench.py [--steps K] [--warmup W] [--precision fp32|fp64]
 """

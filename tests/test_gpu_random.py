@@ -1,6 +1,6 @@
 """Seeded random configurations on the GPU against the oracle: grid shapes down to
-1 x 1, every field kind with and without a y component, all schemes, both
-precisions and valleys, random launch shapes, chunked solves and snapshots.
+1 x 1, every field kind with and without a y component, all schemes, all three
+precisions, both valleys, random launch shapes, chunked solves and snapshots.
 Each case prints its parameters before it runs.  Tolerances as in
 test_gpu_parity (FP64 1e-12, FP32 1e-5 per point)."""
 import math
@@ -62,6 +62,8 @@ def draw_case(seed):
     n_chunks = int(rng.integers(1, 4))
     cuts = sorted(set(int(c) for c in rng.integers(1, N + 1, size=n_chunks - 1))) if N > 1 else []
     chunks = [b - a for a, b in zip([0] + cuts, cuts + [N]) if b > a]
+    if precision == "fp32" and seed % 2:
+        precision = "fp32fast"  # (chosen after the draws, which stay as they were)
     return dict(grid=grid, field=field, N=N, scheme=scheme, precision=precision, valley=valley, ppl=ppl,
                 block=block, stage=stage, chunk=chunk, chunks=chunks)
 
