@@ -42,19 +42,27 @@ def algo(info: dict, precision: str):
     fourth-order step is `stages` = 5 second-order stages.
     Strang stage: three rotations (ALGO), a fourth one (the field part of the y
     rotation) when the field has a y component.
-    Midpoint stage with Taylor order J: phase X = c dt(px + A) (1 add) and x = X^2 + Y^2
-    (1 fma) in FP64; cos - 1 (J - 1 fma + 1 mul) and sin(x)/x (J fma); alpha, beta (2 mul);
-    the 2x2 update: FP64 3 fma per component (24 flop, 12 instr), FP32 mul + 2 fma + add
-    per component (24 flop, 16 instr) plus 3 conversions; a y component adds Y = Y0 + dy
-    and Y^2 (2 flop, 2 instr)."""
+    Midpoint stage, phase X = c dt(px + A) (1 add, FP64) and x = X^2 + Y^2 (1 fma):
+      tangent form (rotation_form 0), J series terms: tan(x)/x - 1 (J - 2 fma + 1 mul),
+      alpha, beta (2 fma), the update mul + fma + add per component (16 flop, 12 instr);
+      in FP32 plus the conversion of X (x is formed in FP32);
+      cosine form (rotation_form 1), order J: cos - 1 (J - 1 fma + 1 mul) and sin(x)/x
+      (J fma), alpha, beta (2 mul), the update: FP64 3 fma per component (24 flop, 12
+      instr), FP32 mul + 2 fma + add per component (24 flop, 16 instr) plus 3 conversions.
+    A y component adds Y = Y0 + dy and Y^2 (2 flop; 2 instr, 3 in FP32 tangent form)."""
     stages = info.get("stages", 1) or 1
     ell = info.get("elliptic", 0)
     if info["scheme"] in (0, 2):
         f, i = ALGO[(info["rotation_form"], precision)]
         return stages * f * (4 if ell else 3) // 3, stages * i * (4 if ell else 3) // 3
     J = info["taylor_order"]
-    flops = 3 + (2 * (J - 1) + 1) + 2 * J + 2 + 24 + (2 if ell else 0)
-    instr = 2 + 2 * J + 2 + (12 if precision == "fp64" else 16 + 3) + (2 if ell else 0)  # fp32fast runs as fp32
+    f32 = precision != "fp64"  # fp32fast runs as fp32
+    if info["rotation_form"] == 0:
+        flops = 3 + (2 * (J - 2) + 1) + 4 + 16 + (2 if ell else 0)
+        instr = 2 + (J - 1) + 2 + 12 + (1 if f32 else 0) + ((3 if f32 else 2) if ell else 0)
+    else:
+        flops = 3 + (2 * (J - 1) + 1) + 2 * J + 2 + 24 + (2 if ell else 0)
+        instr = 2 + 2 * J + 2 + (16 + 3 if f32 else 12) + (2 if ell else 0)
     return stages * flops, stages * instr
 # MI355X vector peaks from its unit counts and clock (256 CU, 2.4 GHz): FP64
 # issues 64 lanes per clock per CU (78.6 TFLOP/s with FMA); unpacked FP32 with

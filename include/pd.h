@@ -149,8 +149,12 @@ typedef struct {
   int table_stage;          /* 1 = LDS chunks, 2 = scalar-unit reads */
   int chunk_steps;
   int rotation_form;        /* Strang: 0 = three shears per rotation (every rotation angle of the
-                               solve <= pi/2), 1 = versine form (h = cos - 1, s = sin) */
-  int taylor_order;         /* midpoint: terms J of the series of cos - 1 and sin(x)/x in x = (dt E)^2 */
+                               solve <= pi/2), 1 = versine form (h = cos - 1, s = sin).
+                               Midpoint: 0 = tangent form (the step divided by cos(dt E), one
+                               series; chosen when the state's growth over 1024 steps stays
+                               below 2^32), 1 = cosine form (cos - 1 and sin(x)/x) */
+  int taylor_order;         /* midpoint: terms J of the series (tan(x)/x, or cos - 1 and
+                               sin(x)/x) in x = (c dt E)^2 */
   size_t device_bytes;      /* device memory the handle owns */
   size_t solve_bytes;       /* device memory a solve of this field needs, chunk state included:
                                tables + n(p) + density partials + state (for admission control) */

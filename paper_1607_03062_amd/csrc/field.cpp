@@ -445,14 +445,24 @@ int strang_form(const Grid& g, const FieldTables& t) {
   return phi <= kShearMaxAngle ? kFormShear : kFormVersine;
 }
 
-int taylor_order(double x_max, int precision) {
+int taylor_order(double x_max, int precision, int form) {
   // Orders compiled into the midpoint kernels.
-  static const int kOrders64[] = {5, 8, 14};
-  static const int kOrders32[] = {3, 5, 9};
-  const int* orders = is_fp32(precision) ? kOrders32 : kOrders64;
-  double tol = is_fp32(precision) ? 0x1p-27 : 0x1p-56;
+  static const int kCos64[] = {5, 8, 14};
+  static const int kCos32[] = {3, 5, 9};
+  static const int kTan64[] = {5, 7, 10};
+  static const int kTan32[] = {2, 3, 5};
+  const bool f32 = is_fp32(precision);
+  const int* orders = form == kMidTangent ? (f32 ? kTan32 : kTan64) : (f32 ? kCos32 : kCos64);
+  double tol = f32 ? 0x1p-27 : 0x1p-56;
   for (int q = 0; q < 3; ++q) {
     int J = orders[q];
+    if (form == kMidTangent) {
+      // a_n > 0 and a_{n+1} / a_n < 4 / pi^2, so the omitted terms sum to at most
+      // a_{J+1} x^J / (1 - 4 x / pi^2), relative to tan(x)/x >= 1
+      double r = 4.0 * x_max / (kPi * kPi);
+      if (r < 1.0 && tan_series_coef(J + 1) * std::pow(x_max, J) / (1.0 - r) <= tol) return J;
+      continue;
+    }
     // relative size of the first omitted terms: 2 x^J / (2J+2)! for cos - 1 and
     // x^(J+1) / (2J+3)! for sin(x)/x
     double f = 1.0;
@@ -462,6 +472,16 @@ int taylor_order(double x_max, int precision) {
     if (e1 <= tol && e2 <= tol) return J;
   }
   return -1;
+}
+
+int midpoint_form(const FieldTables& t, int precision) {
+  // every stage angle is at most theta = cmax dt E_max; a step of S stages grows
+  // the state by at most (1 / cos theta)^S
+  const double theta = t.comp.cmax * t.dt * t.E_max;
+  if (!(theta < 0.5 * kPi)) return kMidCosine;
+  const double growth_log2 = (double)kRenormEvery * t.comp.stages * -std::log2(std::cos(theta));
+  if (growth_log2 > 32.0) return kMidCosine;
+  return taylor_order(theta * theta, precision, kMidTangent) > 0 ? kMidTangent : kMidCosine;
 }
 
 }  // namespace pdx

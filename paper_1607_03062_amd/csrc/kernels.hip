@@ -28,8 +28,13 @@
 //
 // Midpoint scheme (Sec. III, Eq. (13)): per step the closed 2x2 form
 //   U = cos(dt E) I - i sigma.P sin(dt E) / E,  P = p + A_k,
-// acting on the spinor (a1 + i b1, a2 + i b2); cos - 1 and sin(x)/x are even
-// Taylor series in x = (dt E)^2 of an order chosen by the host.
+// acting on the spinor (a1 + i b1, a2 + i b2).  For the small step angles of
+// most solves the kernel applies U / cos(dt E) = I - i tan(dt E) sigma.P / E, one
+// even series (tan(x)/x) instead of two and one rounding per component; the
+// state's norm then grows by 1 / cos(dt E) per step and is renormalised every
+// kRenormEvery steps (n divides it out).  Otherwise cos - 1 and sin(x)/x are
+// evaluated.  The series are Taylor series in x = (dt E)^2 of an order chosen
+// by the host.
 //
 // Both kernels are templated on the composition (NS = 1 second-order step, or
 // NS = 5 stages of Suzuki's fourth-order composition, each a second-order step
@@ -44,8 +49,6 @@
 
 namespace pdx {
 namespace {
-
-constexpr long long kRenormEvery = 1024;  // FP32 form: renormalise after every 1024th step
 
 // Rotation of (u, v) by phi: u' = u cos - v sin, v' = u sin + v cos.
 // Shear form, t = tan(phi/2), s = sin(phi): u -= t v; v += s u; u -= t v.
@@ -473,6 +476,34 @@ __device__ __forceinline__ void midpoint_update(float& a1, float& b1, float& a2,
   b2 += db2;
 }
 
+// tan(sqrt x) / sqrt x - 1 = sum_{n=2}^{J} a_n x^(n-1) (coefficients from tan' = 1 + tan^2).
+// The 1 is left out so that the rounding of the sum is relative to its own small
+// size; the caller adds it exactly, as (al, be) = fma(tau - 1, (X, Y), (X, Y)).
+template <int J>
+struct TanSeries {
+  template <typename R>
+  __device__ __forceinline__ static R minus1(R x) {
+    R acc = (R)tan_series_coef(J);
+#pragma unroll
+    for (int n = J - 1; n >= 2; --n) acc = fma(acc, x, (R)tan_series_coef(n));
+    return acc * x;
+  }
+};
+
+// Tangent form: psi += (-i al sigma_x - i be sigma_y) psi with (al, be) = tan(theta) (X, Y) / theta,
+// i.e. U / cos(theta); each component rounded once (the increment is formed first).
+template <typename R>
+__device__ __forceinline__ void midpoint_update_tan(R& a1, R& b1, R& a2, R& b2, R al, R be) {
+  R da1 = fma(-be, a2, al * b2);
+  R db1 = fma(-be, b2, -(al * a2));
+  R da2 = fma(be, a1, al * b1);
+  R db2 = fma(be, b1, -(al * a1));
+  a1 += da1;
+  b1 += db1;
+  a2 += da2;
+  b2 += db2;
+}
+
 // Stage layout of the midpoint kernel: stage j of a step of the NS-stage
 // composition uses the per-point phase of class mcls(j) (c = p or q).
 template <int NS>
@@ -480,10 +511,13 @@ __device__ __forceinline__ constexpr int mcls(int j) {
   return NS == 5 && j == 2 ? 1 : 0;
 }
 
-template <typename R, int J, int PPL, int NS, int POL>
+// TAN: the tangent form (U / cos(theta), one series); otherwise the cosine form.
+template <typename R, int J, int PPL, int NS, int POL, int TAN>
 __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
   constexpr int NC = NS == 5 ? 2 : 1;  // distinct stage coefficients
   constexpr int W = NS * (1 + POL);    // table values per step
+  constexpr bool kRenorm = sizeof(R) == 4 || TAN;  // renormalise every kRenormEvery steps
+  constexpr int kUnroll = NS == 1 ? 4 : 1;
   const long long base = (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x;
   R a1[PPL], b1[PPL], a2[PPL], b2[PPL];
   double X0[NC][PPL], Y0[NC][PPL], Y2[NC][PPL];
@@ -521,11 +555,11 @@ __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
   long long k = p.k_begin;
   while (k < p.k_end) {
     long long seg = p.k_end;
-    if (sizeof(R) == 4) {
+    if (kRenorm) {
       long long next = (k / kRenormEvery + 1) * kRenormEvery;
       seg = next < p.k_end ? next : p.k_end;
     }
-#pragma unroll(NS == 1 ? 4 : 1)
+#pragma unroll kUnroll
     for (; k < seg; ++k) {
       const double* row = tab + k * W;
 #pragma unroll
@@ -536,16 +570,29 @@ __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
         for (int q = 0; q < PPL; ++q) {
           double X = X0[mcls<NS>(j)][q] + d;  // vsign c dt (px + A_x), FP64 in both forms
           double Y = POL ? Y0[mcls<NS>(j)][q] + dy : Y0[mcls<NS>(j)][q];
-          double x = POL ? fma(X, X, Y * Y) : fma(X, X, Y2[mcls<NS>(j)][q]);  // (c dt E)^2
-          R xr = (R)x;
-          R h = Taylor<J>::h(xr);
-          R sp = Taylor<J>::s(xr);  // sin(c dt E) / (c dt E)
-          R al = sp * (R)X, be = sp * (R)Y;
-          midpoint_update(a1[q], b1[q], a2[q], b2[q], h, al, be);
+          if constexpr (TAN && sizeof(R) == 4) {
+            // the series is evaluated in FP32, so (c dt E)^2 is formed from the rounded
+            // phases (a relative error of the size of the coefficient's own rounding)
+            float Xr = (float)X, Yr = (float)Y;
+            float x = POL ? fmaf(Xr, Xr, Yr * Yr) : fmaf(Xr, Xr, (float)Y2[mcls<NS>(j)][q]);
+            float t1 = TanSeries<J>::minus1(x);  // tan(c dt E) / (c dt E) - 1
+            midpoint_update_tan(a1[q], b1[q], a2[q], b2[q], fmaf(t1, Xr, Xr), fmaf(t1, Yr, Yr));
+          } else if constexpr (TAN) {
+            double x = POL ? fma(X, X, Y * Y) : fma(X, X, Y2[mcls<NS>(j)][q]);
+            double t1 = TanSeries<J>::minus1(x);
+            midpoint_update_tan(a1[q], b1[q], a2[q], b2[q], fma(t1, X, X), fma(t1, Y, Y));
+          } else {
+            double x = POL ? fma(X, X, Y * Y) : fma(X, X, Y2[mcls<NS>(j)][q]);  // (c dt E)^2
+            R xr = (R)x;
+            R h = Taylor<J>::h(xr);
+            R sp = Taylor<J>::s(xr);  // sin(c dt E) / (c dt E)
+            R al = sp * (R)X, be = sp * (R)Y;
+            midpoint_update(a1[q], b1[q], a2[q], b2[q], h, al, be);
+          }
         }
       }
     }
-    if (sizeof(R) == 4 && (k % kRenormEvery) == 0 && k < p.n_steps) {
+    if (kRenorm && (k % kRenormEvery) == 0 && k < p.n_steps) {
 #pragma unroll
       for (int q = 0; q < PPL; ++q) {
         double A1 = a1[q], B1 = b1[q], A2 = a2[q], B2 = b2[q];
@@ -576,7 +623,7 @@ __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
         double re = (Eo * A1 + Pxo * A2) + Pyo * B2;
         double im = (Eo * B1 + Pxo * B2) - Pyo * A2;
         n = (re * re + im * im) / (2.0 * Eo * Eo);
-        if (sizeof(R) == 4) n = n / (A1 * A1 + B1 * B1 + A2 * A2 + B2 * B2);
+        if (kRenorm) n = n / (A1 * A1 + B1 * B1 + A2 * A2 + B2 * B2);
       }
       if (valid) p.n_out[idx] = n;
     }
@@ -786,28 +833,30 @@ hipError_t strang_variant(int stages, int elliptic, int ppl, int block, const So
                   : strang_ppl<R, FORM, 1, 0, ONCE>(ppl, block, p, stream);
 }
 
-template <typename R, int J, int PPL, int NS, int POL>
+template <typename R, int J, int PPL, int NS, int POL, int TAN>
 hipError_t launch_midpoint(int block, const SolveParams& p, hipStream_t stream) {
   long long per_block = (long long)block * PPL;
   long long blocks = (p.npts + per_block - 1) / per_block;
-  hipLaunchKernelGGL((midpoint_kernel<R, J, PPL, NS, POL>), dim3((unsigned)blocks), dim3(block), 0, stream, p);
+  hipLaunchKernelGGL((midpoint_kernel<R, J, PPL, NS, POL, TAN>), dim3((unsigned)blocks), dim3(block), 0, stream, p);
   return hipGetLastError();
 }
 
-template <typename R, int J, int NS, int POL>
+template <typename R, int J, int NS, int POL, int TAN>
 hipError_t midpoint_ppl(int ppl, int block, const SolveParams& p, hipStream_t stream) {
   switch (ppl) {
-    case 1: return launch_midpoint<R, J, 1, NS, POL>(block, p, stream);
-    case 2: return launch_midpoint<R, J, 2, NS, POL>(block, p, stream);
-    default: return launch_midpoint<R, J, 4, NS, POL>(block, p, stream);
+    case 1: return launch_midpoint<R, J, 1, NS, POL, TAN>(block, p, stream);
+    case 2: return launch_midpoint<R, J, 2, NS, POL, TAN>(block, p, stream);
+    default: return launch_midpoint<R, J, 4, NS, POL, TAN>(block, p, stream);
   }
 }
 
-template <typename R, int J>
+template <typename R, int J, int TAN>
 hipError_t midpoint_variant(int stages, int elliptic, int ppl, int block, const SolveParams& p, hipStream_t stream) {
   if (stages == 5)
-    return elliptic ? midpoint_ppl<R, J, 5, 1>(ppl, block, p, stream) : midpoint_ppl<R, J, 5, 0>(ppl, block, p, stream);
-  return elliptic ? midpoint_ppl<R, J, 1, 1>(ppl, block, p, stream) : midpoint_ppl<R, J, 1, 0>(ppl, block, p, stream);
+    return elliptic ? midpoint_ppl<R, J, 5, 1, TAN>(ppl, block, p, stream)
+                    : midpoint_ppl<R, J, 5, 0, TAN>(ppl, block, p, stream);
+  return elliptic ? midpoint_ppl<R, J, 1, 1, TAN>(ppl, block, p, stream)
+                  : midpoint_ppl<R, J, 1, 0, TAN>(ppl, block, p, stream);
 }
 
 }  // namespace
@@ -829,17 +878,32 @@ hipError_t launch_propagate(int scheme, int precision, int ppl, int block, int t
     return p.form == kFormShear ? strang_variant<double, kFormShear, 0>(S, elliptic, ppl, block, p, stream)
                                 : strang_variant<double, kFormVersine, 0>(S, elliptic, ppl, block, p, stream);
   }
+  // series orders: those taylor_order() chooses from
+  if (p.form == kMidTangent) {
+    if (is_fp32(precision)) {
+      switch (taylor) {
+        case 2: return midpoint_variant<float, 2, 1>(S, elliptic, ppl, block, p, stream);
+        case 3: return midpoint_variant<float, 3, 1>(S, elliptic, ppl, block, p, stream);
+        default: return midpoint_variant<float, 5, 1>(S, elliptic, ppl, block, p, stream);
+      }
+    }
+    switch (taylor) {
+      case 5: return midpoint_variant<double, 5, 1>(S, elliptic, ppl, block, p, stream);
+      case 7: return midpoint_variant<double, 7, 1>(S, elliptic, ppl, block, p, stream);
+      default: return midpoint_variant<double, 10, 1>(S, elliptic, ppl, block, p, stream);
+    }
+  }
   if (is_fp32(precision)) {
     switch (taylor) {
-      case 3: return midpoint_variant<float, 3>(S, elliptic, ppl, block, p, stream);
-      case 5: return midpoint_variant<float, 5>(S, elliptic, ppl, block, p, stream);
-      default: return midpoint_variant<float, 9>(S, elliptic, ppl, block, p, stream);
+      case 3: return midpoint_variant<float, 3, 0>(S, elliptic, ppl, block, p, stream);
+      case 5: return midpoint_variant<float, 5, 0>(S, elliptic, ppl, block, p, stream);
+      default: return midpoint_variant<float, 9, 0>(S, elliptic, ppl, block, p, stream);
     }
   }
   switch (taylor) {
-    case 5: return midpoint_variant<double, 5>(S, elliptic, ppl, block, p, stream);
-    case 8: return midpoint_variant<double, 8>(S, elliptic, ppl, block, p, stream);
-    default: return midpoint_variant<double, 14>(S, elliptic, ppl, block, p, stream);
+    case 5: return midpoint_variant<double, 5, 0>(S, elliptic, ppl, block, p, stream);
+    case 8: return midpoint_variant<double, 8, 0>(S, elliptic, ppl, block, p, stream);
+    default: return midpoint_variant<double, 14, 0>(S, elliptic, ppl, block, p, stream);
   }
 }
 

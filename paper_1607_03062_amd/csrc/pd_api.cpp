@@ -121,7 +121,7 @@ void release(T*& p) {
 }
 
 pd_status prepare_field(pd_grid g, const pd_field* f, long long n_steps, FieldTables* t, long long* masked,
-                        int* taylor) {
+                        int* taylor, int* form) {
   if (!g) return fail(PD_ERR_INVALID, "null handle");
   if (!f) return fail(PD_ERR_INVALID, "null field");
   std::string err;
@@ -135,8 +135,11 @@ pd_status prepare_field(pd_grid g, const pd_field* f, long long n_steps, FieldTa
   *taylor = 0;
   if (base_scheme(g->scheme) == PD_SCHEME_MIDPOINT) {
     double xm = t->comp.cmax * t->dt * t->E_max;  // largest stage phase
-    *taylor = taylor_order(xm * xm, g->precision);
+    *form = midpoint_form(*t, g->precision);
+    *taylor = taylor_order(xm * xm, g->precision, *form);
     if (*taylor < 0) return fail(PD_ERR_UNSUPPORTED, "midpoint step too large for the compiled Taylor orders");
+  } else {
+    *form = strang_form(g->grid, *t);
   }
   return ok();
 }
@@ -164,7 +167,8 @@ void fill_info(pd_grid g, const FieldTables& t, long long masked, long long step
   out->rotation_form = t.n_steps > 0 ? strang_form(g->grid, t) : kFormShear;
   if (base_scheme(g->scheme) == PD_SCHEME_MIDPOINT && t.n_steps > 0) {
     double xm = t.comp.cmax * t.dt * t.E_max;
-    out->taylor_order = taylor_order(xm * xm, g->precision);
+    out->rotation_form = midpoint_form(t, g->precision);
+    out->taylor_order = taylor_order(xm * xm, g->precision, out->rotation_form);
   }
   out->device_bytes = g->device_bytes();
   if (t.n_steps > 0) out->solve_bytes = pd_solve_bytes(g, t.n_steps);
@@ -222,8 +226,8 @@ pd_status pd_create_grid(int nx, int ny, double px_min, double px_max, double py
 pd_status pd_check_field(pd_grid g, const pd_field* f, long long n_steps, pd_info* out) {
   FieldTables t;
   long long masked = 0;
-  int taylor = 0;
-  pd_status s = prepare_field(g, f, n_steps, &t, &masked, &taylor);
+  int taylor = 0, form = 0;
+  pd_status s = prepare_field(g, f, n_steps, &t, &masked, &taylor, &form);
   if (out && g && (s == PD_OK || !t.A_mid.empty())) fill_info(g, t, masked, 0, out);
   return s;
 }
@@ -281,11 +285,10 @@ pd_status pd_set_valley(pd_grid g, int valley) {
 pd_status pd_set_field(pd_grid g, const pd_field* f, long long n_steps) {
   FieldTables t;
   long long masked = 0;
-  int taylor = 0;
-  pd_status s = prepare_field(g, f, n_steps, &t, &masked, &taylor);
+  int taylor = 0, form = 0;
+  pd_status s = prepare_field(g, f, n_steps, &t, &masked, &taylor, &form);
   if (s != PD_OK) return s;
   std::vector<unsigned char> rows;
-  const int form = strang_form(g->grid, t);
   build_step_table(t, g->scheme, g->precision, form, g->vsign(), &rows);
   size_t col_offset = 0, row_offset = 0;
   if (base_scheme(g->scheme) == PD_SCHEME_STRANG)

@@ -86,13 +86,45 @@ size_t point_coefficient_pairs_y(int scheme);  // including the half step
 // Coefficients (a, s) of the rotation by phi = 2 * half in a rotation form.
 void rotation_coefficients(double half, int form, double* a, double* s);
 
-// Smallest Taylor order (terms of cos - 1 and of sin(x)/x in x = (dt E)^2) whose
-// truncation stays below the precision's rounding for x <= x_max.
-int taylor_order(double x_max, int precision);
-
 // Strang rotation forms: three shears (tan(phi/2), sin phi) or versine (cos phi - 1, sin phi).
 constexpr int kFormShear = 0;
 constexpr int kFormVersine = 1;
+
+// Midpoint step forms.  The step is U = cos(theta) I - i sin(theta) sigma.P / E with
+// theta = c dt E (Sec. III, Eq. (13)).
+//   Tangent: U / cos(theta) = I - i tan(theta) sigma.P / E, one series in x = theta^2;
+//            the state then grows by 1 / cos(theta) per stage and is renormalised.
+//   Cosine:  U itself, with the series of cos - 1 and sin(x)/x.
+constexpr int kMidTangent = 0;
+constexpr int kMidCosine = 1;
+
+// Steps between renormalisations of the state (the FP32 forms and the midpoint
+// tangent form); counted in absolute steps, so a chunked solve renormalises at the
+// same steps as a single launch.
+constexpr long long kRenormEvery = 1024;
+
+// Coefficients of tan(sqrt x) / sqrt x = sum_{n >= 1} a_n x^(n-1).  From
+// tan' = 1 + tan^2: a_1 = 1 and (2n - 1) a_n = sum_{k=1}^{n-1} a_k a_{n-k}.
+constexpr double tan_series_coef(int n) {
+  double a[24] = {};
+  a[1] = 1.0;
+  for (int m = 2; m <= n; ++m) {
+    double s = 0.0;
+    for (int k = 1; k < m; ++k) s += a[k] * a[m - k];
+    a[m] = s / (2 * m - 1);
+  }
+  return a[n];
+}
+
+// Midpoint form of a solve: tangent when the state's growth over kRenormEvery
+// steps stays below 2^32 and a compiled series order reaches the precision's
+// rounding; cosine otherwise.
+int midpoint_form(const FieldTables& t, int precision);
+
+// Smallest compiled series order of a midpoint form (terms of tan(x)/x, or of
+// cos - 1 and of sin(x)/x, in x = (c dt E)^2) whose truncation stays below the
+// precision's rounding for x <= x_max; -1 if none does.
+int taylor_order(double x_max, int precision, int form);
 // The shear form is used when every rotation angle of a solve is at most this (|tan(phi/2)| <= 1).
 constexpr double kShearMaxAngle = 1.5707963267948966;
 
@@ -114,7 +146,7 @@ struct SolveParams {
   int load_state;    // 1: resume from state; 0: start from v_in
   int store_state;   // 1: keep the state after k_end
   int stage;         // Strang table path: 0 scalar-unit loads, 1 LDS chunks
-  int form;          // Strang rotation form: kFormShear or kFormVersine
+  int form;          // Strang: kFormShear or kFormVersine; midpoint: kMidTangent or kMidCosine
   long long chunk_steps;  // LDS chunk length in steps (power of two; divides 1024 in FP32)
 };
 

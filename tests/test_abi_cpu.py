@@ -116,6 +116,55 @@ def test_rotation_form_choice():
     s.close()
 
 
+def _tan_over_x_coefficients(n_max):
+    """a_n of tan(z)/z = sum_{n>=1} a_n z^(2n-2), exactly, from the Bernoulli numbers:
+    a_n = (-1)^(n-1) 2^(2n) (2^(2n) - 1) B_(2n) / (2n)!."""
+    from fractions import Fraction
+
+    B = [Fraction(1)]
+    for m in range(1, 2 * n_max + 1):
+        B.append(-sum(math.comb(m + 1, k) * B[k] for k in range(m)) / (m + 1))
+    return [None] + [(-1) ** (n - 1) * 2 ** (2 * n) * (2 ** (2 * n) - 1) * B[2 * n] / math.factorial(2 * n)
+                     for n in range(1, n_max + 1)]
+
+
+def test_midpoint_form_and_series_order():
+    """The midpoint step takes the tangent form while the state's growth over the
+    1024-step renormalisation period, (1 / cos theta)^(1024 stages), stays below 2^32
+    (theta = c_max dt E_max), else the cosine form.  The tangent series' order J keeps
+    the omitted terms below the precision's rounding (2^-27 FP32, 2^-56 FP64) at the
+    solve's largest x = theta^2, and the next smaller compiled order would not."""
+    from fractions import Fraction
+
+    a = _tan_over_x_coefficients(30)
+    assert a[1:5] == [1, Fraction(1, 3), Fraction(2, 15), Fraction(17, 315)]
+    compiled = {"fp32": [2, 3, 5], "fp64": [5, 7, 10]}
+    g = {"nx": 37, "ny": 29, "px": (-3.0, 2.5), "py": (-2.0, 2.2)}
+    seen = set()
+    for scheme, stages, cmax in (("midpoint", 1, 1.0), ("midpoint4", 5, abs(1 - 4 / (4 - 4 ** (1 / 3))))):
+        for prec in ("fp32", "fp64"):
+            tol = 2.0 ** -27 if prec == "fp32" else 2.0 ** -56
+            s = pd.Solver.for_grid(g, prec, scheme)
+            for N in (60, 120, 200, 300, 450, 700, 1000, 2600, 9000, 40000):
+                try:
+                    info = s.check_field(wl.sin2(0.4, 0.7, 4), N)
+                except pd.PDError:
+                    continue
+                theta = cmax * info["dt"] * info["E_max"]
+                growth = 1024 * stages * -math.log2(math.cos(theta)) if theta < math.pi / 2 else math.inf
+                x = theta * theta
+                tail = lambda J: float(sum(a[n] * Fraction(x) ** (n - 1) for n in range(J + 1, 31)))
+                fits = [J for J in compiled[prec] if tail(J) <= tol]
+                want = 0 if growth <= 32 and fits else 1
+                assert info["rotation_form"] == want, (scheme, prec, N, theta)
+                if want == 0:
+                    J = info["taylor_order"]
+                    assert J == fits[0], (scheme, prec, N, J, fits)
+                seen.add((scheme, prec, want))
+            s.close()
+    assert len(seen) == 8  # both forms in every scheme and precision
+
+
 def test_masked_count_with_final_momentum_zero():
     """Constant field E0 = 0.2 on [0, 200]: A_out = -40, so p = (40, 0) has E_out = 0."""
     s = pd.Solver(81, 3, (0.0, 81.0), (-1.0, 2.0))  # p_x = 0, 1, ..., 80; p_y = -1, 0, 1

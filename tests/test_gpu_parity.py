@@ -124,6 +124,36 @@ def test_chunked_equals_single_launch(gpu, precision, scheme):
     assert np.array_equal(single[0], bound[0])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_midpoint_step_forms(gpu, precision):
+    """Both forms of the midpoint step match the oracle: the tangent form (step angles
+    small enough; the state grows by 1 / cos(dt E) per step and is renormalised every
+    1024 steps, in FP64 too) and the cosine form (larger angles).  A chunked
+    tangent-form solve, cut next to the renormalisation steps, reproduces the single
+    launch, and so does a snapshot taken between the chunks."""
+    g = {"nx": 37, "ny": 29, "px": (-3.0, 2.5), "py": (-2.0, 2.2)}
+    f = wl.sin2(0.4, 0.7, 4)
+    tol = FP64_N_ABS if precision == "fp64" else FP32_N_ABS
+    for N, form in ((2600, 0), (300, 1)):
+        n, rho, info = run(gpu, g, f, N, precision, "midpoint")
+        assert info["rotation_form"] == form, (N, info["rotation_form"])
+        n_o = oracle.solve_grid(f, g, N, "midpoint")[0]
+        assert np.max(np.abs(n - n_o)) <= tol, N
+        if precision == "fp64":
+            assert abs(rho / oracle.density(g, n_o) - 1) <= FP64_RHO_REL
+    chunked = run(gpu, g, f, 2600, precision, "midpoint", chunks=[1023, 2, 1023, 552])
+    single = run(gpu, g, f, 2600, precision, "midpoint")
+    assert np.array_equal(chunked[0], single[0]) and chunked[1] == single[1]
+    s = gpu.Solver.for_grid(g, precision, "midpoint")
+    s.set_field(f, 2600)
+    s.propagate(1500)
+    n_mid = np.empty(g["nx"] * g["ny"])
+    s.snapshot(n_out=n_mid)
+    s.close()
+    n_o = oracle.snapshot_grid(f, g, 2600, 1500, "midpoint")[0]
+    assert np.max(np.abs(n_mid - n_o)) <= (5e-12 if precision == "fp64" else tol)
+
+
 def test_degenerate_inputs(gpu):
     # one point, one step
     g1 = {"nx": 1, "ny": 1, "px": (0.3, 0.4), "py": (0.2, 0.3)}
