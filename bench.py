@@ -37,6 +37,15 @@ ALGO = {(0, "fp64"): (18, 9), (0, "fp32"): (21, 12), (0, "fp32fast"): (18, 9),
         (1, "fp64"): (24, 12), (1, "fp32"): (24, 18), (1, "fp32fast"): (24, 18)}
 
 
+def host_cpu_model() -> str:
+    """The host CPU's model name and logical CPU count (from /proc/cpuinfo)."""
+    try:
+        names = [ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")]
+    except OSError:
+        return "unknown"
+    return "%s (%d logical CPUs)" % (names[0], len(names)) if names else "unknown"
+
+
 def algo(info: dict, precision: str):
     """(flop, VALU instructions) per point-step of the solve described by pd_info; a
     fourth-order step is `stages` = 5 second-order stages.
@@ -353,7 +362,7 @@ def main():
         n_o = oracle.solve_grid(c["field"], c["grid"], c["n_steps"], sch, idx=idx, threads=threads)[0]
         t_cpu = time.perf_counter() - t0
         cpu = {"value": idx.shape[0] * c["n_steps"] / t_cpu, "unit": "point-steps/s", "cores": threads,
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": host_cpu_model(),
                "sample": "%dx%d subsample (stride %d) of the %d^2 grid, %d FP64 %s steps, %.1f s" % (
                    sub, sub, args.grid // sub, args.grid, c["n_steps"], sch, t_cpu)}
         # the 64 x 64 subsample (stride grid/64) is contained in the larger one
