@@ -62,6 +62,39 @@ def test_create_grid_rejects_bad_arguments(args):
     assert lib.pd_last_error().decode()
 
 
+def test_last_error_is_per_thread():
+    """Two threads fail different calls at the same time; after both have failed, each
+    reads its own message (ctypes releases the GIL around the calls)."""
+    import threading
+
+    lib = pd.require_native()
+    cases = [(0, 4, -1, 1, -1, 1, 0, 0), (4, 4, 2, 1, -1, 1, 0, 0)]
+    msgs = [None, None]
+    both_failed = threading.Barrier(2)
+
+    def work(i):
+        for _ in range(200):
+            h = ctypes.c_void_p()
+            assert lib.pd_create_grid(*cases[i], ctypes.byref(h)) == _lib.PD_ERR_INVALID
+            both_failed.wait()
+            m = lib.pd_last_error().decode()
+            assert msgs[i] is None or m == msgs[i]
+            msgs[i] = m
+            both_failed.wait()
+
+    ts = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert msgs[0] and msgs[1] and msgs[0] != msgs[1]
+    ref = []
+    for c in cases:  # the same messages as on a single thread
+        assert lib.pd_create_grid(*c, ctypes.byref(ctypes.c_void_p())) == _lib.PD_ERR_INVALID
+        ref.append(lib.pd_last_error().decode())
+    assert msgs == ref
+
+
 def test_null_handles():
     lib = pd.require_native()
     assert lib.pd_propagate(None, -1, None) == _lib.PD_ERR_INVALID
