@@ -409,7 +409,7 @@ __global__ void __launch_bounds__(256) batch_kernel(const BatchSolve* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Midpoint scheme: spinor state, Taylor coefficients per point and step.
+// Midpoint scheme: spinor state, series coefficients per point and step.
 
 template <int J>
 struct Taylor {
