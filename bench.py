@@ -244,24 +244,26 @@ def run_serve(args):
     cap_reqs = [serve.Request.from_workload(w) for w in wl.config5(count=args.capacity_requests, seed=55,
                                                                      rate_per_s=1e9)]
     ex = serve.GpuExecutor(pd, stream=st)
-    cap = serve.Server(ex, budget, epoch_steps=args.epoch_steps).run(cap_reqs)
+    kw = dict(epoch_steps=args.epoch_steps, policy=args.policy, epoch_ms=args.epoch_ms)
+    cap = serve.Server(ex, budget, **kw).run(cap_reqs)
     ex.close()
     mean_ps = float(np.mean([r.point_steps for r in cap_reqs]))
     capacity_rps = cap.point_steps_per_s / mean_ps
-    rate = args.load * capacity_rps
+    rate = args.rate_per_s if args.rate_per_s else args.load * capacity_rps
     reqs = [serve.Request.from_workload(w) for w in wl.config5(count=args.requests, seed=5, rate_per_s=rate)]
     ex = serve.GpuExecutor(pd, stream=st)
-    res = serve.Server(ex, budget, epoch_steps=args.epoch_steps).run(reqs)
+    res = serve.Server(ex, budget, **kw).run(reqs)
     ex.close()
     line = {
         "metric": METRIC, "value": res.point_steps_per_s, "unit": "point-steps/s", "n_gpus": 1,
         "steps": res.completed, "warmup": 0, "ms_per_step": res.makespan_s / max(res.completed, 1) * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "Poisson stream of %d solve requests (config-4 distributions, 50/50 FP32/FP64), "
-                               "rate %.1f req/s = %.2f x capacity, HBM budget %.0f GiB, epochs of %d steps" % (
-                                   args.requests, rate, args.load, args.budget_gb, args.epoch_steps),
+                               "rate %.1f req/s = %.2f x capacity, HBM budget %.0f GiB, %s epochs (%d steps / %.1f ms)" % (
+                                   args.requests, rate, rate / capacity_rps, args.budget_gb, args.policy, args.epoch_steps,
+                                   args.epoch_ms),
                    "requests": args.requests, "rate_per_s": rate, "budget_bytes": budget,
-                   "epoch_steps": args.epoch_steps},
+                   "epoch_steps": args.epoch_steps, "policy": args.policy, "epoch_ms": args.epoch_ms},
         "p50_ms": res.p50_ms, "p99_ms": res.p99_ms, "mean_ms": res.mean_ms, "serve": res.as_dict(),
         "capacity": {"requests_per_s": capacity_rps, "point_steps_per_s": cap.point_steps_per_s,
                      "requests": args.capacity_requests},
@@ -281,6 +283,11 @@ def main():
     ap.add_argument("--load", type=float, default=0.7)
     ap.add_argument("--budget-gb", type=float, default=16.0)
     ap.add_argument("--epoch-steps", type=int, default=2048)
+    ap.add_argument("--policy", choices=["lockstep", "srpt"], default="srpt",
+                    help="serving: how an epoch shares the device (paper_1607_03062_amd/serve.py)")
+    ap.add_argument("--epoch-ms", type=float, default=3.0, help="serving (srpt): time budget of an epoch")
+    ap.add_argument("--rate-per-s", type=float, default=0.0,
+                    help="serving: arrival rate (default: --load x the capacity measured in the same run)")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["fp32", "fp64", "fp32fast"], default="fp32")

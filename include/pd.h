@@ -337,6 +337,15 @@ pd_status pd_batch_run(pd_batch b, double* rho_out, void* stream);
    be NULL) is 1 for every complete member.  Waits for stream if rho_out is
    given. */
 pd_status pd_batch_step(pd_batch b, long long max_steps, double* rho_out, int* finished_out, void* stream);
+/* As pd_batch_step with a step limit per member: member i advances by up to
+   max_steps[i] steps (host array of pd_batch_size(b) values, each >= 0; 0 leaves
+   the member where it stands), so a scheduler can give members different shares
+   of an epoch.  The items of the persistent launch are ordered by their step
+   counts, longest first.  Each member's arithmetic, and so its n(p) and rho, is
+   the same as alone, whatever the limits.  PD_ERR_INVALID if max_steps is NULL
+   or a limit is negative. */
+pd_status pd_batch_step_each(pd_batch b, const long long* max_steps, double* rho_out, int* finished_out,
+                             void* stream);
 pd_status pd_batch_get_info(pd_batch b, pd_batch_info* out);
 /* Time points_per_lane {1, 2, 4} x block_threads {64, 128, 256} over the first
    trial_steps steps of every member, keep the fastest; members are left

@@ -131,6 +131,8 @@ SIGNATURES = [
     ("pd_batch_set_launch", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     ("pd_batch_run", ctypes.c_int, [_vp, _dp, _vp]),
     ("pd_batch_step", ctypes.c_int, [_vp, ctypes.c_longlong, _dp, ctypes.POINTER(ctypes.c_int), _vp]),
+    ("pd_batch_step_each", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_longlong), _dp, ctypes.POINTER(ctypes.c_int),
+                                          _vp]),
     ("pd_batch_get_info", ctypes.c_int, [_vp, ctypes.c_void_p]),
     ("pd_batch_autotune", ctypes.c_int, [_vp, ctypes.c_longlong, _vp]),
     ("pd_batch_destroy", None, [_vp]),
@@ -407,6 +409,19 @@ class Batch:
         fin = (ctypes.c_int * max(n, 1))()
         check(load().pd_batch_step(self._h, int(max_steps), rho.ctypes.data_as(_dp) if want_rho else None, fin,
                                    stream_handle(stream)), "pd_batch_step")
+        return (rho if want_rho else None), np.array(fin[:n], dtype=bool)
+
+    def step_each(self, max_steps, stream=None, want_rho: bool = True):
+        """One epoch with a step limit per member (sequence in member order, 0 = stays);
+        returns (rho array with NaN for members not completing now, finished flags)."""
+        n = len(self.members)
+        if len(max_steps) != n:
+            raise ValueError("max_steps has %d values for %d members" % (len(max_steps), n))
+        lim = (ctypes.c_longlong * max(n, 1))(*[int(m) for m in max_steps])
+        rho = np.full(n, np.nan)
+        fin = (ctypes.c_int * max(n, 1))()
+        check(load().pd_batch_step_each(self._h, lim, rho.ctypes.data_as(_dp) if want_rho else None, fin,
+                                        stream_handle(stream)), "pd_batch_step_each")
         return (rho if want_rho else None), np.array(fin[:n], dtype=bool)
 
     def autotune(self, trial_steps: int = 1024, stream=None):

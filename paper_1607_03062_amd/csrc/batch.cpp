@@ -249,6 +249,38 @@ pd_status prepare_device(pd_batch b) {
   return PD_OK;
 }
 
+// Advance member i by up to max_steps[i] steps (one epoch of pd_batch_step / _each).
+pd_status step_members(pd_batch b, const long long* max_steps, double* rho_out, int* finished_out, void* stream) {
+  pd_status s = PD_OK;
+  if (!b->grids.empty() && b->device < 0 && b->grids[0]->field_set && (s = prepare_device(b)) != PD_OK) return s;
+  if ((s = check_members(b)) != PD_OK) return s;
+  DeviceScope scope(b->device);
+  if (!scope.ok) return set_error(PD_ERR_DEVICE, "cannot select device %d", b->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t n = b->grids.size();
+  if ((s = ensure_device(&b->d_rho, &b->cap_rho_dev, n)) != PD_OK) return s;
+  std::vector<long long> begin(n), end(n);
+  for (size_t i = 0; i < n; ++i) {
+    pd_grid g = b->grids[i];
+    begin[i] = g->steps_done;
+    end[i] = g->steps_done + std::min(g->field.n_steps - g->steps_done, max_steps[i]);
+  }
+  Plan plan;
+  if ((s = make_plan(b, begin, end, &plan)) != PD_OK) return s;
+  if ((s = upload(b, plan, st)) != PD_OK) return s;
+  if ((s = enqueue(b, plan, st)) != PD_OK) return s;
+  b->n_items_last = (int)plan.items.size();
+  b->n_separate_last = (int)plan.separate.size();
+  std::vector<char> completed(n, 0);
+  for (size_t i = 0; i < n; ++i) {
+    completed[i] = begin[i] < end[i] && end[i] == b->grids[i]->field.n_steps;
+    b->grids[i]->steps_done = end[i];
+  }
+  if (finished_out)
+    for (size_t i = 0; i < n; ++i) finished_out[i] = b->grids[i]->steps_done == b->grids[i]->field.n_steps;
+  return copy_rho(b, rho_out, &completed, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -363,34 +395,17 @@ pd_status pd_batch_run(pd_batch b, double* rho_out, void* stream) {
 pd_status pd_batch_step(pd_batch b, long long max_steps, double* rho_out, int* finished_out, void* stream) {
   if (!b) return set_error(PD_ERR_INVALID, "null handle");
   if (max_steps < 1) return set_error(PD_ERR_INVALID, "max_steps must be >= 1");
-  pd_status s = PD_OK;
-  if (!b->grids.empty() && b->device < 0 && b->grids[0]->field_set && (s = prepare_device(b)) != PD_OK) return s;
-  if ((s = check_members(b)) != PD_OK) return s;
-  DeviceScope scope(b->device);
-  if (!scope.ok) return set_error(PD_ERR_DEVICE, "cannot select device %d", b->device);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const size_t n = b->grids.size();
-  if ((s = ensure_device(&b->d_rho, &b->cap_rho_dev, n)) != PD_OK) return s;
-  std::vector<long long> begin(n), end(n);
-  for (size_t i = 0; i < n; ++i) {
-    pd_grid g = b->grids[i];
-    begin[i] = g->steps_done;
-    end[i] = std::min(g->field.n_steps, g->steps_done + max_steps);
-  }
-  Plan plan;
-  if ((s = make_plan(b, begin, end, &plan)) != PD_OK) return s;
-  if ((s = upload(b, plan, st)) != PD_OK) return s;
-  if ((s = enqueue(b, plan, st)) != PD_OK) return s;
-  b->n_items_last = (int)plan.items.size();
-  b->n_separate_last = (int)plan.separate.size();
-  std::vector<char> completed(n, 0);
-  for (size_t i = 0; i < n; ++i) {
-    completed[i] = begin[i] < end[i] && end[i] == b->grids[i]->field.n_steps;
-    b->grids[i]->steps_done = end[i];
-  }
-  if (finished_out)
-    for (size_t i = 0; i < n; ++i) finished_out[i] = b->grids[i]->steps_done == b->grids[i]->field.n_steps;
-  return copy_rho(b, rho_out, &completed, st);
+  std::vector<long long> limits(b->grids.size(), max_steps);
+  return step_members(b, limits.data(), rho_out, finished_out, stream);
+}
+
+pd_status pd_batch_step_each(pd_batch b, const long long* max_steps, double* rho_out, int* finished_out,
+                             void* stream) {
+  if (!b) return set_error(PD_ERR_INVALID, "null handle");
+  if (!max_steps && !b->grids.empty()) return set_error(PD_ERR_INVALID, "null max_steps");
+  for (size_t i = 0; i < b->grids.size(); ++i)
+    if (max_steps[i] < 0) return set_error(PD_ERR_INVALID, "max_steps[%zu] = %lld is negative", i, max_steps[i]);
+  return step_members(b, max_steps, rho_out, finished_out, stream);
 }
 
 pd_status pd_batch_get_info(pd_batch b, pd_batch_info* out) {

@@ -2,15 +2,24 @@
 
 Requests (a grid, a field, a step count, a precision, a scheme and a valley)
 arrive over time.  The server keeps a set of active solves on the device and runs
-them in epochs: each epoch advances every active solve by up to `epoch_steps`
-steps in one batched launch sequence (pd_batch_step: one persistent kernel for
-the second-order Strang solves of fields along x, the others' own launches after
-it), with every solve's state resident in device memory between epochs.  Solves that reach their last step are projected and
-reduced in the same epoch and leave the set; arrivals are admitted between
-epochs, in arrival order, while their device footprint (tables, state, n(p),
-partials; pd_info.solve_bytes) fits in the memory budget.  A request larger than
-the whole budget is rejected.  Latency is the time from a request's arrival to
-its density being on the host.
+them in epochs: each epoch advances active solves in one batched launch sequence
+(pd_batch_step_each: one persistent kernel for the second-order Strang solves of
+fields along x, the others' own launches after it), with every solve's state
+resident in device memory between epochs.  Solves that reach their last step are
+projected and reduced in the same epoch and leave the set; arrivals are admitted
+between epochs, in arrival order, while their device footprint (tables, state,
+n(p), partials; pd_info.solve_bytes) fits in the memory budget.  A request larger
+than the whole budget is rejected.  Latency is the time from a request's arrival
+to its density being on the host.
+
+How an epoch shares the device is the policy:
+  lockstep  every active solve advances `epoch_steps` steps;
+  srpt      shortest remaining work first: the solves with the least remaining
+            work (points x steps left / the device rate of their precision)
+            take an epoch's time budget (`epoch_ms`) in that order, each up to
+            the steps one tile of it runs in that time; the largest may get
+            none in an epoch.  This cuts the waiting of small solves behind
+            large ones at the same device throughput.
 
 The device work is in libpd; this module is the host-side scheduler.  The
 executor interface (footprint / admit / epoch / release) has a GPU
@@ -101,15 +110,21 @@ class GpuExecutor:
         self.batch.add(s)
 
     def epoch(self, steps: int):
-        """Advance every active solve; returns [(name, rho)] of the solves that completed.
-        Which solves complete is known on the host, so the call only waits for the device
-        in epochs where one does; otherwise the next epoch is enqueued behind this one."""
-        completing = any(self.left[name] <= steps for name in self.order)
-        rho, fin = self.batch.step(steps, stream=self.stream, want_rho=completing)
+        """Advance every active solve by up to `steps` steps (see epoch_each)."""
+        return self.epoch_each({name: steps for name in self.order})
+
+    def epoch_each(self, steps: dict):
+        """Advance each active solve by up to steps[name] steps (absent: 0); returns
+        [(name, rho)] of the solves that completed.  Which solves complete is known on
+        the host, so the call only waits for the device in epochs where one does;
+        otherwise the next epoch is enqueued behind this one."""
+        lim = [min(self.left[name], max(0, int(steps.get(name, 0)))) for name in self.order]
+        completing = any(m > 0 and m == self.left[name] for name, m in zip(self.order, lim))
+        rho, fin = self.batch.step_each(lim, stream=self.stream, want_rho=completing)
         done = []
         for i, name in enumerate(self.order):
-            self.left[name] = max(0, self.left[name] - steps)
-            if completing and not np.isnan(rho[i]):
+            self.left[name] -= lim[i]
+            if completing and lim[i] > 0 and self.left[name] == 0:
                 done.append((name, float(rho[i])))
         return done
 
@@ -133,12 +148,17 @@ class GpuExecutor:
 
 
 class FakeExecutor:
-    """CPU stand-in with the same interface: a solve costs point-steps / rate seconds of
-    device time, shared evenly by the active solves; rho is a fixed function of the request."""
+    """CPU stand-in with the same interface: an epoch costs its point-steps / rate seconds
+    of device time, or, if longer, the steps of its longest share times tile_step_s (the
+    time one tile takes per step, which bounds how fast a small solve can go), plus
+    epoch_overhead_s; rho is a fixed function of the request."""
 
-    def __init__(self, rate_point_steps_per_s: float = 1e12, bytes_per_point: int = 40):
+    def __init__(self, rate_point_steps_per_s: float = 1e12, bytes_per_point: int = 40, tile_step_s: float = 0.0,
+                 epoch_overhead_s: float = 0.0):
         self.rate = rate_point_steps_per_s
         self.bytes_per_point = bytes_per_point
+        self.tile_step_s = tile_step_s
+        self.epoch_overhead_s = epoch_overhead_s
         self.active = collections.OrderedDict()  # name -> [request, steps_done]
         self.clock = 0.0                          # simulated device time
 
@@ -149,16 +169,21 @@ class FakeExecutor:
         self.active[req.name] = [req, 0]
 
     def epoch(self, steps: int):
+        return self.epoch_each({name: steps for name in self.active})
+
+    def epoch_each(self, steps: dict):
         work = 0.0
+        longest = 0
         done = []
         for name, entry in self.active.items():
             req, k = entry
-            m = min(steps, req.n_steps - k)
+            m = min(max(0, int(steps.get(name, 0))), req.n_steps - k)
             work += float(req.points) * m
+            longest = max(longest, m)
             entry[1] = k + m
             if entry[1] == req.n_steps and m > 0:
                 done.append((name, 1e-3 * req.points / (1.0 + req.n_steps)))
-        self.clock += work / self.rate
+        self.clock += max(work / self.rate, longest * self.tile_step_s) + self.epoch_overhead_s
         return done
 
     def release(self, name: str):
@@ -186,19 +211,60 @@ class ServeStats:
         return dataclasses.asdict(self)
 
 
+# Device rates (point-steps/s) the srpt policy prices work with, and the time one
+# 1024-point tile takes per step on a full device (MI355X measurements, Strang).
+DEFAULT_RATES = {"fp32": 5.0e12, "fp32fast": 6.5e12, "fp64": 3.4e12}
+DEFAULT_TILE_STEP_S = 0.43e-6
+
+
 class Server:
     def __init__(self, executor, budget_bytes: int, epoch_steps: int = 2048, max_active: int = 4096,
-                 backfill: bool = False):
+                 backfill: bool = False, policy: str = "lockstep", epoch_ms: float = 3.0, rates: dict = None,
+                 tile_step_s: float = DEFAULT_TILE_STEP_S):
         if epoch_steps < 1:
             raise ValueError("epoch_steps must be >= 1")
+        if policy not in ("lockstep", "srpt"):
+            raise ValueError("policy must be 'lockstep' or 'srpt'")
+        if not (epoch_ms > 0 and tile_step_s > 0):
+            raise ValueError("epoch_ms and tile_step_s must be > 0")
         self.ex = executor
         self.budget = int(budget_bytes)
         self.epoch_steps = int(epoch_steps)
         self.max_active = int(max_active)
         self.backfill = backfill
+        self.policy = policy
+        self.epoch_s = epoch_ms * 1e-3
+        self.rates = dict(DEFAULT_RATES, **(rates or {}))
+        self.tile_step_s = tile_step_s
         self.in_use = 0
         self.peak = 0
         self.active = {}
+        self.left = {}  # request name -> steps still to run
+
+    def plan_epoch(self) -> dict:
+        """Steps each active solve advances in the next epoch (absent: none)."""
+        if self.policy == "lockstep":
+            return {name: min(self.epoch_steps, left) for name, left in self.left.items()}
+        budget = self.epoch_s
+        share = max(self.epoch_steps, int(self.epoch_s / self.tile_step_s))  # steps a tile runs in an epoch
+        rate = {name: self.rates.get(r.precision, self.rates["fp32"]) for name, r in self.active.items()}
+        order = sorted(self.left, key=lambda n: (self.active[n].points * self.left[n] / rate[n], n))
+        plan = {}
+        for name in order:
+            pts = self.active[name].points
+            m = min(self.left[name], share)
+            if pts * m / rate[name] > budget:
+                m = int(budget * rate[name] / pts)
+                if m < min(self.left[name], self.epoch_steps // 8 or 1):
+                    continue  # too little left for a useful share of this solve
+            plan[name] = m
+            budget -= pts * m / rate[name]
+            if budget <= 0:
+                break
+        if not plan:  # a single solve larger than the whole budget still advances
+            name = order[0]
+            plan[name] = min(self.left[name], self.epoch_steps)
+        return plan
 
     def _now(self, t0, simulated):
         return self.ex.clock if simulated else time.perf_counter() - t0
@@ -235,6 +301,7 @@ class Server:
                         continue
                     r.admitted_s, r.status = now, "active"
                     self.active[r.name] = r
+                    self.left[r.name] = r.n_steps
                     self.in_use += r.bytes
                     self.peak = max(self.peak, self.in_use)
                 elif self.backfill:
@@ -253,11 +320,15 @@ class Server:
                 if waiting:
                     raise RuntimeError("a waiting request can never be admitted")
                 break
-            done = self.ex.epoch(self.epoch_steps)
+            plan = self.plan_epoch()
+            done = self.ex.epoch_each(plan)
+            for name, m in plan.items():
+                self.left[name] -= m
             epochs += 1
             active_sum += len(self.active)
             now = self._now(t0, simulated)
             for name, rho in done:
+                del self.left[name]
                 r = self.active.pop(name)
                 r.rho, r.done_s, r.status = rho, now, "done"
                 self.in_use -= r.bytes

@@ -120,6 +120,48 @@ def test_epochs_equal_single_launch(gpu):
     b.close()
 
 
+def test_epochs_with_a_step_limit_per_member(gpu):
+    """pd_batch_step_each: every epoch gives each member its own step limit (seeded draws,
+    0 included, limits past the last step included); members finish at different epochs,
+    report rho then, and end with n(p) and rho bit-identical to their solves alone.  One
+    member (midpoint scheme) runs its own launch beside the persistent kernel."""
+    ms = members(gpu, count=8)
+    mc = {"name": "midpoint", "grid": {"nx": 41, "ny": 29, "px": (-2.0, 2.0), "py": (-1.5, 1.5)},
+          "field": wl.sin2(0.3, 0.6, 3), "n_steps": 2300}
+    sm = gpu.Solver.for_grid(mc["grid"], "fp32", "midpoint")
+    sm.set_field(mc["field"], mc["n_steps"])
+    ms.append((mc, sm))
+    ref = [alone(s) for _, s in ms]
+    for _, s in ms:
+        s.rewind()
+    b = gpu.Batch([s for _, s in ms])
+    rng = np.random.default_rng(11)
+    done_rho = [None] * len(ms)
+    epochs = 0
+    while True:
+        lim = [int(v) for v in rng.choice([0, 1, 37, 256, 700, 1500, 10 ** 6], size=len(ms))]
+        before = [s.info()["steps_done"] for _, s in ms]
+        rho, fin = b.step_each(lim)
+        epochs += 1
+        for i, (_, s) in enumerate(ms):
+            n_steps = s.info()["n_steps"]
+            assert s.info()["steps_done"] == min(n_steps, before[i] + lim[i])
+            if not np.isnan(rho[i]):
+                assert done_rho[i] is None and before[i] + lim[i] >= n_steps
+                done_rho[i] = rho[i]
+        if fin.all():
+            break
+        assert epochs < 400
+    for (c, s), (n0, r0), r in zip(ms, ref, done_rho):
+        assert r == r0, c["name"]
+        assert np.array_equal(member_n(s)[0], n0), c["name"]
+    with pytest.raises(ValueError):
+        b.step_each([1] * (len(ms) - 1))
+    with pytest.raises(gpu.PDError):
+        b.step_each([-1] + [1] * (len(ms) - 1))
+    b.close()
+
+
 @pytest.mark.parametrize("ppl,block", [(1, 64), (2, 128), (4, 256)])
 def test_batch_launch_shapes(gpu, ppl, block):
     ms = members(gpu, count=5)

@@ -10,7 +10,8 @@ from paper_1607_03062_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 
-def test_results_in_the_mix_equal_alone(gpu):
+@pytest.mark.parametrize("policy", ["lockstep", "srpt"])
+def test_results_in_the_mix_equal_alone(gpu, policy):
     ws = wl.config5(count=14, seed=5, rate_per_s=400.0, sizes=(64, 96, 128, 192), step_range=(800, 5000))
     # a few requests of the other schemes, precisions, polarisations and valleys in the stream
     extras = [("strang4", "fp32", "both", 0.0), ("midpoint", "fp64", "K-", 0.6), ("strang", "fp32fast", "K+", 0.8),
@@ -24,7 +25,8 @@ def test_results_in_the_mix_equal_alone(gpu):
     ex = serve.GpuExecutor(gpu, keep_n=True)
     fp = [ex.footprint(r) for r in reqs]
     budget = int(2.5 * max(fp))  # a few at a time: arrivals queue behind running solves
-    st = serve.Server(ex, budget, epoch_steps=700).run(reqs)
+    # srpt: a small time budget so that epochs give the solves unequal step counts
+    st = serve.Server(ex, budget, epoch_steps=700, policy=policy, epoch_ms=0.2).run(reqs)
     print("serve:", st.as_dict(), flush=True)
     assert st.completed == len(reqs) and st.peak_bytes <= budget
     assert any(r.admitted_s > r.arrival_s + 1e-4 for r in reqs)

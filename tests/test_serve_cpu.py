@@ -103,3 +103,65 @@ def test_solve_bytes_closed_form_matches_check_field():
             info = s.check_field(wl.sin2(0.2, 0.5, 8), 5000)
             assert s.solve_bytes(5000) == info["solve_bytes"] > 6000 * 8
             s.close()
+
+
+def mixed_stream(count=120, seed=7, rate=None):
+    """Poisson arrivals of grids 32^2..256^2 with 500..6000 steps (both precisions)."""
+    ws = wl.config5(count=count, seed=seed, rate_per_s=rate or 1.0, sizes=(32, 64, 128, 256),
+                    step_range=(500, 6000))
+    return [serve.Request.from_workload(w) for w in ws]
+
+
+def test_srpt_serves_everything_and_cuts_latency():
+    """At 0.7 load, shortest-remaining-work-first epochs complete every request and lower the
+    mean and median latency against lockstep epochs, at the same device throughput."""
+    rate_dev, tile = 2e10, 2e-6
+    probe = mixed_stream()
+    mean_work = np.mean([r.point_steps for r in probe]) / rate_dev
+    stats = {}
+    for policy in ("lockstep", "srpt"):
+        reqs = mixed_stream(rate=0.7 / mean_work)
+        ex = serve.FakeExecutor(rate_point_steps_per_s=rate_dev, tile_step_s=tile, epoch_overhead_s=1e-5)
+        srv = serve.Server(ex, 10 ** 12, epoch_steps=256, policy=policy, epoch_ms=1.0,
+                           rates={"fp32": rate_dev, "fp64": rate_dev}, tile_step_s=tile)
+        st = srv.run(reqs, simulated=True)
+        assert st.completed == len(reqs) and st.rejected == 0
+        assert all(r.status == "done" for r in reqs) and not srv.left
+        stats[policy] = st
+    assert stats["srpt"].mean_ms < 0.9 * stats["lockstep"].mean_ms
+    assert stats["srpt"].p50_ms < stats["lockstep"].p50_ms
+    assert stats["srpt"].makespan_s <= 1.05 * stats["lockstep"].makespan_s
+
+
+def test_srpt_epoch_plan():
+    """The plan fills the epoch's time budget with the least remaining work first, each solve
+    up to one tile's share of steps and never past its last step; a solve larger than the whole
+    budget still advances when it is alone."""
+    ex = serve.FakeExecutor()
+    srv = serve.Server(ex, 10 ** 12, epoch_steps=100, policy="srpt", epoch_ms=1.0,
+                       rates={"fp32": 1e9, "fp64": 1e9}, tile_step_s=1e-6)  # share = 1000 steps
+    sizes = {"a": (16, 5000), "b": (32, 300), "c": (64, 4000), "d": (256, 9000)}
+    for name, (n, steps) in sizes.items():
+        r = serve.Request(name, 0.0, wl.grid(n, 2.0), wl.sin2(0.1, 0.5, 8), steps)
+        srv.active[name] = r
+        srv.left[name] = steps
+    plan = srv.plan_epoch()
+    # remaining work: b 3.1e5 < a 1.3e6 < c 1.6e7 < d 5.9e8 point-steps; budget 1e6 point-steps
+    assert plan["b"] == 300 and plan["a"] == 1000
+    assert "d" not in plan
+    used = sum(srv.active[k].points * m for k, m in plan.items())
+    assert used <= 1e6 + 1e-6
+    assert all(m <= srv.left[k] for k, m in plan.items())
+    for k in ("a", "b", "c"):
+        del srv.active[k], srv.left[k]
+    assert srv.plan_epoch() == {"d": 15}  # 1e6 / 65536 points
+    srv.rates = {"fp32": 1e6, "fp64": 1e6}  # now larger than the whole budget
+    assert srv.plan_epoch() == {"d": 100}
+
+
+def test_policy_arguments_are_checked():
+    ex = serve.FakeExecutor()
+    with pytest.raises(ValueError):
+        serve.Server(ex, 10 ** 9, policy="fifo")
+    with pytest.raises(ValueError):
+        serve.Server(ex, 10 ** 9, policy="srpt", epoch_ms=0)
