@@ -19,7 +19,10 @@ How an epoch shares the device is the policy:
             take an epoch's time budget (`epoch_ms`) in that order, each up to
             the steps one tile of it runs in that time; the largest may get
             none in an epoch.  This cuts the waiting of small solves behind
-            large ones at the same device throughput.
+            large ones at the same device throughput.  Solves that got no steps
+            for `max_wait_epochs` epochs in a row go first (the longest waiting
+            first, each with at least a minimal share), so a large request keeps
+            advancing even when a flow of small ones could fill every epoch.
 
 The device work is in libpd; this module is the host-side scheduler.  The
 executor interface (footprint / admit / epoch / release) has a GPU
@@ -220,13 +223,15 @@ DEFAULT_TILE_STEP_S = 0.43e-6
 class Server:
     def __init__(self, executor, budget_bytes: int, epoch_steps: int = 2048, max_active: int = 4096,
                  backfill: bool = False, policy: str = "lockstep", epoch_ms: float = 3.0, rates: dict = None,
-                 tile_step_s: float = DEFAULT_TILE_STEP_S):
+                 tile_step_s: float = DEFAULT_TILE_STEP_S, max_wait_epochs: int = 32):
         if epoch_steps < 1:
             raise ValueError("epoch_steps must be >= 1")
         if policy not in ("lockstep", "srpt"):
             raise ValueError("policy must be 'lockstep' or 'srpt'")
         if not (epoch_ms > 0 and tile_step_s > 0):
             raise ValueError("epoch_ms and tile_step_s must be > 0")
+        if max_wait_epochs < 1:
+            raise ValueError("max_wait_epochs must be >= 1")
         self.ex = executor
         self.budget = int(budget_bytes)
         self.epoch_steps = int(epoch_steps)
@@ -236,6 +241,8 @@ class Server:
         self.epoch_s = epoch_ms * 1e-3
         self.rates = dict(DEFAULT_RATES, **(rates or {}))
         self.tile_step_s = tile_step_s
+        self.max_wait = int(max_wait_epochs)
+        self.waited = {}  # request name -> epochs in a row without steps (srpt)
         self.in_use = 0
         self.peak = 0
         self.active = {}
@@ -248,15 +255,24 @@ class Server:
         budget = self.epoch_s
         share = max(self.epoch_steps, int(self.epoch_s / self.tile_step_s))  # steps a tile runs in an epoch
         rate = {name: self.rates.get(r.precision, self.rates["fp32"]) for name, r in self.active.items()}
-        order = sorted(self.left, key=lambda n: (self.active[n].points * self.left[n] / rate[n], n))
+        # solves that waited max_wait epochs in a row first, the longest waiting first;
+        # then the least remaining work first
+        def key(n):
+            w = self.waited.get(n, 0)
+            return (0, -w, n) if w >= self.max_wait else (1, self.active[n].points * self.left[n] / rate[n], n)
+
+        order = sorted(self.left, key=key)
         plan = {}
         for name in order:
             pts = self.active[name].points
             m = min(self.left[name], share)
             if pts * m / rate[name] > budget:
                 m = int(budget * rate[name] / pts)
-                if m < min(self.left[name], self.epoch_steps // 8 or 1):
-                    continue  # too little left for a useful share of this solve
+                floor = min(self.left[name], self.epoch_steps // 8 or 1)
+                if m < floor:
+                    if self.waited.get(name, 0) < self.max_wait:
+                        continue  # too little of the budget left for a useful share of this solve
+                    m = floor  # a solve that waited long advances, past the budget if need be
             plan[name] = m
             budget -= pts * m / rate[name]
             if budget <= 0:
@@ -322,6 +338,8 @@ class Server:
                 break
             plan = self.plan_epoch()
             done = self.ex.epoch_each(plan)
+            for name in self.left:
+                self.waited[name] = 0 if plan.get(name, 0) > 0 else self.waited.get(name, 0) + 1
             for name, m in plan.items():
                 self.left[name] -= m
             epochs += 1
@@ -329,6 +347,7 @@ class Server:
             now = self._now(t0, simulated)
             for name, rho in done:
                 del self.left[name]
+                self.waited.pop(name, None)
                 r = self.active.pop(name)
                 r.rho, r.done_s, r.status = rho, now, "done"
                 self.in_use -= r.bytes

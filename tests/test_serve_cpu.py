@@ -165,3 +165,35 @@ def test_policy_arguments_are_checked():
         serve.Server(ex, 10 ** 9, policy="fifo")
     with pytest.raises(ValueError):
         serve.Server(ex, 10 ** 9, policy="srpt", epoch_ms=0)
+
+
+def test_srpt_does_not_starve_a_large_request():
+    """Overload: small requests (1 ms of device time each) arrive every 0.8 ms after a large
+    one, so that on their own they would take every epoch.  Without aging the large request
+    gets no steps until the stream ends; with aging (max_wait_epochs = 8) the solves that
+    waited long are served in turn, the longest waiting first, and the large one keeps
+    advancing while the stream lasts."""
+    def progress_by_last_arrival(max_wait):
+        rate_dev, tile = 1e9, 1e-6
+        big = serve.Request("big", 0.0, wl.grid(256, 2.0), wl.sin2(0.1, 0.5, 8), 3000)
+        smalls = [serve.Request("s%d" % i, 8e-4 * i, wl.grid(32, 2.0), wl.sin2(0.1, 0.5, 8), 1000)
+                  for i in range(1, 800)]
+        ex = serve.FakeExecutor(rate_point_steps_per_s=rate_dev, tile_step_s=tile)
+        srv = serve.Server(ex, 10 ** 12, epoch_steps=100, policy="srpt", epoch_ms=1.0,
+                           rates={"fp32": rate_dev, "fp64": rate_dev}, tile_step_s=tile, max_wait_epochs=max_wait)
+        seen = []
+        epoch_each = ex.epoch_each
+
+        def record(steps):
+            out = epoch_each(steps)
+            seen.append((ex.clock, ex.active["big"][1] if "big" in ex.active else big.n_steps))
+            return out
+        ex.epoch_each = record
+        st = srv.run([big] + smalls, simulated=True)
+        assert big.status == "done" and st.completed == len(smalls) + 1
+        return max(k for clock, k in seen if clock <= smalls[-1].arrival_s)
+
+    starved = progress_by_last_arrival(10 ** 9)
+    aged = progress_by_last_arrival(8)
+    assert starved <= 100  # only the epochs before the small requests arrived
+    assert aged >= 150 and aged >= 5 * starved
