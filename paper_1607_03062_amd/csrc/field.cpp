@@ -219,13 +219,15 @@ bool sample_field(const pd_field& f, long long n_steps, const Composition& comp,
     t.Ay_in = t.elliptic ? f.Ay_in : 0.0;
     t.Ay_out = t.elliptic ? f.Ay_out : 0.0;
   } else {
-    double ax, ay;
-    for (long long k = 0; k < n_steps; ++k)
-      for (int j = 0; j < S; ++j) {
-        eval_A(f, t.t_i + ((double)k + comp.sigma[j]) * t.dt, &ax, &ay);
-        t.A_mid[(size_t)k * S + j] = ax;
-        if (t.elliptic) t.Ay_mid[(size_t)k * S + j] = ay;
-      }
+    parallel_ranges(n_steps, 8192, [&](long long k0, long long k1) {
+      double ax, ay;
+      for (long long k = k0; k < k1; ++k)
+        for (int j = 0; j < S; ++j) {
+          eval_A(f, t.t_i + ((double)k + comp.sigma[j]) * t.dt, &ax, &ay);
+          t.A_mid[(size_t)k * S + j] = ax;
+          if (t.elliptic) t.Ay_mid[(size_t)k * S + j] = ay;
+        }
+    });
     eval_A(f, t.t_i, &t.A_in, &t.Ay_in);
     eval_A(f, t.t_f, &t.A_out, &t.Ay_out);
   }

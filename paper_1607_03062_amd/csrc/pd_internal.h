@@ -3,12 +3,42 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "pd.h"
 
 namespace pdx {
+
+// Calls body(begin, end) on contiguous ranges that together cover [0, n): on up to
+// 16 host threads when n is at least 2 * grain (the calling thread takes the first
+// range), else once on the calling thread.  A range whose thread cannot be started
+// runs on the calling thread.  body must not throw; the ranges write disjoint data.
+template <typename F>
+void parallel_ranges(long long n, long long grain, F&& body) {
+  const unsigned hw = std::thread::hardware_concurrency();
+  const long long nt = std::min<long long>(std::min<long long>(hw ? hw : 1, 16), n / std::max(grain, 1LL));
+  if (nt <= 1) {
+    if (n > 0) body(0LL, n);
+    return;
+  }
+  const long long chunk = (n + nt - 1) / nt;
+  std::vector<std::thread> pool;
+  pool.reserve((size_t)nt);
+  for (long long t = 1; t < nt; ++t) {
+    const long long b = t * chunk, e = std::min(n, b + chunk);
+    if (b >= e) break;
+    try {
+      pool.emplace_back([&body, b, e] { body(b, e); });
+    } catch (...) {
+      body(b, e);
+    }
+  }
+  body(0LL, std::min(n, chunk));
+  for (auto& th : pool) th.join();
+}
 
 // Stages of a step: 1 for the second-order schemes, 5 for Suzuki's fourth-order
 // composition S(c1 dt) ... S(c5 dt), c = (p, p, 1 - 4p, p, p), p = 1/(4 - 4^(1/3));

@@ -8,7 +8,9 @@ fields along x, the others' own launches after it), with every solve's state
 resident in device memory between epochs.  Solves that reach their last step are
 projected and reduced in the same epoch and leave the set; arrivals are admitted
 between epochs, in arrival order, while their device footprint (tables, state,
-n(p), partials; pd_info.solve_bytes) fits in the memory budget.  A request larger
+n(p), partials; pd_info.solve_bytes) fits in the memory budget, at most
+`admit_per_epoch` at a time so that a burst of arrivals is set up on the host while
+the device runs the epochs of those already admitted.  A request larger
 than the whole budget is rejected.  Latency is the time from a request's arrival
 to its density being on the host.
 
@@ -223,7 +225,7 @@ DEFAULT_TILE_STEP_S = 0.43e-6
 class Server:
     def __init__(self, executor, budget_bytes: int, epoch_steps: int = 2048, max_active: int = 4096,
                  backfill: bool = False, policy: str = "lockstep", epoch_ms: float = 3.0, rates: dict = None,
-                 tile_step_s: float = DEFAULT_TILE_STEP_S, max_wait_epochs: int = 32):
+                 tile_step_s: float = DEFAULT_TILE_STEP_S, max_wait_epochs: int = 32, admit_per_epoch: int = 4):
         if epoch_steps < 1:
             raise ValueError("epoch_steps must be >= 1")
         if policy not in ("lockstep", "srpt"):
@@ -232,6 +234,8 @@ class Server:
             raise ValueError("epoch_ms and tile_step_s must be > 0")
         if max_wait_epochs < 1:
             raise ValueError("max_wait_epochs must be >= 1")
+        if admit_per_epoch < 1:
+            raise ValueError("admit_per_epoch must be >= 1")
         self.ex = executor
         self.budget = int(budget_bytes)
         self.epoch_steps = int(epoch_steps)
@@ -242,6 +246,7 @@ class Server:
         self.rates = dict(DEFAULT_RATES, **(rates or {}))
         self.tile_step_s = tile_step_s
         self.max_wait = int(max_wait_epochs)
+        self.admit_per_epoch = int(admit_per_epoch)
         self.waited = {}  # request name -> epochs in a row without steps (srpt)
         self.in_use = 0
         self.peak = 0
@@ -304,9 +309,12 @@ class Server:
                     r.done_s = now
                     continue
                 waiting.append(r)
-            # admit in arrival order while memory and slots allow (optionally skipping a blocked head)
+            # admit in arrival order while memory and slots allow (optionally skipping a blocked
+            # head), at most admit_per_epoch before the next epoch: the device then runs that
+            # epoch (enqueued without waiting) while the host sets up the next arrivals
             blocked = []
-            while waiting and len(self.active) < self.max_active:
+            admitted = 0
+            while waiting and len(self.active) < self.max_active and admitted < self.admit_per_epoch:
                 r = waiting[0]
                 if self.in_use + r.bytes <= self.budget:
                     waiting.popleft()
@@ -316,6 +324,7 @@ class Server:
                         r.status, r.reason, r.done_s = "rejected", str(e), now
                         continue
                     r.admitted_s, r.status = now, "active"
+                    admitted += 1
                     self.active[r.name] = r
                     self.left[r.name] = r.n_steps
                     self.in_use += r.bytes

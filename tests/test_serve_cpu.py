@@ -197,3 +197,25 @@ def test_srpt_does_not_starve_a_large_request():
     aged = progress_by_last_arrival(8)
     assert starved <= 100  # only the epochs before the small requests arrived
     assert aged >= 150 and aged >= 5 * starved
+
+
+def test_admissions_per_epoch_are_capped():
+    """A burst of 10 requests at t = 0 with admit_per_epoch = 3: the first epochs run with 3, 6
+    and 9 admitted solves, in arrival order; all complete."""
+    ex = serve.FakeExecutor(rate_point_steps_per_s=1e10)
+    reqs = [serve.Request("r%d" % i, 0.0, wl.grid(64, 2.0), wl.sin2(0.1, 0.5, 8), 20000) for i in range(10)]
+    srv = serve.Server(ex, 10 ** 12, epoch_steps=512, admit_per_epoch=3)
+    sizes = []
+    epoch_each = ex.epoch_each
+
+    def record(steps):
+        sizes.append(len(ex.active))
+        return epoch_each(steps)
+    ex.epoch_each = record
+    st = srv.run(reqs, simulated=True)
+    assert sizes[:4] == [3, 6, 9, 10]
+    assert st.completed == 10
+    adm = [r.admitted_s for r in reqs]
+    assert all(a <= b for a, b in zip(adm, adm[1:]))
+    with pytest.raises(ValueError):
+        serve.Server(ex, 10 ** 9, admit_per_epoch=0)
