@@ -198,7 +198,9 @@ pd_status pd_set_valley(pd_grid g, int valley);
    table of the field on the host (A at the step midpoints, Sec. III,
    Eqs. (11)-(12)), uploads it with a blocking copy, allocates the handle's
    device buffers on first use and resets the solve to t_i (steps_done = 0).
-   Same validation as pd_check_field. */
+   Same validation as pd_check_field.  For long solves (16384 steps or more) the
+   sampling of an analytic field runs on up to 16 short-lived host threads,
+   joined before the call returns. */
 pd_status pd_set_field(pd_grid g, const pd_field* f, long long n_steps);
 
 /* Restart the solve at t_i (steps_done = 0) with the field already set; the
