@@ -309,8 +309,8 @@ def main():
                     help="also run a plain device copy of this many MiB (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the solve shards over momentum points; "
-              "multi-GPU runs are not part of it). Use --gpus 1.", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU only (a solve would shard over bands of momentum "
+              "rows, one reduction of rho; not implemented here). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -52,7 +52,7 @@ typedef enum {
   PD_ERR_STATE = 2,       /* call out of order (e.g. pd_density before the last step) */
   PD_ERR_NOMEM = 3,       /* a device or host allocation failed */
   PD_ERR_DEVICE = 4,      /* a HIP call failed (no device, launch failure, ...) */
-  PD_ERR_UNSUPPORTED = 5  /* a valid request this build does not implement */
+  PD_ERR_UNSUPPORTED = 5  /* a valid request the library does not implement */
 } pd_status;
 
 typedef enum {
