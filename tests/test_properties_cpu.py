@@ -104,3 +104,24 @@ def test_pulse_without_flat_part_is_accepted():
     Ax, Ay, ends = _lib.sample_field_xy(f, 200, "strang")
     Ao = oracle.field_table(f, 200)[0]
     assert np.max(np.abs(Ax - Ao)) <= 1e-13
+
+
+def test_long_field_sampling_matches_oracle():
+    """Long solves sample A on several host threads (contiguous ranges of steps): every sample,
+    end value and dt still equals the oracle's, for each analytic kind, both polarisations and
+    both stage counts."""
+    fields = [{"kind": "sin2", "E0": 0.3, "omega": 0.5, "cycles": 30, "ellipticity": 0.6},
+              {"kind": "pulse", "E0": 1.0, "omega": 0.4876, "phi": 0.3, "omega_rise": 0.0609, "omega_fall": 0.0609,
+               "duration": 70.9},
+              {"kind": "constant", "E0": 0.2, "t_end": 200.0, "ellipticity": -0.4}]
+    for field in fields:
+        for n, scheme in ((50000, "strang"), (20000, "strang4")):
+            Ax, Ay, ends = _lib.sample_field_xy(field, n, scheme)
+            Ao, ax_in, ax_out, dt = oracle.field_table(field, n, scheme)
+            Ayo, ay_in, ay_out = oracle.field_table_y(field, n, scheme)
+            scale = max(1.0, float(np.abs(Ao).max()), float(np.abs(Ayo).max()))
+            assert Ax.shape == Ao.shape and Ay.shape == Ayo.shape
+            assert np.max(np.abs(Ax - Ao)) <= 1e-13 * scale, (field["kind"], scheme)
+            assert np.max(np.abs(Ay - Ayo)) <= 1e-13 * scale, (field["kind"], scheme)
+            assert abs(ends[2] - ax_in) <= 1e-13 * scale and abs(ends[3] - ax_out) <= 1e-13 * scale
+            assert abs((ends[1] - ends[0]) / n - dt) <= 1e-15 * max(1.0, dt)
