@@ -255,6 +255,17 @@ size_t pd_solve_bytes(pd_grid g, long long n_steps);
    dev_ptr = NULL returns to the handle's own buffer. */
 pd_status pd_bind_state(pd_grid g, void* dev_ptr, size_t bytes);
 
+/* Checkpoint and restart: declare that the buffer bound with pd_bind_state holds
+   the state after steps_done steps of this same solve (the same grid, field,
+   step count, precision, scheme and valley), as a chunked pd_propagate that
+   stopped there left it (for example saved to a file and copied back), so that
+   the next pd_propagate continues from it.  The continuation is bit-identical to
+   the uninterrupted solve.  1 <= steps_done <= N - 1.  PD_ERR_STATE before
+   pd_set_field or with no buffer bound; PD_ERR_INVALID for steps_done out of
+   range.  The content of the buffer is the caller's responsibility: another
+   solve's state gives that solve's continuation, not this one's. */
+pd_status pd_resume(pd_grid g, long long steps_done);
+
 /* Override the launch shape of the propagation kernel: points_per_lane in
    {1, 2, 4}; block_threads in {64, 128, 256}; table_stage 1 = the per-step
    field rows are staged through LDS in time chunks (read from VGPRs), 2 = read

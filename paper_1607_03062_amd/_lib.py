@@ -110,6 +110,7 @@ SIGNATURES = [
     ("pd_set_valley", ctypes.c_int, [_vp, ctypes.c_int]),
     ("pd_set_field", ctypes.c_int, [_vp, ctypes.POINTER(pd_field), ctypes.c_longlong]),
     ("pd_rewind", ctypes.c_int, [_vp]),
+    ("pd_resume", ctypes.c_int, [_vp, ctypes.c_longlong]),
     ("pd_propagate", ctypes.c_int, [_vp, ctypes.c_longlong, _vp]),
     ("pd_density", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _vp]),
     ("pd_snapshot", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _vp]),
@@ -284,6 +285,12 @@ class Solver:
 
     def rewind(self):
         check(load().pd_rewind(self._h), "pd_rewind")
+        return self
+
+    def resume(self, steps_done: int):
+        """Continue from the state in the bound buffer (bind_state), which holds this solve's
+        state after steps_done steps (e.g. a checkpoint copied back)."""
+        check(load().pd_resume(self._h, int(steps_done)), "pd_resume")
         return self
 
     def propagate(self, max_steps: int = -1, stream=None):

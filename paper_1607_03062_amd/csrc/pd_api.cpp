@@ -373,6 +373,16 @@ pd_status pd_bind_state(pd_grid g, void* dev_ptr, size_t bytes) {
   return ok();
 }
 
+pd_status pd_resume(pd_grid g, long long steps_done) {
+  if (!g) return fail(PD_ERR_INVALID, "null handle");
+  if (!g->field_set) return fail(PD_ERR_STATE, "pd_resume before pd_set_field");
+  if (!g->d_state_bound) return fail(PD_ERR_STATE, "pd_resume needs a state buffer bound with pd_bind_state");
+  if (steps_done < 1 || steps_done >= g->field.n_steps)
+    return fail(PD_ERR_INVALID, "steps_done = %lld outside 1 .. N - 1 (N = %lld)", steps_done, g->field.n_steps);
+  g->steps_done = steps_done;
+  return ok();
+}
+
 pd_status pd_set_launch(pd_grid g, int points_per_lane, int block_threads, int table_stage, int chunk_steps) {
   if (!g) return fail(PD_ERR_INVALID, "null handle");
   if (points_per_lane != 0 && points_per_lane != 1 && points_per_lane != 2 && points_per_lane != 4)

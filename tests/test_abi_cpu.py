@@ -248,6 +248,9 @@ def test_state_errors_without_device():
         s.set_launch(0, 0, 0, 100)
     with pytest.raises(pd.PDError):
         s.set_launch(0, 0, 0, 8192)
+    with pytest.raises(pd.PDError) as e:
+        s.resume(10)  # before pd_set_field
+    assert e.value.status == _lib.PD_ERR_STATE and "pd_set_field" in e.value.message
     s.set_launch(4, 64, 1, 256)
     info = s.info()
     assert (info["points_per_lane"], info["block_threads"], info["table_stage"], info["chunk_steps"]) == (4, 64, 1, 256)

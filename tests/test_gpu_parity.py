@@ -124,6 +124,46 @@ def test_chunked_equals_single_launch(gpu, precision, scheme):
     assert np.array_equal(single[0], bound[0])
 
 
+@pytest.mark.parametrize("precision,scheme,N,k", [("fp32", "strang", 3000, 1500), ("fp64", "strang", 2777, 1024),
+                                                  ("fp64", "midpoint", 3000, 2047), ("fp32", "midpoint", 2600, 700),
+                                                  ("fp32", "strang4", 600, 333)])
+def test_checkpoint_and_resume(gpu, precision, scheme, N, k):
+    """A chunked solve stops after k steps and its bound state is saved to host memory; a new
+    handle for the same solve gets the saved state in its own bound buffer, resumes at k and
+    finishes: n(p) and rho bit-identical to the uninterrupted solve.  (The elliptic field puts
+    the fourth-order case on the y-component path.)"""
+    import torch
+
+    field = dict(RAGGED_FIELD, ellipticity=0.5) if scheme == "strang4" else RAGGED_FIELD
+    single = run(gpu, RAGGED, field, N, precision, scheme)
+    s = gpu.Solver.for_grid(RAGGED, precision, scheme)
+    s.set_field(field, N)
+    nb = s.state_bytes()
+    buf = torch.zeros(nb // 4 + 64, dtype=torch.float32, device="cuda")
+    s.bind_state(buf)
+    s.propagate(k)
+    torch.cuda.synchronize()
+    saved = buf.cpu().clone()
+    s.close()
+    del buf
+    s2 = gpu.Solver.for_grid(RAGGED, precision, scheme)
+    s2.set_field(field, N)
+    with pytest.raises(gpu.PDError):
+        s2.resume(k)  # no buffer bound yet
+    buf2 = saved.to("cuda")
+    s2.bind_state(buf2)
+    for bad in (0, N):
+        with pytest.raises(gpu.PDError):
+            s2.resume(bad)
+    s2.resume(k)
+    assert s2.info()["steps_done"] == k
+    s2.propagate(-1)
+    n = np.empty(RAGGED["nx"] * RAGGED["ny"])
+    rho = s2.density(n_out=n)
+    s2.close()
+    assert np.array_equal(n, single[0]) and rho == single[1]
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_midpoint_step_forms(gpu, precision):
     """Both forms of the midpoint step match the oracle: the tangent form (step angles
