@@ -14,7 +14,7 @@ from .test_gpu_parity import FP32_N_ABS, FP64_N_ABS
 
 pytestmark = pytest.mark.gpu
 
-N_CASES = 40
+N_CASES = 100
 
 
 def draw_case(seed):
