@@ -5,7 +5,7 @@ momentum grid on [-2,2]^2 under the sin^2 pulse (E0 = 0.1, omega = 0.5, 30
 cycles), 80000 Strang steps (state init, propagation, projection on u_out,
 density reduction and the copy of rho to the host).  The field table is
 resident in HBM before the timed region (pd_set_field once, pd_rewind per
-step).  The FP64 form and the fast FP32 form (plain shears, PD_FP32_FAST) of the
+step).  The FP64 form and the fast FP32 form (alternating plain shears, PD_FP32_FAST) of the
 same workload are timed beside it, and all are checked against the FP64 CPU
 oracle on the 64 x 64 subsample (stride 32) and on the larger sample whose
 oracle run is also the CPU baseline.
@@ -30,7 +30,7 @@ METRIC = "momentum point-steps/s (FP32 vs FP64 form) at stated n(p) error; p50/p
 # rotations of the Bloch vector per Strang step.
 #   shear form (every rotation angle <= pi/2): 3 FMA per rotation -> 9 FMA = 18 flop, 9 VALU instructions
 #     FP32 form: each component rounded once per rotation, 3 FMA + 1 add -> 21 flop, 12 instructions
-#     (fp32fast: the plain shears, 18 flop, 9 instructions)
+#     (fp32fast: plain shears of alternating orientation, 18 flop, 9 instructions)
 #   versine form, FP64: 2 FMA per rotated component -> 12 FMA = 24 flop, 12 instructions
 #   versine form, FP32: mul + fma + add per rotated component -> 24 flop, 18 instructions
 ALGO = {(0, "fp64"): (18, 9), (0, "fp32"): (21, 12), (0, "fp32fast"): (18, 9),

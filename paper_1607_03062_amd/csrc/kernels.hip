@@ -100,13 +100,41 @@ __device__ __forceinline__ void rotate_shear_once(float& u, float& v, float t, f
   v = v1;
 }
 
-// A rotation in the solve's form; ONCE selects the once-rounded shears (FP32 form).
-template <int FORM, int ONCE, typename R>
-__device__ __forceinline__ void rot(R& u, R& v, R a, R s) {
-  if constexpr (FORM == kFormShear && ONCE && sizeof(R) == 4)
+// The same shear rotation with the roles of u and v exchanged: v += t u; u -= s v;
+// v += t u.  Now v is the component rounded twice.
+template <typename R>
+__device__ __forceinline__ void rotate_shear_vu(R& u, R& v, R t, R s) {
+  v = fma(t, u, v);
+  u = fma(-s, v, u);
+  v = fma(t, u, v);
+}
+
+// Shear variants (FP32 forms):
+//   kShearPlain  u -= t v; v += s u; u -= t v (u rounded twice per rotation);
+//   kShearOnce   each component rounded once (rotate_shear_once, 4 instructions);
+//   kShearAlt    the plain triple with its orientation alternating from one stage to
+//                the next (u-v-u, then v-u-v; the parity of the absolute stage index),
+//                so that the doubly rounded component alternates: 3 instructions, and
+//                the systematic part of the two roundings largely cancels between
+//                neighbouring stages.
+constexpr int kShearPlain = 0;
+constexpr int kShearOnce = 1;
+constexpr int kShearAlt = 2;
+
+// A rotation in the solve's form and shear variant SH; odd: the stage's parity
+// (kShearAlt only; a compile-time constant wherever the steps are unrolled).
+template <int FORM, int SH, typename R>
+__device__ __forceinline__ void rot(R& u, R& v, R a, R s, bool odd = false) {
+  if constexpr (FORM == kFormShear && SH == kShearOnce && sizeof(R) == 4) {
     rotate_shear_once(u, v, a, s);
-  else
+  } else if constexpr (FORM == kFormShear && SH == kShearAlt) {
+    if (odd)
+      rotate_shear_vu(u, v, a, s);
+    else
+      rotate_shear(u, v, a, s);
+  } else {
     rotate<FORM>(u, v, a, s);
+  }
 }
 
 struct PointCoords {
@@ -149,7 +177,7 @@ struct Layout<5> {
 };
 
 // The Bloch vectors of a lane's points and their per-point rotations.
-template <typename R, int PPL, int FORM, int NS, int POL, int ONCE>
+template <typename R, int PPL, int FORM, int NS, int POL, int SH>
 struct BlochLanes {
   using L = Layout<NS>;
   static constexpr int kRow = 2 * NS * (1 + POL);  // table values per step
@@ -158,22 +186,32 @@ struct BlochLanes {
   R aY[L::NY - 1][PPL], sY[L::NY - 1][PPL];  // y rotations after the stages, by (c_j + c_j+1) dt py
 
   // One step; row = the step's table values.  LAST: the y rotation after the
-  // last stage is the closing half step (ha, hs per point).
+  // last stage is the closing half step (ha, hs per point).  odd: the parity of
+  // the step's absolute index (stage j of step k has parity k + j, NS odd).
   template <bool LAST>
-  __device__ __forceinline__ void step(const R* row, const R* ha, const R* hs) {
+  __device__ __forceinline__ void step(const R* row, const R* ha, const R* hs, bool odd = false) {
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
+      const bool o = odd != ((j & 1) != 0);
 #pragma unroll
       for (int q = 0; q < PPL; ++q) {
-        rot<FORM, ONCE>(y[q], z[q], row[2 * j], row[2 * j + 1]);
-        rot<FORM, ONCE>(y[q], z[q], aX[L::xcls(j)][q], sX[L::xcls(j)][q]);
+        rot<FORM, SH>(y[q], z[q], row[2 * j], row[2 * j + 1], o);
+        rot<FORM, SH>(y[q], z[q], aX[L::xcls(j)][q], sX[L::xcls(j)][q], o);
         if (LAST && j == NS - 1)
-          rot<FORM, ONCE>(z[q], x[q], ha[q], hs[q]);
+          rot<FORM, SH>(z[q], x[q], ha[q], hs[q], o);
         else
-          rot<FORM, ONCE>(z[q], x[q], aY[L::ycls(j)][q], sY[L::ycls(j)][q]);
-        if (POL) rot<FORM, ONCE>(z[q], x[q], row[2 * NS + 2 * j], row[2 * NS + 2 * j + 1]);
+          rot<FORM, SH>(z[q], x[q], aY[L::ycls(j)][q], sY[L::ycls(j)][q], o);
+        if (POL) rot<FORM, SH>(z[q], x[q], row[2 * NS + 2 * j], row[2 * NS + 2 * j + 1], o);
       }
     }
+  }
+
+  // A step whose parity is known only at run time (uniform over the wave).
+  __device__ __forceinline__ void step_at(const R* row, long long k) {
+    if (SH == kShearAlt && (k & 1))
+      step<false>(row, nullptr, nullptr, true);
+    else
+      step<false>(row, nullptr, nullptr, false);
   }
 
   __device__ __forceinline__ void renormalise() {
@@ -196,10 +234,10 @@ struct RowN {
 };
 
 // Steps [k, k_full) with the table rows read by the scalar unit (SGPR operands).
-template <typename R, int PPL, int FORM, int NS, int POL, int ONCE>
-__device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM, NS, POL, ONCE>& L, const R* __restrict__ table,
+template <typename R, int PPL, int FORM, int NS, int POL, int SH>
+__device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM, NS, POL, SH>& L, const R* __restrict__ table,
                                              long long k, long long k_full) {
-  using Lanes = BlochLanes<R, PPL, FORM, NS, POL, ONCE>;
+  using Lanes = BlochLanes<R, PPL, FORM, NS, POL, SH>;
   using Row = RowN<R, Lanes::kRow>;
   const Row* __restrict__ tab = reinterpret_cast<const Row*>(table);
   while (k < k_full) {
@@ -209,16 +247,29 @@ __device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM, NS, POL, O
       seg = next < k_full ? next : k_full;
     }
     constexpr int kGroup = Lanes::kRow >= 8 ? 1 : 8 / (Lanes::kRow / 2);  // rows fetched together
+    if constexpr (SH == kShearAlt && kGroup % 2 == 0) {
+      // groups start at even steps, so a step's parity is its place in the group
+      if ((k & 1) && k < seg) {
+        const Row r = tab[k];
+        L.step_at(r.v, k);
+        ++k;
+      }
+    }
     for (; k + kGroup <= seg; k += kGroup) {
       Row r[kGroup];
 #pragma unroll
       for (int u = 0; u < kGroup; ++u) r[u] = tab[k + u];
+      if constexpr (SH == kShearAlt && kGroup % 2 == 1) {
 #pragma unroll
-      for (int u = 0; u < kGroup; ++u) L.template step<false>(r[u].v, nullptr, nullptr);
+        for (int u = 0; u < kGroup; ++u) L.step_at(r[u].v, k + u);
+      } else {
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) L.template step<false>(r[u].v, nullptr, nullptr, (u & 1) != 0);
+      }
     }
     for (; k < seg; ++k) {
       const Row r = tab[k];
-      L.template step<false>(r.v, nullptr, nullptr);
+      L.step_at(r.v, k);
     }
     if (sizeof(R) == 4 && (k % kRenormEvery) == 0) L.renormalise();
   }
@@ -227,10 +278,10 @@ __device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM, NS, POL, O
 // Steps [k, k_full) with the table staged through LDS in chunks of `chunk` rows
 // (absolute chunk boundaries; a power of two dividing the renormalisation period
 // in the FP32 form), so every lane reads its rotation from VGPRs.
-template <typename R, int PPL, int FORM, int NS, int POL, int ONCE>
-__device__ __forceinline__ void steps_lds(BlochLanes<R, PPL, FORM, NS, POL, ONCE>& L, const R* __restrict__ table,
+template <typename R, int PPL, int FORM, int NS, int POL, int SH>
+__device__ __forceinline__ void steps_lds(BlochLanes<R, PPL, FORM, NS, POL, SH>& L, const R* __restrict__ table,
                                           long long k, long long k_full, long long chunk) {
-  using Lanes = BlochLanes<R, PPL, FORM, NS, POL, ONCE>;
+  using Lanes = BlochLanes<R, PPL, FORM, NS, POL, SH>;
   using Row = RowN<R, Lanes::kRow>;
   const Row* __restrict__ tab = reinterpret_cast<const Row*>(table);
   extern __shared__ unsigned char pd_lds[];
@@ -242,10 +293,30 @@ __device__ __forceinline__ void steps_lds(BlochLanes<R, PPL, FORM, NS, POL, ONCE
     __syncthreads();  // every wave has finished with the previous chunk
     for (int t = threadIdx.x; t < cnt; t += blockDim.x) rows[t] = tab[k + t];
     __syncthreads();
+    if constexpr (SH == kShearAlt) {
+      // in pairs from an even step: parities known at compile time
+      int t = 0;
+      if (k & 1) {
+        const Row r = rows[0];
+        L.step_at(r.v, k);
+        t = 1;
+      }
+#pragma unroll 4
+      for (; t + 1 < cnt; t += 2) {
+        const Row r0 = rows[t], r1 = rows[t + 1];
+        L.template step<false>(r0.v, nullptr, nullptr, false);
+        L.template step<false>(r1.v, nullptr, nullptr, true);
+      }
+      if (t < cnt) {
+        const Row r = rows[t];
+        L.step_at(r.v, k + t);
+      }
+    } else {
 #pragma unroll 8
-    for (int t = 0; t < cnt; ++t) {
-      const Row r = rows[t];
-      L.template step<false>(r.v, nullptr, nullptr);
+      for (int t = 0; t < cnt; ++t) {
+        const Row r = rows[t];
+        L.template step<false>(r.v, nullptr, nullptr);
+      }
     }
     k = cend;
     if (sizeof(R) == 4 && (k % kRenormEvery) == 0) L.renormalise();
@@ -254,9 +325,9 @@ __device__ __forceinline__ void steps_lds(BlochLanes<R, PPL, FORM, NS, POL, ONCE
 
 // One tile of a Strang solve: the block's lanes own points base + q * blockDim.x,
 // q < PPL; steps [p.k_begin, p.k_end).
-template <typename R, int PPL, int STAGE, int FORM, int NS, int POL, int ONCE>
+template <typename R, int PPL, int STAGE, int FORM, int NS, int POL, int SH>
 __device__ __forceinline__ void strang_tile(const SolveParams& p, const long long base) {
-  using Lanes = BlochLanes<R, PPL, FORM, NS, POL, ONCE>;
+  using Lanes = BlochLanes<R, PPL, FORM, NS, POL, SH>;
   using LY = Layout<NS>;
   constexpr int CX = 2 * LY::NX, CY = 2 * LY::NY;  // coefficient values per column / row
   constexpr int HALF = 2 * (LY::NY - 1);           // offset of the half-step pair in a row
@@ -299,10 +370,10 @@ __device__ __forceinline__ void strang_tile(const SolveParams& p, const long lon
       L.y[q] = (R)ry;
       L.z[q] = (R)0;
       // opening half step about y: per-point part, then (POL) the field part
-      rot<FORM, ONCE>(L.z[q], L.x[q], rowc[CY * c.j + HALF], rowc[CY * c.j + HALF + 1]);
+      rot<FORM, SH>(L.z[q], L.x[q], rowc[CY * c.j + HALF], rowc[CY * c.j + HALF + 1]);
       if (POL) {
         const R* open = table + (size_t)p.n_steps * Lanes::kRow + 2 * NS;
-        rot<FORM, ONCE>(L.z[q], L.x[q], open[0], open[1]);
+        rot<FORM, SH>(L.z[q], L.x[q], open[0], open[1]);
       }
     }
   }
@@ -325,7 +396,7 @@ __device__ __forceinline__ void strang_tile(const SolveParams& p, const long lon
       hs[q] = rowc[CY * c.j + HALF + 1];
     }
     const R* last = table + (size_t)(p.n_steps - 1) * Lanes::kRow;
-    L.template step<true>(last, ha, hs);
+    L.template step<true>(last, ha, hs, SH == kShearAlt && ((p.n_steps - 1) & 1));
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
       long long idx = base + (long long)q * blockDim.x;
@@ -359,9 +430,9 @@ __device__ __forceinline__ void strang_tile(const SolveParams& p, const long lon
   }
 }
 
-template <typename R, int PPL, int STAGE, int FORM, int NS, int POL, int ONCE>
+template <typename R, int PPL, int STAGE, int FORM, int NS, int POL, int SH>
 __global__ void __launch_bounds__(256) strang_kernel(const SolveParams p) {
-  strang_tile<R, PPL, STAGE, FORM, NS, POL, ONCE>(p, (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x);
+  strang_tile<R, PPL, STAGE, FORM, NS, POL, SH>(p, (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -391,19 +462,19 @@ __global__ void __launch_bounds__(256) batch_kernel(const BatchSolve* __restrict
     const long long base = w.base + threadIdx.x;
     if (s.precision == PD_FP32) {
       if (s.form == kFormShear)
-        strang_tile<float, PPL, 0, kFormShear, 1, 0, 1>(s.p, base);
+        strang_tile<float, PPL, 0, kFormShear, 1, 0, kShearOnce>(s.p, base);
       else
-        strang_tile<float, PPL, 0, kFormVersine, 1, 0, 1>(s.p, base);
+        strang_tile<float, PPL, 0, kFormVersine, 1, 0, kShearPlain>(s.p, base);
     } else if (s.precision == PD_FP32_FAST) {
       if (s.form == kFormShear)
-        strang_tile<float, PPL, 0, kFormShear, 1, 0, 0>(s.p, base);
+        strang_tile<float, PPL, 0, kFormShear, 1, 0, kShearAlt>(s.p, base);
       else
-        strang_tile<float, PPL, 0, kFormVersine, 1, 0, 0>(s.p, base);
+        strang_tile<float, PPL, 0, kFormVersine, 1, 0, kShearPlain>(s.p, base);
     } else {
       if (s.form == kFormShear)
-        strang_tile<double, PPL, 0, kFormShear, 1, 0, 0>(s.p, base);
+        strang_tile<double, PPL, 0, kFormShear, 1, 0, kShearPlain>(s.p, base);
       else
-        strang_tile<double, PPL, 0, kFormVersine, 1, 0, 0>(s.p, base);
+        strang_tile<double, PPL, 0, kFormVersine, 1, 0, kShearPlain>(s.p, base);
     }
   }
 }
@@ -800,37 +871,37 @@ __global__ void __launch_bounds__(kRedThreads) batch_density_finish(const Densit
   }
 }
 
-template <typename R, int PPL, int FORM, int NS, int POL, int ONCE>
+template <typename R, int PPL, int FORM, int NS, int POL, int SH>
 hipError_t launch_strang(int block, const SolveParams& p, hipStream_t stream) {
   long long per_block = (long long)block * PPL;
   long long blocks = (p.npts + per_block - 1) / per_block;
   if (p.stage == 1) {
-    size_t lds = (size_t)p.chunk_steps * BlochLanes<R, PPL, FORM, NS, POL, ONCE>::kRow * sizeof(R);
-    hipLaunchKernelGGL((strang_kernel<R, PPL, 1, FORM, NS, POL, ONCE>), dim3((unsigned)blocks), dim3(block), lds,
+    size_t lds = (size_t)p.chunk_steps * BlochLanes<R, PPL, FORM, NS, POL, SH>::kRow * sizeof(R);
+    hipLaunchKernelGGL((strang_kernel<R, PPL, 1, FORM, NS, POL, SH>), dim3((unsigned)blocks), dim3(block), lds,
                        stream, p);
   } else {
-    hipLaunchKernelGGL((strang_kernel<R, PPL, 0, FORM, NS, POL, ONCE>), dim3((unsigned)blocks), dim3(block), 0,
+    hipLaunchKernelGGL((strang_kernel<R, PPL, 0, FORM, NS, POL, SH>), dim3((unsigned)blocks), dim3(block), 0,
                        stream, p);
   }
   return hipGetLastError();
 }
 
-template <typename R, int FORM, int NS, int POL, int ONCE>
+template <typename R, int FORM, int NS, int POL, int SH>
 hipError_t strang_ppl(int ppl, int block, const SolveParams& p, hipStream_t stream) {
   switch (ppl) {
-    case 1: return launch_strang<R, 1, FORM, NS, POL, ONCE>(block, p, stream);
-    case 2: return launch_strang<R, 2, FORM, NS, POL, ONCE>(block, p, stream);
-    default: return launch_strang<R, 4, FORM, NS, POL, ONCE>(block, p, stream);
+    case 1: return launch_strang<R, 1, FORM, NS, POL, SH>(block, p, stream);
+    case 2: return launch_strang<R, 2, FORM, NS, POL, SH>(block, p, stream);
+    default: return launch_strang<R, 4, FORM, NS, POL, SH>(block, p, stream);
   }
 }
 
-template <typename R, int FORM, int ONCE>
+template <typename R, int FORM, int SH>
 hipError_t strang_variant(int stages, int elliptic, int ppl, int block, const SolveParams& p, hipStream_t stream) {
   if (stages == 5)
-    return elliptic ? strang_ppl<R, FORM, 5, 1, ONCE>(ppl, block, p, stream)
-                    : strang_ppl<R, FORM, 5, 0, ONCE>(ppl, block, p, stream);
-  return elliptic ? strang_ppl<R, FORM, 1, 1, ONCE>(ppl, block, p, stream)
-                  : strang_ppl<R, FORM, 1, 0, ONCE>(ppl, block, p, stream);
+    return elliptic ? strang_ppl<R, FORM, 5, 1, SH>(ppl, block, p, stream)
+                    : strang_ppl<R, FORM, 5, 0, SH>(ppl, block, p, stream);
+  return elliptic ? strang_ppl<R, FORM, 1, 1, SH>(ppl, block, p, stream)
+                  : strang_ppl<R, FORM, 1, 0, SH>(ppl, block, p, stream);
 }
 
 template <typename R, int J, int PPL, int NS, int POL, int TAN>
@@ -870,13 +941,13 @@ hipError_t launch_propagate(int scheme, int precision, int ppl, int block, int t
   const int S = (scheme == PD_SCHEME_STRANG4 || scheme == PD_SCHEME_MIDPOINT4) ? 5 : 1;
   if (base_scheme(scheme) == PD_SCHEME_STRANG) {
     if (precision == PD_FP32)
-      return p.form == kFormShear ? strang_variant<float, kFormShear, 1>(S, elliptic, ppl, block, p, stream)
-                                  : strang_variant<float, kFormVersine, 0>(S, elliptic, ppl, block, p, stream);
+      return p.form == kFormShear ? strang_variant<float, kFormShear, kShearOnce>(S, elliptic, ppl, block, p, stream)
+                                  : strang_variant<float, kFormVersine, kShearPlain>(S, elliptic, ppl, block, p, stream);
     if (precision == PD_FP32_FAST)
-      return p.form == kFormShear ? strang_variant<float, kFormShear, 0>(S, elliptic, ppl, block, p, stream)
-                                  : strang_variant<float, kFormVersine, 0>(S, elliptic, ppl, block, p, stream);
-    return p.form == kFormShear ? strang_variant<double, kFormShear, 0>(S, elliptic, ppl, block, p, stream)
-                                : strang_variant<double, kFormVersine, 0>(S, elliptic, ppl, block, p, stream);
+      return p.form == kFormShear ? strang_variant<float, kFormShear, kShearAlt>(S, elliptic, ppl, block, p, stream)
+                                  : strang_variant<float, kFormVersine, kShearPlain>(S, elliptic, ppl, block, p, stream);
+    return p.form == kFormShear ? strang_variant<double, kFormShear, kShearPlain>(S, elliptic, ppl, block, p, stream)
+                                : strang_variant<double, kFormVersine, kShearPlain>(S, elliptic, ppl, block, p, stream);
   }
   // series orders: those taylor_order() chooses from
   if (p.form == kMidTangent) {
