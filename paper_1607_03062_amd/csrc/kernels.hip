@@ -246,9 +246,11 @@ __device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM, NS, POL, S
       long long next = (k / kRenormEvery + 1) * kRenormEvery;
       seg = next < k_full ? next : k_full;
     }
-    constexpr int kGroup = Lanes::kRow >= 8 ? 1 : 8 / (Lanes::kRow / 2);  // rows fetched together
-    if constexpr (SH == kShearAlt && kGroup % 2 == 0) {
-      // groups start at even steps, so a step's parity is its place in the group
+    constexpr int kRows = Lanes::kRow >= 8 ? 1 : 8 / (Lanes::kRow / 2);  // rows fetched together
+    // alternating shears: groups of an even number of steps that start at even steps,
+    // so a step's parity is its place in the group (a compile-time constant)
+    constexpr int kGroup = (SH == kShearAlt && kRows % 2 == 1) ? 2 * kRows : kRows;
+    if constexpr (SH == kShearAlt) {
       if ((k & 1) && k < seg) {
         const Row r = tab[k];
         L.step_at(r.v, k);
@@ -259,13 +261,8 @@ __device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM, NS, POL, S
       Row r[kGroup];
 #pragma unroll
       for (int u = 0; u < kGroup; ++u) r[u] = tab[k + u];
-      if constexpr (SH == kShearAlt && kGroup % 2 == 1) {
 #pragma unroll
-        for (int u = 0; u < kGroup; ++u) L.step_at(r[u].v, k + u);
-      } else {
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u) L.template step<false>(r[u].v, nullptr, nullptr, (u & 1) != 0);
-      }
+      for (int u = 0; u < kGroup; ++u) L.template step<false>(r[u].v, nullptr, nullptr, (u & 1) != 0);
     }
     for (; k < seg; ++k) {
       const Row r = tab[k];
