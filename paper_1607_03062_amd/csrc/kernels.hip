@@ -429,7 +429,7 @@ __device__ __forceinline__ void strang_tile(const SolveParams& p, const long lon
 
 template <typename R, int PPL, int STAGE, int FORM, int NS, int POL, int SH>
 __global__ void __launch_bounds__(256) strang_kernel(const SolveParams p) {
-  strang_tile<R, PPL, STAGE, FORM, NS, POL, SH>(p, (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x);
+  strang_tile<R, PPL, STAGE, FORM, NS, POL, SH>(p, p.first + (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -586,7 +586,7 @@ __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
   constexpr int W = NS * (1 + POL);    // table values per step
   constexpr bool kRenorm = sizeof(R) == 4 || TAN;  // renormalise every kRenormEvery steps
   constexpr int kUnroll = NS == 1 ? 4 : 1;
-  const long long base = (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x;
+  const long long base = p.first + (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x;
   R a1[PPL], b1[PPL], a2[PPL], b2[PPL];
   double X0[NC][PPL], Y0[NC][PPL], Y2[NC][PPL];
 #pragma unroll
@@ -717,7 +717,7 @@ __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
 template <typename R, int POL>
 __global__ void __launch_bounds__(256) strang_snapshot_kernel(const SolveParams p, const SnapshotParams s,
                                                               int half_offset, int row_stride) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long idx = p.first + (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= p.npts) return;
   PointCoords c = coords(p, idx);
   double Pxi = c.px + p.A_in, Pyi = c.py + p.Ay_in;
@@ -759,7 +759,7 @@ __global__ void __launch_bounds__(256) strang_snapshot_kernel(const SolveParams 
 
 template <typename R>
 __global__ void __launch_bounds__(256) midpoint_snapshot_kernel(const SolveParams p, const SnapshotParams s) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long idx = p.first + (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= p.npts) return;
   PointCoords c = coords(p, idx);
   double Pxi = p.vsign * (c.px + p.A_in), Pyi = p.vsign * (c.py + p.Ay_in);
@@ -868,19 +868,40 @@ __global__ void __launch_bounds__(kRedThreads) batch_density_finish(const Densit
   }
 }
 
+// A dispatch packet holds a grid's size in work-items in 32 bits, so one launch
+// covers at most kMaxLanes lanes; a larger grid (up to 65536 x 65536 points at one
+// point per lane) runs as consecutive launches over point ranges, each starting at
+// a multiple of the block's span, so every point sees the same tile as in one launch.
+constexpr long long kMaxLanes = 1LL << 31;
+
+// Launch `launch(q, blocks)` over the grid in slices of at most kMaxLanes lanes,
+// q.first being the slice's first point.
+template <typename F>
+hipError_t sliced_launch(const SolveParams& p, int block, int ppl, F launch) {
+  const long long span = (long long)block * ppl;
+  const long long blocks = (p.npts + span - 1) / span;
+  const long long max_blocks = kMaxLanes / block;
+  SolveParams q = p;
+  for (long long b0 = 0; b0 < blocks; b0 += max_blocks) {
+    q.first = b0 * span;
+    launch(q, (unsigned)(blocks - b0 < max_blocks ? blocks - b0 : max_blocks));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template <typename R, int PPL, int FORM, int NS, int POL, int SH>
 hipError_t launch_strang(int block, const SolveParams& p, hipStream_t stream) {
-  long long per_block = (long long)block * PPL;
-  long long blocks = (p.npts + per_block - 1) / per_block;
   if (p.stage == 1) {
-    size_t lds = (size_t)p.chunk_steps * BlochLanes<R, PPL, FORM, NS, POL, SH>::kRow * sizeof(R);
-    hipLaunchKernelGGL((strang_kernel<R, PPL, 1, FORM, NS, POL, SH>), dim3((unsigned)blocks), dim3(block), lds,
-                       stream, p);
-  } else {
-    hipLaunchKernelGGL((strang_kernel<R, PPL, 0, FORM, NS, POL, SH>), dim3((unsigned)blocks), dim3(block), 0,
-                       stream, p);
+    const size_t lds = (size_t)p.chunk_steps * BlochLanes<R, PPL, FORM, NS, POL, SH>::kRow * sizeof(R);
+    return sliced_launch(p, block, PPL, [&](const SolveParams& q, unsigned nb) {
+      hipLaunchKernelGGL((strang_kernel<R, PPL, 1, FORM, NS, POL, SH>), dim3(nb), dim3(block), lds, stream, q);
+    });
   }
-  return hipGetLastError();
+  return sliced_launch(p, block, PPL, [&](const SolveParams& q, unsigned nb) {
+    hipLaunchKernelGGL((strang_kernel<R, PPL, 0, FORM, NS, POL, SH>), dim3(nb), dim3(block), 0, stream, q);
+  });
 }
 
 template <typename R, int FORM, int NS, int POL, int SH>
@@ -903,10 +924,9 @@ hipError_t strang_variant(int stages, int elliptic, int ppl, int block, const So
 
 template <typename R, int J, int PPL, int NS, int POL, int TAN>
 hipError_t launch_midpoint(int block, const SolveParams& p, hipStream_t stream) {
-  long long per_block = (long long)block * PPL;
-  long long blocks = (p.npts + per_block - 1) / per_block;
-  hipLaunchKernelGGL((midpoint_kernel<R, J, PPL, NS, POL, TAN>), dim3((unsigned)blocks), dim3(block), 0, stream, p);
-  return hipGetLastError();
+  return sliced_launch(p, block, PPL, [&](const SolveParams& q, unsigned nb) {
+    hipLaunchKernelGGL((midpoint_kernel<R, J, PPL, NS, POL, TAN>), dim3(nb), dim3(block), 0, stream, q);
+  });
 }
 
 template <typename R, int J, int NS, int POL, int TAN>
@@ -977,31 +997,31 @@ hipError_t launch_propagate(int scheme, int precision, int ppl, int block, int t
 
 hipError_t launch_snapshot(int scheme, int precision, int elliptic, const SolveParams& p, const SnapshotParams& q,
                            hipStream_t stream) {
-  const long long blocks = (p.npts + 255) / 256;
-  if (base_scheme(scheme) == PD_SCHEME_STRANG) {
-    const bool four = scheme == PD_SCHEME_STRANG4;
-    const int row_stride = four ? 6 : 4, half_offset = four ? 4 : 2;
-    if (is_fp32(precision)) {
-      if (elliptic)
-        hipLaunchKernelGGL((strang_snapshot_kernel<float, 1>), dim3((unsigned)blocks), dim3(256), 0, stream, p, q,
-                           half_offset, row_stride);
-      else
-        hipLaunchKernelGGL((strang_snapshot_kernel<float, 0>), dim3((unsigned)blocks), dim3(256), 0, stream, p, q,
-                           half_offset, row_stride);
+  return sliced_launch(p, 256, 1, [&](const SolveParams& ps, unsigned nb) {
+    if (base_scheme(scheme) == PD_SCHEME_STRANG) {
+      const bool four = scheme == PD_SCHEME_STRANG4;
+      const int row_stride = four ? 6 : 4, half_offset = four ? 4 : 2;
+      if (is_fp32(precision)) {
+        if (elliptic)
+          hipLaunchKernelGGL((strang_snapshot_kernel<float, 1>), dim3(nb), dim3(256), 0, stream, ps, q, half_offset,
+                             row_stride);
+        else
+          hipLaunchKernelGGL((strang_snapshot_kernel<float, 0>), dim3(nb), dim3(256), 0, stream, ps, q, half_offset,
+                             row_stride);
+      } else {
+        if (elliptic)
+          hipLaunchKernelGGL((strang_snapshot_kernel<double, 1>), dim3(nb), dim3(256), 0, stream, ps, q, half_offset,
+                             row_stride);
+        else
+          hipLaunchKernelGGL((strang_snapshot_kernel<double, 0>), dim3(nb), dim3(256), 0, stream, ps, q, half_offset,
+                             row_stride);
+      }
+    } else if (is_fp32(precision)) {
+      hipLaunchKernelGGL((midpoint_snapshot_kernel<float>), dim3(nb), dim3(256), 0, stream, ps, q);
     } else {
-      if (elliptic)
-        hipLaunchKernelGGL((strang_snapshot_kernel<double, 1>), dim3((unsigned)blocks), dim3(256), 0, stream, p, q,
-                           half_offset, row_stride);
-      else
-        hipLaunchKernelGGL((strang_snapshot_kernel<double, 0>), dim3((unsigned)blocks), dim3(256), 0, stream, p, q,
-                           half_offset, row_stride);
+      hipLaunchKernelGGL((midpoint_snapshot_kernel<double>), dim3(nb), dim3(256), 0, stream, ps, q);
     }
-  } else if (is_fp32(precision)) {
-    hipLaunchKernelGGL((midpoint_snapshot_kernel<float>), dim3((unsigned)blocks), dim3(256), 0, stream, p, q);
-  } else {
-    hipLaunchKernelGGL((midpoint_snapshot_kernel<double>), dim3((unsigned)blocks), dim3(256), 0, stream, p, q);
-  }
-  return hipGetLastError();
+  });
 }
 
 hipError_t launch_density(const double* n, long long npts, double scale, double* partial, double* rho,
