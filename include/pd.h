@@ -158,7 +158,7 @@ typedef struct {
                                below 2^32), 1 = cosine form (cos - 1 and sin(x)/x) */
   int taylor_order;         /* midpoint: terms J of the series (tan(x)/x, or cos - 1 and
                                sin(x)/x) in x = (c dt E)^2 */
-  size_t device_bytes;      /* device memory the handle owns */
+  size_t device_bytes;      /* device memory the handle owns (its table allocation may exceed the current table) */
   size_t solve_bytes;       /* device memory a solve of this field needs, chunk state included:
                                tables + n(p) + density partials + state (for admission control) */
   int valley;               /* pd_valley */
@@ -203,7 +203,14 @@ pd_status pd_set_valley(pd_grid g, int valley);
    device buffers on first use and resets the solve to t_i (steps_done = 0).
    Same validation as pd_check_field.  For long solves (16384 steps or more) the
    sampling of an analytic field runs on up to 16 short-lived host threads,
-   joined before the call returns. */
+   joined before the call returns.
+   On a handle already used, the call first waits for the work the library last
+   enqueued on its buffers (propagation, density, snapshot, batch epoch), not
+   for other work on the device; if that work was enqueued under stream
+   capture, it waits for the whole device.  The device table is reallocated
+   only when the new one is larger (freeing the old one waits for the whole
+   device), so a handle reused for solves of up to the longest it has seen
+   frees and allocates nothing. */
 pd_status pd_set_field(pd_grid g, const pd_field* f, long long n_steps);
 
 /* Restart the solve at t_i (steps_done = 0) with the field already set; the

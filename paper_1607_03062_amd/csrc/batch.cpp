@@ -269,6 +269,8 @@ pd_status step_members(pd_batch b, const long long* max_steps, double* rho_out, 
   if ((s = make_plan(b, begin, end, &plan)) != PD_OK) return s;
   if ((s = upload(b, plan, st)) != PD_OK) return s;
   if ((s = enqueue(b, plan, st)) != PD_OK) return s;
+  for (pd_grid g : b->grids)
+    if ((s = mark_use(g, st)) != PD_OK) return s;
   b->n_items_last = (int)plan.items.size();
   b->n_separate_last = (int)plan.separate.size();
   std::vector<char> completed(n, 0);
@@ -388,7 +390,10 @@ pd_status pd_batch_run(pd_batch b, double* rho_out, void* stream) {
   }
   hipError_t e = hipGraphLaunch(b->exec, st);
   if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
-  for (pd_grid g : b->grids) g->steps_done = g->field.n_steps;
+  for (pd_grid g : b->grids) {
+    g->steps_done = g->field.n_steps;
+    if ((s = mark_use(g, st)) != PD_OK) return s;
+  }
   return copy_rho(b, rho_out, nullptr, st);
 }
 

@@ -41,6 +41,20 @@ pd_status hip_error(hipError_t e, const char* what) {
   return set_error(PD_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+pd_status mark_use(pd_grid g, hipStream_t stream) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(stream, &cs);
+  if (e != hipSuccess) return hip_error(e, "hipStreamIsCapturing");
+  if (cs != hipStreamCaptureStatusNone) {
+    g->wait_device = true;
+    return PD_OK;
+  }
+  if (!g->last_use && (e = hipEventCreateWithFlags(&g->last_use, hipEventDisableTiming)) != hipSuccess)
+    return hip_error(e, "hipEventCreate");
+  if ((e = hipEventRecord(g->last_use, stream)) != hipSuccess) return hip_error(e, "hipEventRecord");
+  return PD_OK;
+}
+
 pd_status grid_state_buffer(pd_grid g, void** out) {
   if (g->d_state_bound) {
     *out = g->d_state_bound;
@@ -303,19 +317,25 @@ pd_status pd_set_field(pd_grid g, const pd_field* f, long long n_steps) {
   DeviceScope scope(g->device);
   if (!scope.ok) return fail(PD_ERR_DEVICE, "cannot select device %d", g->device);
   hipError_t e;
-  if (g->d_table) {
-    // Work of an earlier solve may still read the table or the state.
+  // Work of an earlier solve on this handle may still read the table or the state:
+  // wait for it (for the whole device only if it was enqueued under stream capture).
+  if (g->wait_device) {
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    g->wait_device = false;
+  } else if (g->last_use) {
+    e = hipEventSynchronize(g->last_use);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
   }
   g->field_set = false;
-  if (rows.size() != g->table_bytes) {
+  if (rows.size() > g->table_capacity) {
     release(g->d_table);
-    g->table_bytes = 0;
+    g->table_bytes = g->table_capacity = 0;
     e = hipMalloc(&g->d_table, rows.size());
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(field table)");
-    g->table_bytes = rows.size();
+    g->table_capacity = rows.size();
   }
+  g->table_bytes = rows.size();
   e = hipMemcpy(g->d_table, rows.data(), rows.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(field table)");
   long long npts = g->grid.points();
@@ -433,7 +453,7 @@ pd_status pd_propagate(pd_grid g, long long max_steps, void* stream) {
                                   g->field.elliptic ? 1 : 0, p, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "propagate launch");
   g->steps_done = p.k_end;
-  return ok();
+  return mark_use(g, static_cast<hipStream_t>(stream));
 }
 
 namespace {
@@ -450,6 +470,8 @@ pd_status reduce_and_copy(pd_grid g, double* n_out, int n_out_on_device, double*
     if (e != hipSuccess) return hip_fail(e, "copy of n(p)");
     wait = !n_out_on_device;
   }
+  pd_status m = mark_use(g, s);
+  if (m != PD_OK) return m;
   double rho = 0.0;
   if (rho_out) {
     e = hipMemcpyAsync(&rho, g->d_rho, sizeof(double), hipMemcpyDeviceToHost, s);
@@ -527,6 +549,7 @@ void pd_destroy_grid(pd_grid g) {
     release(g->d_partial);
     release(g->d_rho);
     release(g->d_state_own);
+    if (g->last_use) (void)hipEventDestroy(g->last_use);
   }
   delete g;
 }

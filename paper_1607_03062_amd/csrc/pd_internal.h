@@ -255,7 +255,8 @@ struct pd_grid_s {
 
   int device = -1;
   void* d_table = nullptr;
-  size_t table_bytes = 0;  // step rows, then (Strang) the column and row coefficients
+  size_t table_bytes = 0;     // step rows, then (Strang) the column and row coefficients
+  size_t table_capacity = 0;  // bytes allocated at d_table: kept when a later table is smaller
   size_t col_offset = 0, row_offset = 0;
   double* d_n = nullptr;
   double* d_partial = nullptr;
@@ -263,9 +264,15 @@ struct pd_grid_s {
   void* d_state_own = nullptr;
   void* d_state_bound = nullptr;
   size_t state_bound_bytes = 0;
+  // Completion of the last work the library enqueued on this handle's buffers
+  // (propagation, projection, copies, batch epochs); a new field waits for it
+  // rather than for the whole device.  Work enqueued under stream capture has no
+  // such event: then the whole device is waited for.
+  hipEvent_t last_use = nullptr;
+  bool wait_device = false;
 
   size_t device_bytes() const {
-    size_t b = table_bytes;
+    size_t b = table_capacity;
     if (d_n) b += (size_t)grid.points() * sizeof(double);
     if (d_partial) b += (size_t)pdx::density_partials(grid.points()) * sizeof(double) + sizeof(double);
     if (d_state_own) b += state_bytes();
@@ -300,4 +307,7 @@ pd_status set_error(pd_status s, const char* fmt, ...);
 pd_status hip_error(hipError_t e, const char* what);
 // The chunk state buffer of a handle, allocated on first use.
 pd_status grid_state_buffer(pd_grid g, void** out);
+// Note work just enqueued on `stream` that uses g's device buffers (the handle's
+// device must be current).
+pd_status mark_use(pd_grid g, hipStream_t stream);
 }  // namespace pdx

@@ -6,7 +6,8 @@ them in epochs: each epoch advances active solves in one batched launch sequence
 (pd_batch_step_each: one persistent kernel for the second-order Strang solves of
 fields along x, the others' own launches after it), with every solve's state
 resident in device memory between epochs.  Solves that reach their last step are
-projected and reduced in the same epoch and leave the set; arrivals are admitted
+projected and reduced in the same epoch and leave the set (their handles are kept
+for later requests of the same shape, within the memory budget); arrivals are admitted
 between epochs, in arrival order, while their device footprint (tables, state,
 n(p), partials; pd_info.solve_bytes) fits in the memory budget, at most
 `admit_per_epoch` at a time so that a burst of arrivals is set up on the host while
@@ -77,12 +78,76 @@ class Request:
                    valley=w.get("valley", "both"))
 
 
+class IdlePool:
+    """Finished solves' handles kept for reuse by shape, oldest first, with their device
+    bytes.  `close` is called on a handle that is evicted."""
+
+    def __init__(self, per_shape: int, close):
+        self.per_shape = int(per_shape)
+        self.close = close
+        self.entries = collections.OrderedDict()  # serial -> (shape key, handle, bytes)
+        self.bytes = 0
+        self._serial = 0
+
+    def take(self, key):
+        for i, (k, h, b) in self.entries.items():
+            if k == key:
+                del self.entries[i]
+                self.bytes -= b
+                return h
+        return None
+
+    def put(self, key, handle, nbytes: int) -> bool:
+        """Keep the handle unless its shape already has per_shape kept; False: not kept."""
+        if sum(k == key for k, _, _ in self.entries.values()) >= self.per_shape:
+            return False
+        self._serial += 1
+        self.entries[self._serial] = (key, handle, int(nbytes))
+        self.bytes += int(nbytes)
+        return True
+
+    def reserve(self, key, spare: int):
+        """Evict until the kept handles hold at most `spare` bytes beyond the one a request
+        of shape `key` will reuse (the oldest of that shape, which take() returns).  Other
+        shapes go first, oldest first; then that shape's newer handles, newest first."""
+        credit = next((b for k, _, b in self.entries.values() if k == key), 0)
+        limit = spare + credit
+        others = [i for i, (k, _, _) in self.entries.items() if k != key]
+        same = [i for i, (k, _, _) in self.entries.items() if k == key][1:]
+        for i in others + same[::-1]:
+            if self.bytes <= limit:
+                return
+            _, h, b = self.entries.pop(i)
+            self.bytes -= b
+            self.close(h)
+
+    def clear(self):
+        for _, h, _ in self.entries.values():
+            self.close(h)
+        self.entries.clear()
+        self.bytes = 0
+
+
+def shape_key(req: "Request"):
+    """Requests of one key can reuse each other's handles (grid, precision, scheme, valley)."""
+    g = req.grid
+    return (int(g["nx"]), int(g["ny"]), tuple(map(float, g["px"])), tuple(map(float, g["py"])), req.precision,
+            req.scheme, req.valley)
+
+
 class GpuExecutor:
     """Active solves as pd_grid handles in one pd_batch."""
 
-    def __init__(self, pd, stream=None, points_per_lane: int = 0, block_threads: int = 0, keep_n: bool = False):
+    def __init__(self, pd, stream=None, points_per_lane: int = 0, block_threads: int = 0, keep_n: bool = False,
+                 idle_per_shape: int = 8):
         """Every scheme, precision, field and valley is served; second-order Strang requests
-        with fields along x share the batch's persistent kernel (see pd_batch)."""
+        with fields along x share the batch's persistent kernel (see pd_batch).
+
+        A finished solve's handle is kept (at most `idle_per_shape` per grid, precision,
+        scheme and valley) and set up again for a later request of the same shape: that
+        request then allocates nothing, and the finished one frees nothing (freeing device
+        memory waits for the whole device).  Kept handles count against the server's
+        memory budget and are closed when admitted work needs the room."""
         self.pd = pd
         self.stream = stream
         self.batch = pd.Batch()
@@ -91,8 +156,19 @@ class GpuExecutor:
         self.solvers = {}   # request name -> Solver
         self.order = []     # request names in batch member order
         self.left = {}      # request name -> steps still to run
+        self.keys = {}      # request name -> shape key
+        self.idle = IdlePool(idle_per_shape, lambda h: h.close())
+        self.reused = 0
         self.keep_n = keep_n
         self.n_results = {}
+
+    @property
+    def idle_bytes(self) -> int:
+        return self.idle.bytes
+
+    def reserve(self, req: Request, spare: int):
+        """Close kept handles so that, with req admitted, they hold at most `spare` bytes."""
+        self.idle.reserve(shape_key(req), spare)
 
     def footprint(self, req: Request) -> int:
         s = self.pd.Solver.for_grid(req.grid, req.precision, req.scheme, req.valley)
@@ -103,13 +179,19 @@ class GpuExecutor:
 
     def admit(self, req: Request):
         """Raises PDError if the library refuses the request (e.g. the step-size condition)."""
-        s = self.pd.Solver.for_grid(req.grid, req.precision, req.scheme, req.valley)
+        key = shape_key(req)
+        s = self.idle.take(key)
+        if s is None:
+            s = self.pd.Solver.for_grid(req.grid, req.precision, req.scheme, req.valley)
+        else:
+            self.reused += 1
         try:
             s.set_field(req.field, req.n_steps)
         except Exception:
             s.close()
             raise
         self.solvers[req.name] = s
+        self.keys[req.name] = key
         self.order.append(req.name)
         self.left[req.name] = req.n_steps
         self.batch.add(s)
@@ -141,13 +223,16 @@ class GpuExecutor:
             self.n_results[name] = n
         self.order.remove(name)
         del self.left[name]
-        self.batch.remove(s)  # leave the batch before the grid is destroyed
-        s.close()
+        key = self.keys.pop(name)
+        self.batch.remove(s)  # leave the batch before the grid is kept or destroyed
+        if not self.idle.put(key, s, int(s.info()["device_bytes"])):
+            s.close()
 
     def close(self):
         self.batch.close()
         for s in self.solvers.values():
             s.close()
+        self.idle.clear()
         self.solvers = {}
         self.order = []
 
@@ -159,18 +244,29 @@ class FakeExecutor:
     epoch_overhead_s; rho is a fixed function of the request."""
 
     def __init__(self, rate_point_steps_per_s: float = 1e12, bytes_per_point: int = 40, tile_step_s: float = 0.0,
-                 epoch_overhead_s: float = 0.0):
+                 epoch_overhead_s: float = 0.0, idle_per_shape: int = 0):
         self.rate = rate_point_steps_per_s
         self.bytes_per_point = bytes_per_point
         self.tile_step_s = tile_step_s
         self.epoch_overhead_s = epoch_overhead_s
         self.active = collections.OrderedDict()  # name -> [request, steps_done]
         self.clock = 0.0                          # simulated device time
+        self.idle = IdlePool(idle_per_shape, lambda h: None)  # kept "handles": the finished requests
+        self.reused = 0
+
+    @property
+    def idle_bytes(self) -> int:
+        return self.idle.bytes
+
+    def reserve(self, req: Request, spare: int):
+        self.idle.reserve(shape_key(req), spare)
 
     def footprint(self, req: Request) -> int:
         return req.points * self.bytes_per_point + 16 * req.n_steps
 
     def admit(self, req: Request):
+        if self.idle.take(shape_key(req)) is not None:
+            self.reused += 1
         self.active[req.name] = [req, 0]
 
     def epoch(self, steps: int):
@@ -192,10 +288,11 @@ class FakeExecutor:
         return done
 
     def release(self, name: str):
-        del self.active[name]
+        req = self.active.pop(name)[0]
+        self.idle.put(shape_key(req), req, self.footprint(req))
 
     def close(self):
-        pass
+        self.idle.clear()
 
 
 @dataclasses.dataclass
@@ -318,6 +415,7 @@ class Server:
                 r = waiting[0]
                 if self.in_use + r.bytes <= self.budget:
                     waiting.popleft()
+                    self.ex.reserve(r, self.budget - self.in_use - r.bytes)  # kept handles give way
                     try:
                         self.ex.admit(r)
                     except Exception as e:  # refused by the solver: reported, not retried
@@ -328,7 +426,7 @@ class Server:
                     self.active[r.name] = r
                     self.left[r.name] = r.n_steps
                     self.in_use += r.bytes
-                    self.peak = max(self.peak, self.in_use)
+                    self.peak = max(self.peak, self.in_use + self.ex.idle_bytes)
                 elif self.backfill:
                     blocked.append(waiting.popleft())
                 else:

@@ -219,3 +219,48 @@ def test_admissions_per_epoch_are_capped():
     assert all(a <= b for a, b in zip(adm, adm[1:]))
     with pytest.raises(ValueError):
         serve.Server(ex, 10 ** 9, admit_per_epoch=0)
+
+
+def test_idle_pool_keeps_reuses_and_evicts():
+    """Kept handles: at most per_shape per shape; reserve() evicts other shapes oldest first,
+    then the requested shape's newer handles, and keeps the oldest one, which take() returns."""
+    closed = []
+    pool = serve.IdlePool(2, closed.append)
+    assert pool.put("A", "a1", 10) and pool.put("A", "a2", 20)
+    assert not pool.put("A", "a3", 5)  # a third of shape A is not kept
+    assert pool.put("B", "b1", 100)
+    assert pool.bytes == 130
+    pool.reserve("A", 15)  # room for 15 bytes beyond a1, which the request will reuse
+    assert closed == ["b1", "a2"] and pool.bytes == 10
+    assert pool.take("A") == "a1" and pool.bytes == 0
+    assert pool.take("A") is None
+    pool.reserve("C", 0)  # nothing kept: nothing to do
+    assert pool.put("C", "c1", 7)
+    pool.reserve("D", 100)  # enough room: c1 stays
+    assert pool.bytes == 7
+    pool.clear()
+    assert closed == ["b1", "a2", "c1"] and pool.bytes == 0
+
+
+@pytest.mark.parametrize("slack", [4.0, 1.0])
+def test_kept_handles_are_reused_within_the_budget(slack):
+    """With handles kept for reuse, requests of a shape seen before reuse one, and the
+    admitted footprints plus the kept handles never exceed the budget, also when the budget
+    holds one request only (every admission then evicts what is kept)."""
+    ex = serve.FakeExecutor(rate_point_steps_per_s=2e10, idle_per_shape=2)
+    reqs = stream(count=60)
+    budget = int(slack * max(ex.footprint(r) for r in reqs)) + 1
+    srv = serve.Server(ex, budget, epoch_steps=512)
+    over = []
+    admit = ex.admit
+
+    def checked(r):
+        admit(r)  # the server adds r.bytes to in_use after this returns
+        over.append(srv.in_use + r.bytes + ex.idle_bytes - budget)
+    ex.admit = checked
+    st = srv.run(reqs, simulated=True)
+    assert st.completed == len(reqs) and st.rejected == 0
+    assert ex.reused > 0
+    assert max(over) <= 0 and st.peak_bytes <= budget
+    shapes = {serve.shape_key(r) for r in reqs}
+    assert len(ex.idle.entries) <= 2 * len(shapes)
