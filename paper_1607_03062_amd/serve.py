@@ -28,9 +28,9 @@ How an epoch shares the device is the policy:
             advancing even when a flow of small ones could fill every epoch.
 
 The device work is in libpd; this module is the host-side scheduler.  The
-executor interface (footprint / admit / epoch / release) has a GPU
-implementation over the C ABI and a CPU fake with a cost model, used to test the
-scheduling without a GPU.
+executor interface (footprint / reserve / admit / epoch_each / release, and
+idle_bytes: the memory of kept handles) has a GPU implementation over the C ABI
+and a CPU fake with a cost model, used to test the scheduling without a GPU.
 """
 from __future__ import annotations
 
