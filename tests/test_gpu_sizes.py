@@ -6,7 +6,8 @@ A dispatch packet holds a grid's size in work-items in 32 bits, so a full
 sides of that split, the first and the last point and whole rows against the
 oracle, the masked point p = 0 and the p_y = 0 row (exactly 0 under a field along
 x), and rho against its definition, 4 dx dy / (2 pi)^2 times the sum of n, with
-the sum taken by torch over the device output.  The thin grids at the maximum
+the sum taken by torch over the device output.  A batch with such a member runs
+it as 4M work items of the persistent kernel.  The thin grids at the maximum
 extent (65536 x 1, 1 x 65536) are compared point by point.
 """
 import math
@@ -123,3 +124,47 @@ def test_thin_grids_at_maximum_extent(gpu, shape, precision):
         assert abs(rho / oracle.density(g, n_o) - 1) <= FP64_RHO_REL
     else:
         assert np.max(np.abs(n - n_o)) <= FP32_N_ABS
+
+
+def test_batch_with_a_maximum_grid_member(gpu):
+    """A batch holding a 65536^2 member (2^32 points: 4M work items of the persistent
+    kernel) beside a 64^2 one: sampled points, the split rows and rho of the large member
+    against the oracle and the definition; the small member equals its solve alone."""
+    import torch
+
+    g = {"nx": NMAX, "ny": NMAX, "px": (-2.0, 2.0), "py": (-2.0, 2.0)}
+    print("gpu batch: 65536x65536 N=%d + 64x64, fp32" % N_STEPS, flush=True)
+    big = gpu.Solver.for_grid(g, "fp32")
+    small = gpu.Solver.for_grid(wl.grid(64, 2.0), "fp32")
+    b = gpu.Batch()
+    out = torch.empty(NMAX * NMAX, dtype=torch.float64, device="cuda")
+    try:
+        big.set_field(FIELD, N_STEPS)
+        small.set_field(wl.sin2(0.15, 0.5, 8), 700)
+        b.add(big)
+        b.add(small)
+        rho = b.run()
+        rho_big = big.density(n_out=out)
+        n_small = np.empty(64 * 64)
+        rho_small = small.density(n_out=n_small)
+    finally:
+        b.close()
+        big.close()
+        small.close()
+    torch.cuda.synchronize()
+    assert rho[0] == rho_big and rho[1] == rho_small
+    idx = _sample()
+    n_o = oracle.solve_grid(FIELD, g, N_STEPS, "strang", idx=idx)[0]
+    assert np.max(np.abs(out[torch.from_numpy(idx).cuda()].cpu().numpy() - n_o)) <= FP32_N_ABS
+    assert torch.all(out[SPLIT:SPLIT + NMAX] == 0.0).item()
+    rho_def = 4.0 * (4.0 / NMAX) ** 2 / (4.0 * math.pi ** 2) * float(out.sum().item())
+    assert abs(rho_big / rho_def - 1) <= FP64_RHO_REL
+    alone = gpu.Solver.for_grid(wl.grid(64, 2.0), "fp32")
+    alone.set_field(wl.sin2(0.15, 0.5, 8), 700)
+    alone.propagate(-1)
+    n_alone = np.empty(64 * 64)
+    rho_alone = alone.density(n_out=n_alone)
+    alone.close()
+    assert rho_small == rho_alone and np.array_equal(n_small, n_alone)
+    del out
+    torch.cuda.empty_cache()
