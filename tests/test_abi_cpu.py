@@ -212,11 +212,23 @@ def test_masked_count_with_final_momentum_zero():
     ({"kind": "constant", "E0": 0.1, "t_end": -1.0}, "t_end"),
     ({"kind": "pulse", "E0": 1.0, "omega": 0.5, "phi": 0, "omega_rise": 0.06, "omega_fall": 0.06,
       "duration": 10.0}, "shorter"),
+    ({"kind": "sin2", "E0": 0.1, "omega": 0.0, "cycles": 8}, "omega > 0"),
+    ({"kind": "sin2", "E0": 0.1, "omega": 0.5, "cycles": 8, "ellipticity": float("nan")}, "ellipticity"),
 ])
 def test_bad_fields(field, msg):
     s = pd.Solver(8, 8, (-1, 1), (-1, 1))
     with pytest.raises(pd.PDError) as e:
         s.check_field(field, 1000)
+    assert e.value.status == _lib.PD_ERR_INVALID and msg in e.value.message
+    s.close()
+
+
+@pytest.mark.parametrize("n_steps,msg", [(0, ">= 1"), (-5, ">= 1"), ((1 << 31) + 1, "2^31")])
+def test_step_count_bounds(n_steps, msg):
+    """N is at least 1 and at most 2^31 (checked before any table is allocated)."""
+    s = pd.Solver(8, 8, (-1, 1), (-1, 1))
+    with pytest.raises(pd.PDError) as e:
+        s.check_field(wl.config1()["field"], n_steps)
     assert e.value.status == _lib.PD_ERR_INVALID and msg in e.value.message
     s.close()
 
