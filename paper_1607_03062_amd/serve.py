@@ -17,7 +17,7 @@ to its density being on the host.
 
 How an epoch shares the device is the policy:
   lockstep  every active solve advances `epoch_steps` steps;
-  srpt      shortest remaining work first: the solves with the least remaining
+  srpt      (the default) shortest remaining work first: the solves with the least remaining
             work (points x steps left / the device rate of their precision)
             take an epoch's time budget (`epoch_ms`) in that order, each up to
             the steps one tile of it runs in that time; the largest may get
@@ -321,7 +321,7 @@ DEFAULT_TILE_STEP_S = 0.43e-6
 
 class Server:
     def __init__(self, executor, budget_bytes: int, epoch_steps: int = 2048, max_active: int = 4096,
-                 backfill: bool = False, policy: str = "lockstep", epoch_ms: float = 3.0, rates: dict = None,
+                 backfill: bool = False, policy: str = "srpt", epoch_ms: float = 3.0, rates: dict = None,
                  tile_step_s: float = DEFAULT_TILE_STEP_S, max_wait_epochs: int = 32, admit_per_epoch: int = 4):
         if epoch_steps < 1:
             raise ValueError("epoch_steps must be >= 1")

@@ -72,7 +72,7 @@ def test_reused_handles_equal_fresh_ones(gpu, precision):
     fp = sorted(ex.footprint(r) for r in reqs)
     assert fp[0] + fp[1] > fp[-1]  # a budget of the largest footprint admits one request at a time
     budget = fp[-1]
-    st = serve.Server(ex, budget, epoch_steps=700).run(reqs)
+    st = serve.Server(ex, budget, epoch_steps=700, policy="lockstep").run(reqs)
     assert st.completed == len(reqs) and st.peak_bytes <= budget
     assert ex.reused == len(reqs) - 1
     for r in reqs:

@@ -16,7 +16,7 @@ def test_every_request_completes_within_budget():
     ex = serve.FakeExecutor(rate_point_steps_per_s=2e10)
     reqs = stream()
     budget = 4 * max(ex.footprint(r) for r in reqs)
-    st = serve.Server(ex, budget, epoch_steps=512).run(reqs, simulated=True)
+    st = serve.Server(ex, budget, epoch_steps=512, policy="lockstep").run(reqs, simulated=True)
     assert st.completed == len(reqs) and st.rejected == 0
     assert st.peak_bytes <= budget
     for r in reqs:
@@ -30,7 +30,7 @@ def test_fifo_admission_and_queueing():
     ex = serve.FakeExecutor(rate_point_steps_per_s=1e10)
     reqs = stream(count=30, rate=1000.0)
     budget = max(ex.footprint(r) for r in reqs) + 1  # forces queueing
-    st = serve.Server(ex, budget, epoch_steps=1024).run(reqs, simulated=True)
+    st = serve.Server(ex, budget, epoch_steps=1024, policy="lockstep").run(reqs, simulated=True)
     assert st.completed == len(reqs)
     adm = [r.admitted_s for r in sorted(reqs, key=lambda r: r.arrival_s)]
     assert all(a <= b for a, b in zip(adm, adm[1:]))  # in arrival order
@@ -43,7 +43,7 @@ def test_oversized_request_is_rejected():
     reqs = stream(count=10)
     big = serve.Request("huge", 0.0, wl.grid(4096, 4.0), wl.sin2(0.1, 0.5, 8), 1000)
     budget = max(ex.footprint(r) for r in reqs) * 2
-    st = serve.Server(ex, budget).run(reqs + [big], simulated=True)
+    st = serve.Server(ex, budget, policy="lockstep").run(reqs + [big], simulated=True)
     assert big.status == "rejected" and "budget" in big.reason
     assert st.rejected == 1 and st.completed == len(reqs)
 
@@ -51,7 +51,7 @@ def test_oversized_request_is_rejected():
 def test_percentiles_and_throughput():
     ex = serve.FakeExecutor(rate_point_steps_per_s=5e10)
     reqs = stream(count=25)
-    st = serve.Server(ex, 10 ** 12, epoch_steps=256).run(reqs, simulated=True)
+    st = serve.Server(ex, 10 ** 12, epoch_steps=256, policy="lockstep").run(reqs, simulated=True)
     lat = np.array([r.latency_s for r in reqs]) * 1e3
     assert st.p50_ms == pytest.approx(np.percentile(lat, 50))
     assert st.p99_ms == pytest.approx(np.percentile(lat, 99))
@@ -63,7 +63,7 @@ def test_percentiles_and_throughput():
 def test_epoch_count_of_a_lone_request():
     ex = serve.FakeExecutor()
     r = serve.Request("one", 0.0, wl.grid(64, 2.0), wl.sin2(0.1, 0.5, 8), 5000)
-    st = serve.Server(ex, 10 ** 12, epoch_steps=2048).run([r], simulated=True)
+    st = serve.Server(ex, 10 ** 12, epoch_steps=2048, policy="lockstep").run([r], simulated=True)
     assert st.epochs == 3 and r.status == "done"
 
 
@@ -74,7 +74,7 @@ def test_backfill_admits_smaller_requests_past_a_blocked_head():
     first = serve.Request("first", 0.0, wl.grid(256, 2.0), wl.sin2(0.1, 0.5, 8), 20000)
     head = serve.Request("head", 0.0005, wl.grid(256, 2.0), wl.sin2(0.1, 0.5, 8), 2000)
     budget = ex.footprint(first) + ex.footprint(small[0]) * 4 + 1
-    serve.Server(ex, budget, epoch_steps=512, backfill=True).run([first, head] + small, simulated=True)
+    serve.Server(ex, budget, epoch_steps=512, backfill=True, policy="lockstep").run([first, head] + small, simulated=True)
     assert all(s.admitted_s < head.admitted_s for s in small)
 
 
@@ -88,7 +88,7 @@ def test_request_refused_at_admission_is_rejected_and_frees_nothing():
     ex = Picky()
     reqs = stream(count=6)
     bad = serve.Request("bad", 0.0, wl.grid(64, 2.0), wl.sin2(0.1, 0.5, 8), 10)
-    srv = serve.Server(ex, 10 ** 12)
+    srv = serve.Server(ex, 10 ** 12, policy="lockstep")
     st = srv.run(reqs + [bad], simulated=True)
     assert bad.status == "rejected" and "pi" in bad.reason
     assert st.completed == len(reqs) and srv.in_use == 0
@@ -204,7 +204,7 @@ def test_admissions_per_epoch_are_capped():
     and 9 admitted solves, in arrival order; all complete."""
     ex = serve.FakeExecutor(rate_point_steps_per_s=1e10)
     reqs = [serve.Request("r%d" % i, 0.0, wl.grid(64, 2.0), wl.sin2(0.1, 0.5, 8), 20000) for i in range(10)]
-    srv = serve.Server(ex, 10 ** 12, epoch_steps=512, admit_per_epoch=3)
+    srv = serve.Server(ex, 10 ** 12, epoch_steps=512, admit_per_epoch=3, policy="lockstep")
     sizes = []
     epoch_each = ex.epoch_each
 
@@ -218,7 +218,7 @@ def test_admissions_per_epoch_are_capped():
     adm = [r.admitted_s for r in reqs]
     assert all(a <= b for a, b in zip(adm, adm[1:]))
     with pytest.raises(ValueError):
-        serve.Server(ex, 10 ** 9, admit_per_epoch=0)
+        serve.Server(ex, 10 ** 9, admit_per_epoch=0, policy="lockstep")
 
 
 def test_idle_pool_keeps_reuses_and_evicts():
@@ -250,7 +250,7 @@ def test_kept_handles_are_reused_within_the_budget(slack):
     ex = serve.FakeExecutor(rate_point_steps_per_s=2e10, idle_per_shape=2)
     reqs = stream(count=60)
     budget = int(slack * max(ex.footprint(r) for r in reqs)) + 1
-    srv = serve.Server(ex, budget, epoch_steps=512)
+    srv = serve.Server(ex, budget, epoch_steps=512, policy="lockstep")
     over = []
     admit = ex.admit
 
