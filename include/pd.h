@@ -222,8 +222,10 @@ pd_status pd_rewind(pd_grid g);
    keeps every spinor in registers; otherwise the state is kept in device
    memory between calls (the handle's own buffer, or the one given to
    pd_bind_state).  The call that reaches step N also projects on u_out and
-   stores n(p) in the handle's device buffer.  PD_ERR_STATE before
-   pd_set_field or after the last step. */
+   stores n(p) in the handle's device buffer.  The work is one kernel launch,
+   or several over consecutive point ranges when the grid needs more than 2^31
+   lanes (above 2^31 points at one point per lane), all on `stream`.
+   PD_ERR_STATE before pd_set_field or after the last step. */
 pd_status pd_propagate(pd_grid g, long long max_steps, void* stream);
 
 /* After the last step: sums n(p) into rho with a fixed-order reduction (the
