@@ -260,6 +260,7 @@ def run_serve(args):
     reqs = [serve.Request.from_workload(w) for w in wl.config5(count=args.requests, seed=5, rate_per_s=rate)]
     ex = serve.GpuExecutor(pd, stream=st)
     res = serve.Server(ex, budget, **kw).run(reqs)
+    reused = ex.reused
     ex.close()
     line = {
         "metric": METRIC, "value": res.point_steps_per_s, "unit": "point-steps/s", "n_gpus": 1,
@@ -271,7 +272,8 @@ def run_serve(args):
                                    args.epoch_ms),
                    "requests": args.requests, "rate_per_s": rate, "budget_bytes": budget,
                    "epoch_steps": args.epoch_steps, "policy": args.policy, "epoch_ms": args.epoch_ms},
-        "p50_ms": res.p50_ms, "p99_ms": res.p99_ms, "mean_ms": res.mean_ms, "serve": res.as_dict(),
+        "p50_ms": res.p50_ms, "p99_ms": res.p99_ms, "mean_ms": res.mean_ms,
+        "serve": dict(res.as_dict(), handles_reused=reused),
         "capacity": {"requests_per_s": capacity_rps, "point_steps_per_s": cap.point_steps_per_s,
                      "requests": args.capacity_requests},
         "roofline": None, "cpu_baseline": None,
