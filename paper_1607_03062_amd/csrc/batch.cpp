@@ -14,13 +14,9 @@
 
 using namespace pdx;
 
-struct pd_batch_s {
-  std::vector<pd_grid> grids;
-  int device = -1;
-  int points_per_lane = 4;  // fastest measured for FP32, FP64 and mixed batches on MI355X
-  int block_threads = 256;
-
-  // device descriptors
+// Device descriptors of one launch sequence: solves, work items, density jobs, the
+// work counter and one rho per member.
+struct BatchDescriptors {
   BatchSolve* d_solves = nullptr;
   size_t cap_solves = 0;
   BatchItem* d_items = nullptr;
@@ -28,15 +24,34 @@ struct pd_batch_s {
   DensityJob* d_jobs = nullptr;
   size_t cap_jobs = 0;
   double* d_rho = nullptr;  // one rho per member, in member order
-  size_t cap_rho_dev = 0;
+  size_t cap_rho = 0;
   unsigned int* d_counter = nullptr;
+};
+
+struct pd_batch_s {
+  std::vector<pd_grid> grids;
+  int device = -1;
+  int points_per_lane = 4;  // fastest measured for FP32, FP64 and mixed batches on MI355X
+  int block_threads = 256;
+
+  // Two descriptor sets: the captured whole-solve graph reads its own, which only a
+  // new capture writes, so that epochs (pd_batch_step, the autotuner) between two
+  // replays cannot change what a replay does.
+  BatchDescriptors epoch;
+  BatchDescriptors whole;
 
   // pinned host staging of the descriptors and of rho
   unsigned char* h_stage = nullptr;
   size_t cap_stage = 0;
   double* h_rho = nullptr;
   size_t cap_rho = 0;
-  hipEvent_t staged = nullptr;  // recorded after the last upload from h_stage
+  hipEvent_t staged = nullptr;      // recorded after the last upload from h_stage
+  hipEvent_t epoch_done = nullptr;  // after the last epoch's launches (its descriptors are free again)
+  hipEvent_t whole_done = nullptr;  // after the last replay of the graph
+  // the members outside the persistent kernel run on the side stream, forked from
+  // and joined back into the caller's stream
+  hipStream_t side_stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 
   // captured whole-solve launch
   hipStream_t capture_stream = nullptr;
@@ -55,13 +70,15 @@ void free_dev(void* p) {
   if (p) (void)hipFree(p);
 }
 
+// Grow a buffer to at least n elements (at least doubling, so that a slowly
+// rising high-water mark reallocates rarely); the old content is not kept.
 template <typename T>
 pd_status ensure_device(T** p, size_t* cap, size_t n) {
   if (n <= *cap) return PD_OK;
+  const size_t want = std::max(n, *cap * 2);
   free_dev(*p);
   *p = nullptr;
   *cap = 0;
-  size_t want = std::max(n, *cap * 2);
   hipError_t e = hipMalloc(reinterpret_cast<void**>(p), want * sizeof(T));
   if (e != hipSuccess) return hip_error(e, "hipMalloc(batch descriptors)");
   *cap = want;
@@ -70,10 +87,10 @@ pd_status ensure_device(T** p, size_t* cap, size_t n) {
 
 pd_status ensure_pinned(unsigned char** p, size_t* cap, size_t n) {
   if (n <= *cap) return PD_OK;
+  const size_t want = std::max(n, *cap * 2);
   if (*p) (void)hipHostFree(*p);
   *p = nullptr;
   *cap = 0;
-  size_t want = std::max(n, *cap * 2);
   hipError_t e = hipHostMalloc(reinterpret_cast<void**>(p), want, hipHostMallocDefault);
   if (e != hipSuccess) return hip_error(e, "hipHostMalloc(batch staging)");
   *cap = want;
@@ -81,7 +98,10 @@ pd_status ensure_pinned(unsigned char** p, size_t* cap, size_t n) {
 }
 
 void drop_graph(pd_batch b) {
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->exec) {
+    (void)hipEventSynchronize(b->whole_done);  // no replay still in flight
+    (void)hipGraphExecDestroy(b->exec);
+  }
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
@@ -110,8 +130,10 @@ struct Plan {
 bool persistent_member(pd_grid g) { return g->scheme == PD_SCHEME_STRANG && !g->field.elliptic; }
 
 // Descriptors for advancing member i over steps [begin[i], end[i]) (no work
-// where begin == end); jobs for the members whose end reaches their last step.
-pd_status make_plan(pd_batch b, const std::vector<long long>& begin, const std::vector<long long>& end, Plan* plan) {
+// where begin == end); jobs for the members whose end reaches their last step,
+// each also writing its rho to rho_copies[i].
+pd_status make_plan(pd_batch b, double* rho_copies, const std::vector<long long>& begin, const std::vector<long long>& end,
+                    Plan* plan) {
   const size_t n = b->grids.size();
   plan->solves.resize(n);
   std::vector<size_t> order;
@@ -154,7 +176,7 @@ pd_status make_plan(pd_batch b, const std::vector<long long>& begin, const std::
     j.tile_begin = plan->density_tiles;
     j.partial = g->d_partial;
     j.rho = g->d_rho;
-    j.rho_copy = b->d_rho + i;
+    j.rho_copy = rho_copies + i;
     j.scale = g->density_scale();
     plan->jobs.push_back(j);
     plan->density_tiles += density_partials(j.npts);
@@ -162,12 +184,12 @@ pd_status make_plan(pd_batch b, const std::vector<long long>& begin, const std::
   return PD_OK;
 }
 
-// Copy the plan's descriptors to the device through the pinned staging buffer.
-pd_status upload(pd_batch b, const Plan& plan, hipStream_t stream) {
+// Copy the plan's descriptors to the set D through the pinned staging buffer.
+pd_status upload(pd_batch b, BatchDescriptors& D, const Plan& plan, hipStream_t stream) {
   pd_status s;
-  if ((s = ensure_device(&b->d_solves, &b->cap_solves, std::max<size_t>(plan.solves.size(), 1))) != PD_OK) return s;
-  if ((s = ensure_device(&b->d_items, &b->cap_items, std::max<size_t>(plan.items.size(), 1))) != PD_OK) return s;
-  if ((s = ensure_device(&b->d_jobs, &b->cap_jobs, std::max<size_t>(plan.jobs.size(), 1))) != PD_OK) return s;
+  if ((s = ensure_device(&D.d_solves, &D.cap_solves, std::max<size_t>(plan.solves.size(), 1))) != PD_OK) return s;
+  if ((s = ensure_device(&D.d_items, &D.cap_items, std::max<size_t>(plan.items.size(), 1))) != PD_OK) return s;
+  if ((s = ensure_device(&D.d_jobs, &D.cap_jobs, std::max<size_t>(plan.jobs.size(), 1))) != PD_OK) return s;
   const size_t a = plan.solves.size() * sizeof(BatchSolve), c = plan.items.size() * sizeof(BatchItem),
                d = plan.jobs.size() * sizeof(DensityJob);
   // the previous upload from the staging buffer must have been consumed
@@ -177,36 +199,51 @@ pd_status upload(pd_batch b, const Plan& plan, hipStream_t stream) {
   std::memcpy(b->h_stage, plan.solves.data(), a);
   std::memcpy(b->h_stage + a, plan.items.data(), c);
   std::memcpy(b->h_stage + a + c, plan.jobs.data(), d);
-  if (a && (e = hipMemcpyAsync(b->d_solves, b->h_stage, a, hipMemcpyHostToDevice, stream)) != hipSuccess)
+  if (a && (e = hipMemcpyAsync(D.d_solves, b->h_stage, a, hipMemcpyHostToDevice, stream)) != hipSuccess)
     return hip_error(e, "hipMemcpyAsync(solves)");
-  if (c && (e = hipMemcpyAsync(b->d_items, b->h_stage + a, c, hipMemcpyHostToDevice, stream)) != hipSuccess)
+  if (c && (e = hipMemcpyAsync(D.d_items, b->h_stage + a, c, hipMemcpyHostToDevice, stream)) != hipSuccess)
     return hip_error(e, "hipMemcpyAsync(items)");
-  if (d && (e = hipMemcpyAsync(b->d_jobs, b->h_stage + a + c, d, hipMemcpyHostToDevice, stream)) != hipSuccess)
+  if (d && (e = hipMemcpyAsync(D.d_jobs, b->h_stage + a + c, d, hipMemcpyHostToDevice, stream)) != hipSuccess)
     return hip_error(e, "hipMemcpyAsync(jobs)");
   if ((e = hipEventRecord(b->staged, stream)) != hipSuccess) return hip_error(e, "hipEventRecord");
   return PD_OK;
 }
 
-pd_status enqueue(pd_batch b, const Plan& plan, hipStream_t stream) {
+// Enqueue one launch sequence on `stream`: the persistent kernel over the plan's
+// items and, concurrently on the side stream (forked from and joined back into
+// `stream` with events, so the sequence stays one stream-ordered unit and one
+// captured graph), the other members' own launches; then the batched density.
+// The side launches take the compute units that the persistent kernel's blocks
+// leave as its queue drains.
+pd_status enqueue(pd_batch b, BatchDescriptors& D, const Plan& plan, hipStream_t stream) {
   hipError_t e;
+  const bool fork = !plan.separate.empty();
+  if (fork) {
+    if ((e = hipEventRecord(b->fork, stream)) != hipSuccess) return hip_error(e, "hipEventRecord(fork)");
+    if ((e = hipStreamWaitEvent(b->side_stream, b->fork, 0)) != hipSuccess) return hip_error(e, "hipStreamWaitEvent");
+  }
   if (!plan.items.empty()) {
     int per_cu = batch_blocks_per_cu(b->points_per_lane, b->block_threads);
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || cus <= 0)
       cus = 1;
     long long blocks = std::min<long long>((long long)cus * per_cu, (long long)plan.items.size());
-    e = launch_batch(b->points_per_lane, b->block_threads, (int)blocks, b->d_solves, b->d_items,
-                     (int)plan.items.size(), b->d_counter, stream);
+    e = launch_batch(b->points_per_lane, b->block_threads, (int)blocks, D.d_solves, D.d_items,
+                     (int)plan.items.size(), D.d_counter, stream);
     if (e != hipSuccess) return hip_error(e, "batch launch");
   }
   // the other members: the single-solve kernels, exactly as a solve alone
   for (const auto& m : plan.separate) {
     pd_grid g = b->grids[m.first];
     e = launch_propagate(g->scheme, g->precision, g->points_per_lane, g->block_threads, g->taylor,
-                         g->field.elliptic ? 1 : 0, m.second, stream);
+                         g->field.elliptic ? 1 : 0, m.second, b->side_stream);
     if (e != hipSuccess) return hip_error(e, "member launch");
   }
-  e = launch_batch_density(b->d_jobs, (int)plan.jobs.size(), plan.density_tiles, stream);
+  if (fork) {
+    if ((e = hipEventRecord(b->join, b->side_stream)) != hipSuccess) return hip_error(e, "hipEventRecord(join)");
+    if ((e = hipStreamWaitEvent(stream, b->join, 0)) != hipSuccess) return hip_error(e, "hipStreamWaitEvent");
+  }
+  e = launch_batch_density(D.d_jobs, (int)plan.jobs.size(), plan.density_tiles, stream);
   if (e != hipSuccess) return hip_error(e, "batch density launch");
   return PD_OK;
 }
@@ -220,14 +257,15 @@ pd_status check_members(pd_batch b) {
   return PD_OK;
 }
 
-// Copy the members' rho to rho_out; only members with completed[i] set (all if
-// completed is null) are written.
-pd_status copy_rho(pd_batch b, double* rho_out, const std::vector<char>* completed, hipStream_t stream) {
+// Copy the members' rho from the set D to rho_out; only members with completed[i]
+// set (all if completed is null) are written.
+pd_status copy_rho(pd_batch b, const BatchDescriptors& D, double* rho_out, const std::vector<char>* completed,
+                   hipStream_t stream) {
   if (!rho_out) return PD_OK;
   const size_t n = b->grids.size();
   pd_status s = ensure_pinned(reinterpret_cast<unsigned char**>(&b->h_rho), &b->cap_rho, n * sizeof(double));
   if (s != PD_OK) return s;
-  hipError_t e = hipMemcpyAsync(b->h_rho, b->d_rho, n * sizeof(double), hipMemcpyDeviceToHost, stream);
+  hipError_t e = hipMemcpyAsync(b->h_rho, D.d_rho, n * sizeof(double), hipMemcpyDeviceToHost, stream);
   if (e != hipSuccess) return hip_error(e, "copy of rho");
   if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_error(e, "hipStreamSynchronize");
   for (size_t i = 0; i < n; ++i)
@@ -241,12 +279,21 @@ pd_status prepare_device(pd_batch b) {
   if (b->device < 0) return set_error(PD_ERR_STATE, "a member grid has no field");
   DeviceScope scope(b->device);
   hipError_t e;
-  if ((e = hipMalloc(&b->d_counter, sizeof(unsigned int))) != hipSuccess) return hip_error(e, "hipMalloc(counter)");
-  if ((e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming)) != hipSuccess)
-    return hip_error(e, "hipEventCreate");
+  for (BatchDescriptors* D : {&b->epoch, &b->whole})
+    if ((e = hipMalloc(&D->d_counter, sizeof(unsigned int))) != hipSuccess) return hip_error(e, "hipMalloc(counter)");
+  for (hipEvent_t* ev : {&b->staged, &b->fork, &b->join, &b->epoch_done, &b->whole_done})
+    if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) return hip_error(e, "hipEventCreate");
+  // both streams at the default priority
   if ((e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)) != hipSuccess)
     return hip_error(e, "hipStreamCreate");
+  if ((e = hipStreamCreateWithFlags(&b->side_stream, hipStreamNonBlocking)) != hipSuccess)
+    return hip_error(e, "hipStreamCreate");
   return PD_OK;
+}
+
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
 }
 
 // Advance member i by up to max_steps[i] steps (one epoch of pd_batch_step / _each).
@@ -258,7 +305,12 @@ pd_status step_members(pd_batch b, const long long* max_steps, double* rho_out, 
   if (!scope.ok) return set_error(PD_ERR_DEVICE, "cannot select device %d", b->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t n = b->grids.size();
-  if ((s = ensure_device(&b->d_rho, &b->cap_rho_dev, n)) != PD_OK) return s;
+  hipError_t e;
+  // the epoch descriptors are rewritten below: the previous epoch, on whatever stream
+  // it ran, must have finished reading them
+  if (!capturing(st) && (e = hipStreamWaitEvent(st, b->epoch_done, 0)) != hipSuccess)
+    return hip_error(e, "hipStreamWaitEvent");
+  if ((s = ensure_device(&b->epoch.d_rho, &b->epoch.cap_rho, n)) != PD_OK) return s;
   std::vector<long long> begin(n), end(n);
   for (size_t i = 0; i < n; ++i) {
     pd_grid g = b->grids[i];
@@ -266,9 +318,10 @@ pd_status step_members(pd_batch b, const long long* max_steps, double* rho_out, 
     end[i] = g->steps_done + std::min(g->field.n_steps - g->steps_done, max_steps[i]);
   }
   Plan plan;
-  if ((s = make_plan(b, begin, end, &plan)) != PD_OK) return s;
-  if ((s = upload(b, plan, st)) != PD_OK) return s;
-  if ((s = enqueue(b, plan, st)) != PD_OK) return s;
+  if ((s = make_plan(b, b->epoch.d_rho, begin, end, &plan)) != PD_OK) return s;
+  if ((s = upload(b, b->epoch, plan, st)) != PD_OK) return s;
+  if ((s = enqueue(b, b->epoch, plan, st)) != PD_OK) return s;
+  if ((e = hipEventRecord(b->epoch_done, st)) != hipSuccess) return hip_error(e, "hipEventRecord");
   for (pd_grid g : b->grids)
     if ((s = mark_use(g, st)) != PD_OK) return s;
   b->n_items_last = (int)plan.items.size();
@@ -280,7 +333,7 @@ pd_status step_members(pd_batch b, const long long* max_steps, double* rho_out, 
   }
   if (finished_out)
     for (size_t i = 0; i < n; ++i) finished_out[i] = b->grids[i]->steps_done == b->grids[i]->field.n_steps;
-  return copy_rho(b, rho_out, &completed, st);
+  return copy_rho(b, b->epoch, rho_out, &completed, st);
 }
 
 }  // namespace
@@ -355,19 +408,22 @@ pd_status pd_batch_run(pd_batch b, double* rho_out, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (!graph_current(b)) {
     drop_graph(b);
+    // the graph's descriptors are rewritten below: the last replay must be done with them
+    hipError_t e = hipEventSynchronize(b->whole_done);
+    if (e != hipSuccess) return hip_error(e, "hipEventSynchronize");
     const size_t n = b->grids.size();
-    if ((s = ensure_device(&b->d_rho, &b->cap_rho_dev, n)) != PD_OK) return s;
+    if ((s = ensure_device(&b->whole.d_rho, &b->whole.cap_rho, n)) != PD_OK) return s;
     std::vector<long long> begin(n, 0), end(n);
     for (size_t i = 0; i < n; ++i) end[i] = b->grids[i]->field.n_steps;
     Plan plan;
-    if ((s = make_plan(b, begin, end, &plan)) != PD_OK) return s;
-    if ((s = upload(b, plan, b->capture_stream)) != PD_OK) return s;
-    hipError_t e = hipStreamSynchronize(b->capture_stream);
-    if (e != hipSuccess) return hip_error(e, "hipStreamSynchronize");
-    // Capture: counter reset, persistent kernel, batched density (kernels only).
+    if ((s = make_plan(b, b->whole.d_rho, begin, end, &plan)) != PD_OK) return s;
+    if ((s = upload(b, b->whole, plan, b->capture_stream)) != PD_OK) return s;
+    if ((e = hipStreamSynchronize(b->capture_stream)) != hipSuccess) return hip_error(e, "hipStreamSynchronize");
+    // Capture: counter reset, persistent kernel and the other members' launches on
+    // two branches, batched density (kernel nodes only).
     if ((e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
       return hip_error(e, "hipStreamBeginCapture");
-    pd_status se = enqueue(b, plan, b->capture_stream);
+    pd_status se = enqueue(b, b->whole, plan, b->capture_stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(b->capture_stream, &graph);
     if (se != PD_OK) {
@@ -390,11 +446,12 @@ pd_status pd_batch_run(pd_batch b, double* rho_out, void* stream) {
   }
   hipError_t e = hipGraphLaunch(b->exec, st);
   if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
+  if ((e = hipEventRecord(b->whole_done, st)) != hipSuccess) return hip_error(e, "hipEventRecord");
   for (pd_grid g : b->grids) {
     g->steps_done = g->field.n_steps;
     if ((s = mark_use(g, st)) != PD_OK) return s;
   }
-  return copy_rho(b, rho_out, nullptr, st);
+  return copy_rho(b, b->whole, rho_out, nullptr, st);
 }
 
 pd_status pd_batch_step(pd_batch b, long long max_steps, double* rho_out, int* finished_out, void* stream) {
@@ -434,16 +491,20 @@ void pd_batch_destroy(pd_batch b) {
   if (b->device >= 0) {
     DeviceScope scope(b->device);
     drop_graph(b);
-    if (b->staged) {
-      (void)hipEventSynchronize(b->staged);
-      (void)hipEventDestroy(b->staged);
-    }
+    if (b->staged) (void)hipEventSynchronize(b->staged);
+    if (b->epoch_done) (void)hipEventSynchronize(b->epoch_done);
+    if (b->whole_done) (void)hipEventSynchronize(b->whole_done);
+    for (hipEvent_t ev : {b->staged, b->fork, b->join, b->epoch_done, b->whole_done})
+      if (ev) (void)hipEventDestroy(ev);
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
-    free_dev(b->d_solves);
-    free_dev(b->d_items);
-    free_dev(b->d_jobs);
-    free_dev(b->d_rho);
-    free_dev(b->d_counter);
+    if (b->side_stream) (void)hipStreamDestroy(b->side_stream);
+    for (BatchDescriptors* D : {&b->epoch, &b->whole}) {
+      free_dev(D->d_solves);
+      free_dev(D->d_items);
+      free_dev(D->d_jobs);
+      free_dev(D->d_rho);
+      free_dev(D->d_counter);
+    }
     if (b->h_stage) (void)hipHostFree(b->h_stage);
     if (b->h_rho) (void)hipHostFree(b->h_rho);
   }

@@ -162,6 +162,57 @@ def test_epochs_with_a_step_limit_per_member(gpu):
     b.close()
 
 
+def mixed_members(pd, count=6):
+    """Strang members of every precision (persistent kernel) and members that run their own
+    launches on the side stream: midpoint, fourth order, a y component, the K- valley."""
+    ms = members(pd, count=count)
+    extra = [("midpoint", "fp32", "both", 0.0, 2300), ("strang4", "fp64", "both", 0.0, 600),
+             ("strang", "fp32", "K-", 0.7, 1900), ("midpoint4", "fp64", "K+", 0.0, 500)]
+    for q, (scheme, prec, valley, ell, N) in enumerate(extra):
+        c = {"name": "side%d-%s" % (q, scheme), "grid": {"nx": 41 + 6 * q, "ny": 29 + 4 * q, "px": (-2.0, 2.0),
+                                                          "py": (-1.5, 1.5)},
+             "field": dict(wl.sin2(0.3, 0.6, 3), ellipticity=ell), "n_steps": N}
+        s = pd.Solver.for_grid(c["grid"], prec, scheme, valley)
+        s.set_field(c["field"], c["n_steps"])
+        ms.append((c, s))
+    return ms
+
+
+def check_members(ms, ref, rho, where):
+    for (c, s), (n0, r0), r in zip(ms, ref, rho):
+        n, rr = member_n(s)
+        assert np.array_equal(n, n0), (where, c["name"])
+        assert r == r0 and rr == r0, (where, c["name"])
+
+
+def test_epochs_and_autotune_between_replays(gpu):
+    """Regression: epochs (pd_batch_step, pd_batch_step_each) and the autotuner between two
+    pd_batch_run calls rewrite the epoch descriptors; a replay of the captured whole-solve
+    graph must still run every member's whole solve (the graph reads descriptors of its
+    own).  Members of other schemes run beside the persistent kernel in the graph."""
+    ms = mixed_members(gpu)
+    ref = [alone(s) for _, s in ms]
+    b = gpu.Batch([s for _, s in ms])
+    shape = (b.info()["points_per_lane"], b.info()["block_threads"])
+    check_members(ms, ref, b.run(), "capture")
+    assert b.info()["graph_captured"] == 1 and b.info()["separate_launches"] == 4
+    for _, s in ms:
+        s.rewind()
+    rng = np.random.default_rng(3)
+    for _ in range(3):  # partial epochs: members left mid-solve, a few finished
+        b.step_each([int(v) for v in rng.choice([0, 5, 333, 1200], size=len(ms))])
+    b.step(250)
+    check_members(ms, ref, b.run(), "replay after epochs")
+    assert b.info()["graph_captured"] == 1
+    b.autotune(128)
+    b.set_launch(*shape)  # the captured shape again: the next run replays
+    assert b.info()["graph_captured"] == 1
+    check_members(ms, ref, b.run(), "replay after autotune")
+    b.close()
+    for _, s in ms:
+        s.close()
+
+
 @pytest.mark.parametrize("ppl,block", [(1, 64), (2, 128), (4, 256)])
 def test_batch_launch_shapes(gpu, ppl, block):
     ms = members(gpu, count=5)

@@ -29,6 +29,8 @@ MUTANTS = {
     "v_spinor_sign": ("v[0] = -Px / d; v[1] = Py / d;", "v[0] = -Px / d; v[1] = -Py / d;"),
     "u_spinor_sign": ("u[0] = E / d; u[1] = 0.0; u[2] = Px / d; u[3] = Py / d;",
                       "u[0] = E / d; u[1] = 0.0; u[2] = Px / d; u[3] = -Py / d;"),
+    "kahan_compensation_sign": ("c = (t - s) - y;", "c = (t - s) + y;"),
+    "kahan_drops_compensation": ("double y = n[k] - c;", "double y = n[k];"),
     "density_factor": ("return 4.0 * dx * dy / (4.0 * M_PI * M_PI) * s;",
                        "return 2.0 * dx * dy / (4.0 * M_PI * M_PI) * s;"),
     "grid_spacing": ("double d = (p_max - p_min) / (double)n;", "double d = (p_max - p_min) / (double)(n - 1);"),
@@ -73,6 +75,7 @@ QUICK_PINS = [
     pins.test_sin2_vector_potential_is_minus_integral_of_E,
     pins.test_constant_and_pulse_vector_potentials,
     pins.test_density_scale,
+    pins.test_density_compensated_sum,
     lambda: pins.test_brute_force_tiny_grid("strang"),
     lambda: pins.test_brute_force_tiny_grid("midpoint"),
     pins.test_masked_point_at_zero_momentum,

@@ -131,6 +131,22 @@ def test_density_scale():
     assert abs(rho - 4 * 3.5 * 2.0 / (4 * math.pi ** 2)) < 1e-16
 
 
+def test_density_compensated_sum():
+    """The compensated (Kahan) branch of the density sum is pinned to the correctly
+    rounded sum (math.fsum) on inputs where the plain index-order sum is visibly off: a
+    1 followed by many terms each below half an ulp of the running sum, and seeded
+    values spanning nine decades.  The rectangle-rule factor is applied the same way."""
+    rng = np.random.default_rng(12)
+    cases = [np.r_[1.0, np.full(999, 1e-17)], np.r_[1.0, rng.uniform(0.0, 1e-16, 4999)],
+             rng.uniform(0.0, 1.0, 5000) * np.r_[1.0, np.full(4999, 1e-9)]]
+    for n in cases:
+        g = {"nx": n.shape[0], "ny": 1, "px": (-0.5, 1.5), "py": (0.0, 3.0)}
+        dx, dy = 2.0 / n.shape[0], 3.0
+        exact = 4.0 * dx * dy / (4.0 * math.pi * math.pi) * math.fsum(n)
+        assert abs(oracle.density(g, n, kahan=True) - exact) <= 4e-16 * exact
+        assert abs(oracle.density(g, n) - exact) > 1e-15 * exact  # the case needs compensation
+
+
 # ---------------------------------------------------------------------------
 # Independent brute force on tiny inputs (Sec. II Eq. (1) with the paper's own
 # spinor normalisation 1/(2 E_out 2 E_in), Sec. III Eqs. (9), (11)-(12))
