@@ -389,51 +389,107 @@ void build_step_table(const FieldTables& t, int scheme, int precision, int form,
   store(N, (size_t)S, vsign * 0.5 * t.dt * (c[0] * ay(0, 0)));  // opening half step
 }
 
-size_t point_coefficient_pairs_x(int scheme) { return composition_of(scheme).stages == 5 ? 2 : 1; }
-size_t point_coefficient_pairs_y(int scheme) { return composition_of(scheme).stages == 5 ? 3 : 2; }
+size_t point_coefficient_pairs_x(int scheme, int precision) {
+  return (composition_of(scheme).stages == 5 ? 2 : 1) * (size_t)coefficient_phases(precision);
+}
+size_t point_coefficient_pairs_y(int scheme, int precision) {
+  return (composition_of(scheme).stages == 5 ? 2 : 1) * (size_t)coefficient_phases(precision) + 1;
+}
+
+namespace {
+
+// The `phases` FP32 values of a coefficient x: the FP32 neighbours of |x| below
+// and above it, the upper one in round(phases * f) of the phases, f being where |x|
+// lies between them, with the sign of x (so that -x gives the negated values: the
+// rotations of the K- valley are those of K+ with every angle negated); the phases
+// that take the upper value are spread over the cycle (order 0, 2, 1, 3 for four
+// phases), so that partial sums over the cycle stay close to x too.
+void dither(double x, int phases, float* out) {
+  if (x < 0.0) {
+    dither(-x, phases, out);
+    for (int h = 0; h < phases; ++h) out[h] = -out[h];
+    return;
+  }
+  float lo = (float)x;
+  if ((double)lo > x) lo = std::nextafter(lo, -INFINITY);
+  const float hi = std::nextafter(lo, INFINITY);
+  const double f = (x - (double)lo) / ((double)hi - (double)lo);
+  const int up = (int)std::lround(f * phases);
+  for (int h = 0; h < phases; ++h) {
+    // rank of phase h in the bit-reversed order of the cycle
+    int r = 0;
+    for (int b = 1, v = h; b < phases; b <<= 1, v >>= 1) r = (r << 1) | (v & 1);
+    out[h] = r < up ? hi : lo;
+  }
+}
+
+}  // namespace
 
 void build_point_coefficients(const Grid& g, const FieldTables& t, int scheme, int precision, int form, double vsign,
                               std::vector<unsigned char>* bytes, size_t* col_offset, size_t* row_offset) {
-  const size_t v = is_fp32(precision) ? sizeof(float) : sizeof(double);
-  const size_t nxp = point_coefficient_pairs_x(scheme), nyp = point_coefficient_pairs_y(scheme);
+  const bool f32 = is_fp32(precision);
+  const size_t v = f32 ? sizeof(float) : sizeof(double);
+  const int H = coefficient_phases(precision);
+  const size_t nxp = point_coefficient_pairs_x(scheme, precision), nyp = point_coefficient_pairs_y(scheme, precision);
   auto align = [](size_t n) { return (n + 255) / 256 * 256; };
   *col_offset = align(bytes->size());
   *row_offset = align(*col_offset + 2 * nxp * v * (size_t)g.nx);
   bytes->resize(align(*row_offset + 2 * nyp * v * (size_t)g.ny));
-  auto store = [&](size_t off, size_t idx, double x) {
-    if (is_fp32(precision))
-      put<float>(bytes, off, idx, x);
-    else
-      put<double>(bytes, off, idx, x);
+  // pair `pair` of `entry` (column or row) from the exact coefficients (a, s): one
+  // value per phase in FP32 (dithered), the value itself in FP64
+  auto store_pair = [&](size_t off, size_t entry, size_t per_entry, size_t pair, int phases, double a, double s) {
+    float da[kDitherFP32], ds[kDitherFP32];
+    if (f32 && phases > 1) {
+      dither(a, phases, da);
+      dither(s, phases, ds);
+    }
+    for (int h = 0; h < phases; ++h) {
+      const size_t idx = 2 * (per_entry * entry + pair + (size_t)h);
+      if (!f32) {
+        put<double>(bytes, off, idx, a);
+        put<double>(bytes, off, idx + 1, s);
+      } else if (phases > 1) {
+        put<float>(bytes, off, idx, da[h]);
+        put<float>(bytes, off, idx + 1, ds[h]);
+      } else {
+        put<float>(bytes, off, idx, a);
+        put<float>(bytes, off, idx + 1, s);
+      }
+    }
   };
   // Half-angle multipliers of dt px and dt py: x rotation of stage j: c_j; y
   // rotation after stage j: (c_j + c_j+1) / 2 (cyclic); opening / closing half: c_1 / 2.
   const double* c = t.comp.c;
   double mx[2], my[3];
+  int nmx, nmy;  // distinct multipliers (the half step excluded)
   if (t.comp.stages == 5) {
     mx[0] = c[0];
     mx[1] = c[2];
     my[0] = 0.5 * (c[0] + c[1]);
     my[1] = 0.5 * (c[1] + c[2]);
     my[2] = 0.5 * c[0];
+    nmx = nmy = 2;
   } else {
     mx[0] = 1.0;
     my[0] = 1.0;
     my[1] = 0.5;
+    nmx = nmy = 1;
   }
   double a, s;
   for (int i = 0; i < g.nx; ++i)
-    for (size_t q = 0; q < nxp; ++q) {
+    for (int q = 0; q < nmx; ++q) {
       rotation_coefficients(vsign * (mx[q] * t.dt) * g.px(i), form, &a, &s);
-      store(*col_offset, (2 * nxp) * (size_t)i + 2 * q, a);
-      store(*col_offset, (2 * nxp) * (size_t)i + 2 * q + 1, s);
+      store_pair(*col_offset, (size_t)i, nxp, (size_t)q * H, H, a, s);
     }
-  for (int j = 0; j < g.ny; ++j)
-    for (size_t q = 0; q < nyp; ++q) {
+  for (int j = 0; j < g.ny; ++j) {
+    for (int q = 0; q < nmy; ++q) {
       rotation_coefficients(vsign * (my[q] * t.dt) * g.py(j), form, &a, &s);
-      store(*row_offset, (2 * nyp) * (size_t)j + 2 * q, a);
-      store(*row_offset, (2 * nyp) * (size_t)j + 2 * q + 1, s);
+      store_pair(*row_offset, (size_t)j, nyp, (size_t)q * H, H, a, s);
     }
+    // the opening / closing half step: applied twice per solve, one value
+    rotation_coefficients(vsign * (my[nmy] * t.dt) * g.py(j), form, &a, &s);
+    store_pair(*row_offset, (size_t)j, nyp, (size_t)nmy * H, 1, a, s);
+  }
 }
 
 int strang_form(const Grid& g, const FieldTables& t) {

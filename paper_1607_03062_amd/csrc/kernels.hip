@@ -176,42 +176,69 @@ struct Layout<5> {
   __device__ static constexpr int ycls(int j) { return (j == 1 || j == 2) ? 1 : 0; }
 };
 
+// Coefficient phases of the per-point rotations (host: coefficient_phases): the
+// FP32 forms cycle through kDitherFP32 values of each coefficient, step k using
+// value k mod kDitherFP32.
+template <typename R>
+constexpr int phases_of() {
+  return sizeof(R) == 4 ? kDitherFP32 : 1;
+}
+
+// Period of a solve's step pattern: the coefficient phases and, for alternating
+// shears, the orientation parity.  Steps run in groups that start at multiples of
+// it, so inside a group every step's pattern is a compile-time constant.
+template <typename R, int SH>
+constexpr int step_period() {
+  return (SH == kShearAlt && phases_of<R>() % 2 != 0) ? 2 * phases_of<R>() : phases_of<R>();
+}
+
 // The Bloch vectors of a lane's points and their per-point rotations.
 template <typename R, int PPL, int FORM, int NS, int POL, int SH>
 struct BlochLanes {
   using L = Layout<NS>;
   static constexpr int kRow = 2 * NS * (1 + POL);  // table values per step
+  static constexpr int D = phases_of<R>();
+  static constexpr int P = step_period<R, SH>();
   R x[PPL], y[PPL], z[PPL];
-  R aX[L::NX][PPL], sX[L::NX][PPL];          // x rotations by 2 c dt px
-  R aY[L::NY - 1][PPL], sY[L::NY - 1][PPL];  // y rotations after the stages, by (c_j + c_j+1) dt py
+  R aX[L::NX][D][PPL], sX[L::NX][D][PPL];          // x rotations by 2 c dt px, per phase
+  R aY[L::NY - 1][D][PPL], sY[L::NY - 1][D][PPL];  // y rotations after the stages, by (c_j + c_j+1) dt py
 
-  // One step; row = the step's table values.  LAST: the y rotation after the
-  // last stage is the closing half step (ha, hs per point).  odd: the parity of
-  // the step's absolute index (stage j of step k has parity k + j, NS odd).
-  template <bool LAST>
-  __device__ __forceinline__ void step(const R* row, const R* ha, const R* hs, bool odd = false) {
+  // One step; row = the step's table values; PH = the step's absolute index modulo
+  // P (phase PH % D of the coefficients; with alternating shears stage j of step k
+  // has parity k + j, NS odd).  LAST: the y rotation after the last stage is the
+  // closing half step (ha, hs per point).
+  template <bool LAST, int PH>
+  __device__ __forceinline__ void step(const R* row, const R* ha, const R* hs) {
+    constexpr int h = PH % D;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
-      const bool o = odd != ((j & 1) != 0);
+      const bool o = ((PH & 1) != 0) != ((j & 1) != 0);
 #pragma unroll
       for (int q = 0; q < PPL; ++q) {
         rot<FORM, SH>(y[q], z[q], row[2 * j], row[2 * j + 1], o);
-        rot<FORM, SH>(y[q], z[q], aX[L::xcls(j)][q], sX[L::xcls(j)][q], o);
+        rot<FORM, SH>(y[q], z[q], aX[L::xcls(j)][h][q], sX[L::xcls(j)][h][q], o);
         if (LAST && j == NS - 1)
           rot<FORM, SH>(z[q], x[q], ha[q], hs[q], o);
         else
-          rot<FORM, SH>(z[q], x[q], aY[L::ycls(j)][q], sY[L::ycls(j)][q], o);
+          rot<FORM, SH>(z[q], x[q], aY[L::ycls(j)][h][q], sY[L::ycls(j)][h][q], o);
         if (POL) rot<FORM, SH>(z[q], x[q], row[2 * NS + 2 * j], row[2 * NS + 2 * j + 1], o);
       }
     }
   }
 
-  // A step whose parity is known only at run time (uniform over the wave).
-  __device__ __forceinline__ void step_at(const R* row, long long k) {
-    if (SH == kShearAlt && (k & 1))
-      step<false>(row, nullptr, nullptr, true);
-    else
-      step<false>(row, nullptr, nullptr, false);
+  // A step whose pattern index k mod P is known only at run time (uniform over the wave).
+  template <bool LAST>
+  __device__ __forceinline__ void step_at(const R* row, long long k, const R* ha = nullptr, const R* hs = nullptr) {
+    switch ((int)(k % P)) {
+      case 0: step<LAST, 0>(row, ha, hs); break;
+      case 1: if constexpr (P > 1) step<LAST, 1 % P>(row, ha, hs); break;
+      case 2: if constexpr (P > 2) step<LAST, 2 % P>(row, ha, hs); break;
+      case 3: if constexpr (P > 3) step<LAST, 3 % P>(row, ha, hs); break;
+      case 4: if constexpr (P > 4) step<LAST, 4 % P>(row, ha, hs); break;
+      case 5: if constexpr (P > 5) step<LAST, 5 % P>(row, ha, hs); break;
+      case 6: if constexpr (P > 6) step<LAST, 6 % P>(row, ha, hs); break;
+      default: if constexpr (P > 7) step<LAST, 7 % P>(row, ha, hs); break;
+    }
   }
 
   __device__ __forceinline__ void renormalise() {
@@ -233,40 +260,46 @@ struct RowN {
   R v[W];
 };
 
+// Steps U of a group that starts at a multiple of the step period, with the
+// pattern index of each known at compile time.
+template <typename Lanes, typename Row, int U, int G>
+__device__ __forceinline__ void group_steps(Lanes& L, const Row* r) {
+  if constexpr (U < G) {
+    L.template step<false, U % Lanes::P>(r[U].v, nullptr, nullptr);
+    group_steps<Lanes, Row, U + 1, G>(L, r);
+  }
+}
+
 // Steps [k, k_full) with the table rows read by the scalar unit (SGPR operands).
 template <typename R, int PPL, int FORM, int NS, int POL, int SH>
 __device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM, NS, POL, SH>& L, const R* __restrict__ table,
                                              long long k, long long k_full) {
   using Lanes = BlochLanes<R, PPL, FORM, NS, POL, SH>;
   using Row = RowN<R, Lanes::kRow>;
+  constexpr int P = Lanes::P;
   const Row* __restrict__ tab = reinterpret_cast<const Row*>(table);
+  constexpr int kRows = Lanes::kRow >= 8 ? 1 : 8 / (Lanes::kRow / 2);  // rows fetched together
+  constexpr int kGroup = (kRows + P - 1) / P * P;                     // whole periods
   while (k < k_full) {
     long long seg = k_full;
     if (sizeof(R) == 4) {
       long long next = (k / kRenormEvery + 1) * kRenormEvery;
       seg = next < k_full ? next : k_full;
     }
-    constexpr int kRows = Lanes::kRow >= 8 ? 1 : 8 / (Lanes::kRow / 2);  // rows fetched together
-    // alternating shears: groups of an even number of steps that start at even steps,
-    // so a step's parity is its place in the group (a compile-time constant)
-    constexpr int kGroup = (SH == kShearAlt && kRows % 2 == 1) ? 2 * kRows : kRows;
-    if constexpr (SH == kShearAlt) {
-      if ((k & 1) && k < seg) {
-        const Row r = tab[k];
-        L.step_at(r.v, k);
-        ++k;
-      }
+    // up to the first multiple of the period (renormalisation steps are multiples of it)
+    for (; (k % P) != 0 && k < seg; ++k) {
+      const Row r = tab[k];
+      L.template step_at<false>(r.v, k);
     }
     for (; k + kGroup <= seg; k += kGroup) {
       Row r[kGroup];
 #pragma unroll
       for (int u = 0; u < kGroup; ++u) r[u] = tab[k + u];
-#pragma unroll
-      for (int u = 0; u < kGroup; ++u) L.template step<false>(r[u].v, nullptr, nullptr, (u & 1) != 0);
+      group_steps<Lanes, Row, 0, kGroup>(L, r);
     }
     for (; k < seg; ++k) {
       const Row r = tab[k];
-      L.step_at(r.v, k);
+      L.template step_at<false>(r.v, k);
     }
     if (sizeof(R) == 4 && (k % kRenormEvery) == 0) L.renormalise();
   }
@@ -274,12 +307,14 @@ __device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM, NS, POL, S
 
 // Steps [k, k_full) with the table staged through LDS in chunks of `chunk` rows
 // (absolute chunk boundaries; a power of two dividing the renormalisation period
-// in the FP32 form), so every lane reads its rotation from VGPRs.
+// in the FP32 form, and a multiple of the step period), so every lane reads its
+// rotation from VGPRs.
 template <typename R, int PPL, int FORM, int NS, int POL, int SH>
 __device__ __forceinline__ void steps_lds(BlochLanes<R, PPL, FORM, NS, POL, SH>& L, const R* __restrict__ table,
                                           long long k, long long k_full, long long chunk) {
   using Lanes = BlochLanes<R, PPL, FORM, NS, POL, SH>;
   using Row = RowN<R, Lanes::kRow>;
+  constexpr int P = Lanes::P;
   const Row* __restrict__ tab = reinterpret_cast<const Row*>(table);
   extern __shared__ unsigned char pd_lds[];
   Row* rows = reinterpret_cast<Row*>(pd_lds);
@@ -290,29 +325,28 @@ __device__ __forceinline__ void steps_lds(BlochLanes<R, PPL, FORM, NS, POL, SH>&
     __syncthreads();  // every wave has finished with the previous chunk
     for (int t = threadIdx.x; t < cnt; t += blockDim.x) rows[t] = tab[k + t];
     __syncthreads();
-    if constexpr (SH == kShearAlt) {
-      // in pairs from an even step: parities known at compile time
-      int t = 0;
-      if (k & 1) {
-        const Row r = rows[0];
-        L.step_at(r.v, k);
-        t = 1;
-      }
-#pragma unroll 4
-      for (; t + 1 < cnt; t += 2) {
-        const Row r0 = rows[t], r1 = rows[t + 1];
-        L.template step<false>(r0.v, nullptr, nullptr, false);
-        L.template step<false>(r1.v, nullptr, nullptr, true);
-      }
-      if (t < cnt) {
+    int t = 0;
+    for (; ((k + t) % P) != 0 && t < cnt; ++t) {
+      const Row r = rows[t];
+      L.template step_at<false>(r.v, k + t);
+    }
+    if constexpr (P == 1) {
+#pragma unroll 8
+      for (; t < cnt; ++t) {
         const Row r = rows[t];
-        L.step_at(r.v, k + t);
+        L.template step<false, 0>(r.v, nullptr, nullptr);
       }
     } else {
-#pragma unroll 8
-      for (int t = 0; t < cnt; ++t) {
+#pragma unroll 2
+      for (; t + P <= cnt; t += P) {
+        Row r[P];
+#pragma unroll
+        for (int u = 0; u < P; ++u) r[u] = rows[t + u];
+        group_steps<Lanes, Row, 0, P>(L, r);
+      }
+      for (; t < cnt; ++t) {
         const Row r = rows[t];
-        L.template step<false>(r.v, nullptr, nullptr);
+        L.template step_at<false>(r.v, k + t);
       }
     }
     k = cend;
@@ -326,8 +360,10 @@ template <typename R, int PPL, int STAGE, int FORM, int NS, int POL, int SH>
 __device__ __forceinline__ void strang_tile(const SolveParams& p, const long long base) {
   using Lanes = BlochLanes<R, PPL, FORM, NS, POL, SH>;
   using LY = Layout<NS>;
-  constexpr int CX = 2 * LY::NX, CY = 2 * LY::NY;  // coefficient values per column / row
-  constexpr int HALF = 2 * (LY::NY - 1);           // offset of the half-step pair in a row
+  constexpr int D = Lanes::D;
+  constexpr int CX = 2 * LY::NX * D;                // coefficient values per column
+  constexpr int CY = 2 * ((LY::NY - 1) * D + 1);    // per row: the phased pairs, then the half step
+  constexpr int HALF = 2 * (LY::NY - 1) * D;        // offset of the half-step pair in a row
   const R* __restrict__ colc = static_cast<const R*>(p.col_coef);
   const R* __restrict__ rowc = static_cast<const R*>(p.row_coef);
   const R* __restrict__ table = static_cast<const R*>(p.table);
@@ -339,15 +375,19 @@ __device__ __forceinline__ void strang_tile(const SolveParams& p, const long lon
     if (idx >= p.npts) idx = p.npts - 1;  // tail lanes recompute a valid point and store nothing
     PointCoords c = coords(p, idx);
 #pragma unroll
-    for (int m = 0; m < LY::NX; ++m) {
-      L.aX[m][q] = colc[CX * c.i + 2 * m];
-      L.sX[m][q] = colc[CX * c.i + 2 * m + 1];
-    }
+    for (int m = 0; m < LY::NX; ++m)
 #pragma unroll
-    for (int m = 0; m < LY::NY - 1; ++m) {
-      L.aY[m][q] = rowc[CY * c.j + 2 * m];
-      L.sY[m][q] = rowc[CY * c.j + 2 * m + 1];
-    }
+      for (int h = 0; h < D; ++h) {
+        L.aX[m][h][q] = colc[CX * c.i + 2 * (m * D + h)];
+        L.sX[m][h][q] = colc[CX * c.i + 2 * (m * D + h) + 1];
+      }
+#pragma unroll
+    for (int m = 0; m < LY::NY - 1; ++m)
+#pragma unroll
+      for (int h = 0; h < D; ++h) {
+        L.aY[m][h][q] = rowc[CY * c.j + 2 * (m * D + h)];
+        L.sY[m][h][q] = rowc[CY * c.j + 2 * (m * D + h) + 1];
+      }
     if (p.load_state) {
       const R* st = static_cast<const R*>(p.state);
       L.x[q] = st[idx];
@@ -393,7 +433,7 @@ __device__ __forceinline__ void strang_tile(const SolveParams& p, const long lon
       hs[q] = rowc[CY * c.j + HALF + 1];
     }
     const R* last = table + (size_t)(p.n_steps - 1) * Lanes::kRow;
-    L.template step<true>(last, ha, hs, SH == kShearAlt && ((p.n_steps - 1) & 1));
+    L.template step_at<true>(last, p.n_steps - 1, ha, hs);
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
       long long idx = base + (long long)q * blockDim.x;
@@ -999,8 +1039,9 @@ hipError_t launch_snapshot(int scheme, int precision, int elliptic, const SolveP
                            hipStream_t stream) {
   return sliced_launch(p, 256, 1, [&](const SolveParams& ps, unsigned nb) {
     if (base_scheme(scheme) == PD_SCHEME_STRANG) {
-      const bool four = scheme == PD_SCHEME_STRANG4;
-      const int row_stride = four ? 6 : 4, half_offset = four ? 4 : 2;
+      // per row: (stage classes) x (coefficient phases) pairs, then the half-step pair
+      const int classes = scheme == PD_SCHEME_STRANG4 ? 2 : 1;
+      const int half_offset = 2 * classes * coefficient_phases(precision), row_stride = half_offset + 2;
       if (is_fp32(precision)) {
         if (elliptic)
           hipLaunchKernelGGL((strang_snapshot_kernel<float, 1>), dim3(nb), dim3(256), 0, stream, ps, q, half_offset,

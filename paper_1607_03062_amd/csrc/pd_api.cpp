@@ -370,8 +370,8 @@ size_t pd_solve_bytes(pd_grid g, long long n_steps) {
   if (base_scheme(g->scheme) == PD_SCHEME_STRANG) {
     const size_t v = is_fp32(g->precision) ? sizeof(float) : sizeof(double);
     size_t col = align(table);
-    size_t row = align(col + 2 * point_coefficient_pairs_x(g->scheme) * v * (size_t)g->grid.nx);
-    table = align(row + 2 * point_coefficient_pairs_y(g->scheme) * v * (size_t)g->grid.ny);
+    size_t row = align(col + 2 * point_coefficient_pairs_x(g->scheme, g->precision) * v * (size_t)g->grid.nx);
+    table = align(row + 2 * point_coefficient_pairs_y(g->scheme, g->precision) * v * (size_t)g->grid.ny);
   }
   const size_t npts = (size_t)g->grid.points();
   return table + npts * sizeof(double) + (size_t)density_partials((long long)npts) * sizeof(double) +

@@ -103,16 +103,30 @@ void build_step_table(const FieldTables& t, int scheme, int precision, int form,
                       std::vector<unsigned char>* rows);
 // Rotation form of a Strang solve: shears when every rotation angle is small enough.
 int strang_form(const Grid& g, const FieldTables& t);
+// Phases of the per-point rotation coefficients of the FP32 Strang forms.  A
+// coefficient rounded to FP32 changes the rotation angle (and its orthogonality)
+// by a relative error of order 2^-24 that is the same at every step, so over a solve
+// it acts as a constant perturbation of that point's Hamiltonian: the error in n
+// grows with the total rotation angle 2 |p| (t_f - t_i), whatever N.  Each coefficient
+// is therefore stored as kDitherFP32 FP32 values, each its lower or upper FP32
+// neighbour, whose mean is the exact value to within 1/(2 kDitherFP32) of an ulp; step
+// k uses value k mod kDitherFP32.  The per-step error then averages out over each
+// cycle instead of adding up.  FP64 coefficients have one phase.
+constexpr int kDitherFP32 = 4;
+inline int coefficient_phases(int precision) { return is_fp32(precision) ? kDitherFP32 : 1; }
+
 // Per-point rotation coefficients of a Strang solve, which depend on one grid
 // coordinate each: per column i the x rotations by 2 c dt px_i for each distinct
 // stage coefficient (1 pair, or 2 for the fourth-order composition), per row j
 // the y rotations that follow the stages (1 or 2 pairs) and the opening / closing
 // half step (1 pair), in the solve's form and precision, appended to `bytes`
-// (each block 256-byte aligned).  Returns the byte offsets of the two blocks.
+// (each block 256-byte aligned).  Every pair except the half step is stored once
+// per coefficient phase, phase-minor: pair q of phase h at index q * phases + h.
+// Returns the byte offsets of the two blocks.
 void build_point_coefficients(const Grid& g, const FieldTables& t, int scheme, int precision, int form, double vsign,
                               std::vector<unsigned char>* bytes, size_t* col_offset, size_t* row_offset);
-size_t point_coefficient_pairs_x(int scheme);
-size_t point_coefficient_pairs_y(int scheme);  // including the half step
+size_t point_coefficient_pairs_x(int scheme, int precision);  // per column, phases included
+size_t point_coefficient_pairs_y(int scheme, int precision);  // per row, phases and the half step included
 // Coefficients (a, s) of the rotation by phi = 2 * half in a rotation form.
 void rotation_coefficients(double half, int form, double* a, double* s);
 

@@ -1,13 +1,33 @@
 """Serving on the GPU: requests arriving while others run are admitted at epoch
 boundaries as memory frees up, share persistent launches, and each result equals
-the same request solved alone (bit for bit: n(p) and rho)."""
+the same request solved alone (bit for bit: n(p) and rho) and the FP64 oracle
+(Sec. II Eq. (1); Sec. III Eqs. (11)-(13)) on the request's full grid, in its
+own scheme and valley."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_1607_03062_amd import serve
 from paper_1607_03062_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
+
+# parity bars: FP64 1e-12 per point and relative on rho; the FP32 forms 1e-5 per point
+FP64_N_ABS, FP64_RHO_REL, FP32_N_ABS = 1e-12, 1e-12, 1e-5
+VALLEY_SIGN = {"both": 1, "K+": 1, "K-": -1}
+VALLEY_FACTOR = {"both": 4.0, "K+": 2.0, "K-": 2.0}  # spins x valleys counted in rho
+
+
+def check_against_oracle(r, n):
+    """A served request's n(p) and rho against the FP64 oracle on its full grid."""
+    n_o = oracle.solve_grid(r.field, r.grid, r.n_steps, r.scheme, valley=VALLEY_SIGN[r.valley])[0]
+    err = float(np.max(np.abs(n - n_o)))
+    if r.precision == "fp64":
+        rho_o = oracle.density(r.grid, n_o) * VALLEY_FACTOR[r.valley] / 4.0
+        assert err <= FP64_N_ABS and abs(r.rho / rho_o - 1) <= FP64_RHO_REL, (r.name, err, r.rho, rho_o)
+    else:
+        assert err <= FP32_N_ABS, (r.name, r.precision, err)
+    return err
 
 
 @pytest.mark.parametrize("policy", ["lockstep", "srpt"])
@@ -43,6 +63,9 @@ def test_results_in_the_mix_equal_alone(gpu, policy):
         s.close()
         assert r.rho == rho, r.name
         assert np.array_equal(ex.n_results[r.name], n), r.name
+        err = check_against_oracle(r, ex.n_results[r.name])
+        print("served %s (%s %s %s %dx%d N=%d): max|dn| vs oracle %.2e" % (
+            r.name, r.scheme, r.precision, r.valley, r.grid["nx"], r.grid["ny"], r.n_steps, err), flush=True)
     ex.close()
 
 
@@ -83,39 +106,51 @@ def test_reused_handles_equal_fresh_ones(gpu, precision):
         rho = s.density(n_out=n)
         s.close()
         assert r.rho == rho and np.array_equal(ex.n_results[r.name], n), r.name
+        check_against_oracle(r, ex.n_results[r.name])
     ex.close()
 
 
 def test_set_field_waits_for_its_own_work_only(gpu):
-    """A new field on a handle waits for that handle's earlier work, not for the device: a
-    long solve on another stream is still running when the call returns (the new field is
-    shorter, so its table fits the allocation and nothing is freed).  The reused handle's
-    chunked solve then matches a fresh handle bit for bit."""
+    """A new field on a handle waits for that handle's earlier work and not for the device.
+    Checked by event status, not wall time: the handle's own last work (queued behind a long
+    solve on its stream) is complete when the call returns, and the work of another stream,
+    queued just before the call, is not (about 0.8 s of device time against a call that
+    samples a 2000-step field and copies 16 KB).  The new field is shorter, so its table fits
+    the allocation and nothing is freed.  The reused handle's chunked solve then matches a
+    fresh handle bit for bit."""
     import torch
 
-    c3 = wl.config3()
-    long_solve = gpu.Solver.for_grid(c3["grid"], "fp64")
-    long_solve.set_field(c3["field"], c3["n_steps"])
-    small = gpu.Solver.for_grid(wl.config1()["grid"], "fp32")
-    f1 = wl.config1()["field"]
-    small.set_field(f1, 3000)
-    st_small = torch.cuda.Stream()
+    c1, c3 = wl.config1(), wl.config3()
+    long_own, long_other = (gpu.Solver.for_grid(c3["grid"], "fp64") for _ in range(2))  # about 0.1 s per solve
+    long_own.set_field(c3["field"], c3["n_steps"])
+    long_other.set_field(c3["field"], c3["n_steps"])
+    small = gpu.Solver.for_grid(c1["grid"], "fp32")
+    small.set_field(c1["field"], 3000)
+    st_small, st_other = torch.cuda.Stream(), torch.cuda.Stream()
+    long_own.propagate(-1, stream=st_small)  # the small solve's own stream is busy first
     small.propagate(700, stream=st_small)  # chunked: the state buffer is in use
     small.propagate(-1, stream=st_small)
-    small.density(stream=st_small)  # waits for the small solve
-    st_long = torch.cuda.Stream()
-    long_solve.propagate(-1, stream=st_long)  # about 0.1 s of device time
+    own_done = torch.cuda.Event()
+    own_done.record(st_small)
+    other_done = torch.cuda.Event()
+    with torch.cuda.stream(st_other):
+        for _ in range(8):
+            long_other.rewind()
+            long_other.propagate(-1, stream=st_other)
+        other_done.record(st_other)
     small.set_field(wl.sin2(0.15, 0.5, 8), 2000)
-    still_running = not st_long.query()
+    own_complete, other_pending = own_done.query(), not other_done.query()
+    st_other.synchronize()
+    long_own.close()
+    long_other.close()
+    assert own_complete, "pd_set_field returned before the handle's own work was done"
+    assert other_pending, "pd_set_field waited for another stream's work"
     small.propagate(1000, stream=st_small)
     small.propagate(-1, stream=st_small)
     n = np.empty(64 * 64)
     rho = small.density(n_out=n, stream=st_small)
-    st_long.synchronize()
-    long_solve.close()
     small.close()
-    assert still_running
-    fresh = gpu.Solver.for_grid(wl.config1()["grid"], "fp32")
+    fresh = gpu.Solver.for_grid(c1["grid"], "fp32")
     fresh.set_field(wl.sin2(0.15, 0.5, 8), 2000)
     fresh.propagate(1000)
     fresh.propagate(-1)
