@@ -235,6 +235,18 @@ pd_status pd_propagate(pd_grid g, long long max_steps, void* stream);
    rho_out or a host n_out is given the call waits for stream. */
 pd_status pd_density(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+   tight serving loops, harnesses that forbid hipMalloc): pd_density with the
+   reduction's scratch -- the per-tile partial sums and the device-side rho -- in
+   a static device array of the library (1 MiB per device, held until the process
+   ends) instead of the handle's buffers.  Same arguments, result (bit for bit)
+   and waiting as pd_density; the call itself allocates nothing and creates
+   nothing.  Grids of at most 2^28 points (16384 x 16384); larger ones return
+   PD_ERR_INVALID before any device work.  Every call on a device shares that
+   device's scratch, so calls that overlap on one device (on different streams or
+   threads) race; calls ordered on one stream do not. */
+pd_status pd_density_static(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, void* stream);
+
 /* Time-resolved occupation after the steps done so far (0 <= steps_done <= N,
    e.g. between chunked pd_propagate calls): the state is projected on the
    positive-energy eigenvector of the Hamiltonian at the step boundary

@@ -114,6 +114,7 @@ SIGNATURES = [
     ("pd_propagate", ctypes.c_int, [_vp, ctypes.c_longlong, _vp]),
     ("pd_density", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _vp]),
     ("pd_snapshot", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _vp]),
+    ("pd_density_static", ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _vp]),
     ("pd_state_bytes", ctypes.c_size_t, [_vp]),
     ("pd_solve_bytes", ctypes.c_size_t, [_vp, ctypes.c_longlong]),
     ("pd_bind_state", ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
@@ -303,6 +304,15 @@ class Solver:
         rho = ctypes.c_double()
         check(load().pd_density(self._h, ptr, dev, ctypes.byref(rho) if want_rho else None,
                                 stream_handle(stream)), "pd_density")
+        return rho.value if want_rho else None
+
+    def density_static(self, n_out=None, want_rho: bool = True, stream=None):
+        """As density(), through pd_density_static (the reduction's scratch in the
+        library's static device array: the call allocates nothing)."""
+        ptr, dev = (None, 0) if n_out is None else _ptr_of(n_out)
+        rho = ctypes.c_double()
+        check(load().pd_density_static(self._h, ptr, dev, ctypes.byref(rho) if want_rho else None,
+                                       stream_handle(stream)), "pd_density_static")
         return rho.value if want_rho else None
 
     def snapshot(self, n_out=None, want_rho: bool = True, stream=None):

@@ -45,6 +45,8 @@
 // plus the sign vsign of the initial state and of the projection.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "pd_internal.h"
 
 namespace pdx {
@@ -1063,6 +1065,40 @@ hipError_t launch_snapshot(int scheme, int precision, int elliptic, const SolveP
       hipLaunchKernelGGL((midpoint_snapshot_kernel<double>), dim3(nb), dim3(256), 0, stream, ps, q);
     }
   });
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of the no-allocation density (pd_density_static): the tile partials
+// of one reduction, then its sum.  Each device holds its own copy until the process
+// ends; every call on a device shares it.
+
+static_assert(kRedTile * kStaticPartials == kStaticMaxPoints, "static scratch sized for the reduction's tiles");
+static __device__ __align__(256) double scratch[kStaticPartials + 1];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(int device, double** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    // the array's device address, looked up once per device with that device current
+    int prev = -1;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return e;
+    if (prev != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (prev != device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 hipError_t launch_density(const double* n, long long npts, double scale, double* partial, double* rho,

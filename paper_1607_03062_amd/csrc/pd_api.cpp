@@ -498,6 +498,55 @@ pd_status pd_density(pd_grid g, double* n_out, int n_out_on_device, double* rho_
   return reduce_and_copy(g, n_out, n_out_on_device, rho_out, static_cast<hipStream_t>(stream));
 }
 
+pd_status pd_density_static(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, void* stream) {
+  if (!g) return fail(PD_ERR_INVALID, "null handle");
+  const long long npts = g->grid.points();
+  if (npts > kStaticMaxPoints)
+    return fail(PD_ERR_INVALID, "pd_density_static: %lld points exceed the static scratch (at most %lld)", npts,
+                kStaticMaxPoints);
+  if (!g->field_set || g->steps_done != g->field.n_steps)
+    return fail(PD_ERR_STATE, "pd_density_static before the last step (%lld of %lld done)", g->steps_done,
+                g->field_set ? g->field.n_steps : 0LL);
+  DeviceScope scope(g->device);
+  if (!scope.ok) return fail(PD_ERR_DEVICE, "cannot select device %d", g->device);
+  double* sc = nullptr;
+  hipError_t e = static_scratch(g->device, &sc);
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // partials in sc[0 .. tiles), the sum in sc[kStaticPartials]; every partial is
+  // written before it is read, so nothing needs clearing
+  e = launch_density(g->d_n, npts, g->density_scale(), sc, sc + kStaticPartials, s);
+  if (e != hipSuccess) return hip_fail(e, "density launch");
+  bool wait = false;
+  if (n_out) {
+    e = hipMemcpyAsync(n_out, g->d_n, (size_t)npts * sizeof(double),
+                       n_out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "copy of n(p)");
+    wait = !n_out_on_device;
+  }
+  // the handle's completion event exists once a propagation was enqueued outside
+  // capture; otherwise a later pd_set_field waits for the device (creating an event
+  // here could allocate)
+  if (g->last_use) {
+    pd_status m = mark_use(g, s);
+    if (m != PD_OK) return m;
+  } else {
+    g->wait_device = true;
+  }
+  double rho = 0.0;
+  if (rho_out) {
+    e = hipMemcpyAsync(&rho, sc + kStaticPartials, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "copy of rho");
+    wait = true;
+  }
+  if (wait) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  }
+  if (rho_out) *rho_out = rho;
+  return ok();
+}
+
 pd_status pd_snapshot(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, void* stream) {
   if (!g) return fail(PD_ERR_INVALID, "null handle");
   if (!g->field_set) return fail(PD_ERR_STATE, "pd_snapshot before pd_set_field");

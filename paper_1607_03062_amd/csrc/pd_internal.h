@@ -238,6 +238,13 @@ hipError_t launch_snapshot(int scheme, int precision, int elliptic, const SolveP
                            hipStream_t stream);
 hipError_t launch_density(const double* n, long long npts, double scale, double* partial, double* rho,
                           hipStream_t stream);
+// Largest grid the static scratch of pd_density_static serves, and the tile
+// partials it holds for it (the density reduction sums tiles of 2048 points).
+constexpr long long kStaticMaxPoints = 1LL << 28;
+constexpr long long kStaticPartials = kStaticMaxPoints / 2048;
+// Device address of the static scratch on `device` (kStaticPartials partials, then
+// one sum), looked up on the first call for that device.
+hipError_t static_scratch(int device, double** out);
 hipError_t launch_batch(int points_per_lane, int block_threads, int grid_blocks, const BatchSolve* solves,
                         const BatchItem* items, int n_items, unsigned int* counter, hipStream_t stream);
 hipError_t launch_batch_density(const DensityJob* jobs, int n_jobs, long long total_tiles, hipStream_t stream);

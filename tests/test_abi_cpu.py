@@ -99,8 +99,24 @@ def test_null_handles():
     lib = pd.require_native()
     assert lib.pd_propagate(None, -1, None) == _lib.PD_ERR_INVALID
     assert lib.pd_density(None, None, 0, None, None) == _lib.PD_ERR_INVALID
+    assert lib.pd_density_static(None, None, 0, None, None) == _lib.PD_ERR_INVALID
     assert lib.pd_state_bytes(None) == 0
     lib.pd_destroy_grid(None)
+
+
+def test_static_density_rejects_grids_above_its_scratch():
+    """pd_density_static serves grids of at most 2^28 points; a larger one is refused before
+    any device work (the handle has no field and no device)."""
+    big = pd.Solver(32768, 16384, (-1.0, 1.0), (-1.0, 1.0), "fp32")  # 2^29 points
+    with pytest.raises(pd.PDError) as e:
+        big.density_static()
+    assert e.value.status == _lib.PD_ERR_INVALID and "static scratch" in e.value.message
+    big.close()
+    ok = pd.Solver(16384, 16384, (-1.0, 1.0), (-1.0, 1.0), "fp32")  # 2^28 points: size accepted, no field yet
+    with pytest.raises(pd.PDError) as e:
+        ok.density_static()
+    assert e.value.status == _lib.PD_ERR_STATE
+    ok.close()
 
 
 @pytest.mark.parametrize("kind", ["sin2", "constant", "pulse"])
