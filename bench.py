@@ -1,4 +1,5 @@
-"""Benchmark: momentum point-steps/s of one full solve on one MI355X.
+"""Benchmark: momentum point-steps/s on one MI355X, FP32 and FP64 forms, with the
+n(p) error against the FP64 CPU oracle, batch throughput, and serving latency.
 
 A step is one whole solve of the precision-form workload: the 2048 x 2048
 momentum grid on [-2,2]^2 under the sin^2 pulse (E0 = 0.1, omega = 0.5, 30
@@ -10,7 +11,18 @@ same workload are timed beside it, and all are checked against the FP64 CPU
 oracle on the 64 x 64 subsample (stride 32) and on the larger sample whose
 oracle run is also the CPU baseline.
 
-    python bench.py [--steps K] [--warmup W] [--precision fp32|fp64]
+The same JSON line carries two more objects (skip them with --no-batch / --no-serve):
+  batch  the 64 seeded solves of the batch workload (grids 256^2..2048^2 on [-4,4]^2,
+         5k-80k steps, FP32 form) in one persistent graph-captured launch per pass,
+         autotuned, with its own roofline and the oracle on every member's 64 x 64
+         subsample (error and CPU baseline);
+  serve  a Poisson stream of solve requests (batch-workload distributions, half FP32
+         and half FP64) served by continuous batching at 0.7 of the capacity measured
+         in the same run: p50 / p99 / mean latency and sustained point-steps/s.
+
+    python bench.py [--steps K] [--warmup W] [--precision fp32|fp64] [--no-batch] [--no-serve]
+    python bench.py --workload batch|serve ...       (one of the two objects as its own line)
+    python bench.py --summarize-profile DIR [...]    (text summary of rocprofv3 output)
 """
 from __future__ import annotations
 
@@ -26,15 +38,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "momentum point-steps/s (FP32 vs FP64 form) at stated n(p) error; p50/p99 solve ms"
 
-# Algorithmic work per point-step of the propagation kernel: three plane
-# rotations of the Bloch vector per Strang step.
-#   shear form (every rotation angle <= pi/2): 3 FMA per rotation -> 9 FMA = 18 flop, 9 VALU instructions
-#     FP32 form: each component rounded once per rotation, 3 FMA + 1 add -> 21 flop, 12 instructions
-#     (fp32fast: plain shears of alternating orientation, 18 flop, 9 instructions)
-#   versine form, FP64: 2 FMA per rotated component -> 12 FMA = 24 flop, 12 instructions
-#   versine form, FP32: mul + fma + add per rotated component -> 24 flop, 18 instructions
-ALGO = {(0, "fp64"): (18, 9), (0, "fp32"): (21, 12), (0, "fp32fast"): (18, 9),
-        (1, "fp64"): (24, 12), (1, "fp32"): (24, 18), (1, "fp32fast"): (24, 18)}
+# Work per point-step of the Strang propagation kernel: three plane rotations of the
+# Bloch vector per step.  The method's own (algorithmic) work is what a rotation
+# needs; the FP32 form executes more for accuracy: each component is rounded once per
+# rotation, which costs one add per rotation beyond the three shears.
+#   shear form (every rotation angle <= pi/2): 3 FMA per rotation -> 9 FMA = 18 flop
+#     executed: FP64 and fp32fast 18 flop / 9 VALU instructions; FP32 21 flop / 12
+#   versine form: 2 FMA per rotated component -> 12 FMA = 24 flop
+#     executed: FP64 24 flop / 12 instructions; FP32 (mul + fma + add per component) 24 / 18
+# (rotation form, precision) -> (algorithmic flop, executed flop, executed VALU instructions)
+ALGO = {(0, "fp64"): (18, 18, 9), (0, "fp32"): (18, 21, 12), (0, "fp32fast"): (18, 18, 9),
+        (1, "fp64"): (24, 24, 12), (1, "fp32"): (24, 24, 18), (1, "fp32fast"): (24, 24, 18)}
 
 
 def host_cpu_model() -> str:
@@ -47,8 +61,8 @@ def host_cpu_model() -> str:
 
 
 def algo(info: dict, precision: str):
-    """(flop, VALU instructions) per point-step of the solve described by pd_info; a
-    fourth-order step is `stages` = 5 second-order stages.
+    """(algorithmic flop, executed flop, VALU instructions) per point-step of the solve
+    described by pd_info; a fourth-order step is `stages` = 5 second-order stages.
     Strang stage: three rotations (ALGO), a fourth one (the field part of the y
     rotation) when the field has a y component.
     Midpoint stage, phase X = c dt(px + A) (1 add, FP64) and x = X^2 + Y^2 (1 fma):
@@ -58,12 +72,14 @@ def algo(info: dict, precision: str):
       cosine form (rotation_form 1), order J: cos - 1 (J - 1 fma + 1 mul) and sin(x)/x
       (J fma), alpha, beta (2 mul), the update: FP64 3 fma per component (24 flop, 12
       instr), FP32 mul + 2 fma + add per component (24 flop, 16 instr) plus 3 conversions.
-    A y component adds Y = Y0 + dy and Y^2 (2 flop; 2 instr, 3 in FP32 tangent form)."""
+    A y component adds Y = Y0 + dy and Y^2 (2 flop; 2 instr, 3 in FP32 tangent form).
+    Every midpoint operation is part of the method's step: algorithmic = executed."""
     stages = info.get("stages", 1) or 1
     ell = info.get("elliptic", 0)
     if info["scheme"] in (0, 2):
-        f, i = ALGO[(info["rotation_form"], precision)]
-        return stages * f * (4 if ell else 3) // 3, stages * i * (4 if ell else 3) // 3
+        fa, fe, i = ALGO[(info["rotation_form"], precision)]
+        r = 4 if ell else 3
+        return stages * fa * r // 3, stages * fe * r // 3, stages * i * r // 3
     J = info["taylor_order"]
     f32 = precision != "fp64"  # fp32fast runs as fp32
     if info["rotation_form"] == 0:
@@ -72,7 +88,9 @@ def algo(info: dict, precision: str):
     else:
         flops = 3 + (2 * (J - 1) + 1) + 2 * J + 2 + 24 + (2 if ell else 0)
         instr = 2 + 2 * J + 2 + (16 + 3 if f32 else 12) + (2 if ell else 0)
-    return stages * flops, stages * instr
+    return stages * flops, stages * flops, stages * instr
+
+
 # MI355X vector peaks from its unit counts and clock (256 CU, 2.4 GHz): FP64
 # issues 64 lanes per clock per CU (78.6 TFLOP/s with FMA); unpacked FP32 with
 # VGPR operands issues 128 lanes per clock per CU (157.3 TFLOP/s with FMA).
@@ -156,13 +174,16 @@ def time_form(pd, torch, c, precision, steps, warmup, ppl, block, stage=0, chunk
             "n_to_host_ms": copy_s[-1] * 1e3}
 
 
-def run_batch(args):
-    """Config 4: 64 seeded solves of uneven grid sizes and step counts, FP32 form, in one
-    persistent graph-captured launch per pass (a step = one pass over all 64 solves)."""
-    import numpy as np
-    import torch
+def log(msg: str):
+    """Progress line on stderr (the JSON line alone goes to stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
-    import paper_1607_03062_amd as pd
+
+def batch_object(args, pd, torch, np):
+    """The 64 seeded batch-workload solves, FP32 form, one persistent graph-captured launch
+    per pass (a pass = every member's whole solve), autotuned; device time from HIP events
+    on the launch stream; every member checked against the oracle on its own 64 x 64
+    subsample, which is also the CPU baseline."""
     from paper_1607_03062_amd import workloads as wl
 
     cfgs = wl.config4(count=args.batch_count)
@@ -172,19 +193,21 @@ def run_batch(args):
         s.set_field(c["field"], c["n_steps"])
         solvers.append(s)
     total = float(sum(c["grid"]["nx"] * c["grid"]["ny"] * c["n_steps"] for c in cfgs))
+    forms = {s.info()["rotation_form"] for s in solvers}
     st = torch.cuda.Stream()
     b = pd.Batch(solvers)
     t_tune = time.perf_counter()
     if not args.no_autotune:
         b.autotune(512, stream=st)
     t_tune = time.perf_counter() - t_tune
-    for _ in range(args.warmup):
+    for _ in range(args.batch_warmup):
         b.run(stream=st)
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    passes = args.batch_passes
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(passes)]
     wall = []
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(passes):
         w0 = time.perf_counter()
         ev[i][0].record(st)
         rho = b.run(stream=st)
@@ -194,47 +217,73 @@ def run_batch(args):
     t = time.perf_counter() - t0
     dev_ms = float(np.mean([a.elapsed_time(c) for a, c in ev]))
     info = b.info()
+    log("batch: %d passes, %.1f ms device time per pass" % (passes, dev_ms))
     # the same solves one after another, each alone with its default launch
     t1 = time.perf_counter()
     rho_alone = []
-    for s in solvers:
+    n_gpu = []
+    for s, c in zip(solvers, cfgs):
         s.rewind()
         s.propagate(-1, stream=st)
-        rho_alone.append(s.density(stream=st))
+        n = np.empty(c["grid"]["nx"] * c["grid"]["ny"])
+        rho_alone.append(s.density(n_out=n, stream=st))
+        n_gpu.append(n[wl.subsample_indices(c["grid"]["nx"], 64)])
     t_seq = time.perf_counter() - t1
     same = bool(np.array_equal(np.array(rho_alone), rho))
     b.close()
     for s in solvers:
         s.close()
-    flops = ALGO[(0, "fp32")][0] * total  # every config-4 solve takes the shear form (checked by the tests)
-    line = {
-        "metric": METRIC, "value": total * args.steps / t, "unit": "point-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "%d seeded solves (grids 256^2..2048^2 on [-4,4]^2, 8k-78k steps), FP32 form, "
-                               "one persistent graph-captured launch per pass" % len(cfgs),
-                   "solves": len(cfgs), "point_steps_per_pass": total, "points_per_lane": info["points_per_lane"],
-                   "block_threads": info["block_threads"], "work_items": info["work_items"]},
-        "graph_captured": info["graph_captured"], "device_ms_per_pass": dev_ms,
+    algo_flop, exec_flop, instr = ALGO[(0, "fp32")]
+    achieved = algo_flop * total / (dev_ms * 1e-3) / 1e12
+    out = {
+        "workload": "%d seeded solves (grids 256^2..2048^2 on [-4,4]^2, 5k-80k steps, sin^2 pulses E0 in "
+                    "[0.05,0.5], omega in [0.1,1], 4-40 cycles), FP32 form, one persistent graph-captured "
+                    "launch per pass" % len(cfgs),
+        "solves": len(cfgs), "passes": passes, "warmup": args.batch_warmup, "point_steps_per_pass": total,
+        "ms_per_pass": t / passes * 1e3, "device_ms_per_pass": dev_ms, "value": total * passes / t,
+        "unit": "point-steps/s", "graph_captured": info["graph_captured"],
+        "points_per_lane": info["points_per_lane"], "block_threads": info["block_threads"],
+        "work_items": info["work_items"], "autotune_s": t_tune,
         "p50_ms": float(np.percentile(np.array(wall) * 1e3, 50)),
         "p99_ms": float(np.percentile(np.array(wall) * 1e3, 99)),
-        "autotune_s": t_tune,
         "sequential_alone": {"value": total / t_seq, "ms": t_seq * 1e3, "rho_bitwise_equal_to_batch": same},
-        "roofline": {"bound": "alu", "achieved": flops / (dev_ms * 1e-3) / 1e12, "peak": PEAK_TFLOPS["fp32"],
-                     "unit": "TFLOP/s", "frac": flops / (dev_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
-                     "traffic": None},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS["fp32"], "traffic": None,
+                     "flop_per_point_step": algo_flop, "executed_flop_per_point_step": exec_flop,
+                     "valu_issue_frac": instr * total / (dev_ms * 1e-3) / (CU_CLOCKS_PER_S * LANES_PER_CLK["fp32"]),
+                     "rotation_forms": sorted(forms)},
         "cpu_baseline": None,
     }
-    print(json.dumps(line), flush=True)
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        worst, worst_name, pts = 0.0, None, 0.0
+        t0 = time.perf_counter()
+        for q, c in enumerate(cfgs):
+            idx = wl.subsample_indices(c["grid"]["nx"], 64)
+            n_o = oracle.solve_grid(c["field"], c["grid"], c["n_steps"], idx=idx, threads=threads)[0]
+            pts += idx.shape[0] * c["n_steps"]
+            err = float(np.max(np.abs(n_gpu[q] - n_o)))
+            if err > worst:
+                worst, worst_name = err, c["name"]
+            if q % 16 == 15:
+                log("batch oracle: %d of %d members, worst %.2e" % (q + 1, len(cfgs), worst))
+        t_cpu = time.perf_counter() - t0
+        out["n_error_max_abs"] = worst
+        out["n_error_worst_member"] = worst_name
+        out["n_error_sample"] = "each member's 64x64 subsample vs the FP64 oracle"
+        out["cpu_baseline"] = {"value": pts / t_cpu, "unit": "point-steps/s", "cores": threads, "kind": "oracle",
+                               "cpu_model": host_cpu_model(),
+                               "sample": "64x64 subsample of each of the %d members, %.3g FP64 Strang point-steps, "
+                                         "%.1f s" % (len(cfgs), pts, t_cpu)}
+    return out
 
 
-def run_serve(args):
-    """Config 5: a Poisson stream of solve requests (config-4 distributions, 50/50 FP32 /
-    FP64) served by continuous batching; arrival rate 0.7 x the measured capacity."""
-    import numpy as np
-    import torch
-
-    import paper_1607_03062_amd as pd
+def serve_object(args, pd, torch, np):
+    """The serving workload: a Poisson stream of solve requests (batch-workload distributions,
+    50/50 FP32/FP64) served by continuous batching; arrival rate 0.7 x the capacity measured
+    in the same run on a closed set of requests present at t = 0."""
     from paper_1607_03062_amd import serve
     from paper_1607_03062_amd import workloads as wl
 
@@ -243,7 +292,7 @@ def run_serve(args):
     kw = dict(epoch_steps=args.epoch_steps, policy=args.policy, epoch_ms=args.epoch_ms)
     # untimed warm-up passes (another draw of 16 requests): the first launches load the
     # code object and instantiate the batch graph, the first allocations map memory
-    for i in range(args.warmup):
+    for i in range(args.serve_warmup):
         warm = [serve.Request.from_workload(w) for w in wl.config5(count=16, seed=54 + 100 * i, rate_per_s=1e9)]
         ex = serve.GpuExecutor(pd, stream=st)
         serve.Server(ex, budget, **kw).run(warm)
@@ -257,38 +306,82 @@ def run_serve(args):
     mean_ps = float(np.mean([r.point_steps for r in cap_reqs]))
     capacity_rps = cap.point_steps_per_s / mean_ps
     rate = args.rate_per_s if args.rate_per_s else args.load * capacity_rps
+    log("serve: capacity %.1f requests/s (%.3g point-steps/s); stream of %d requests at %.1f/s" % (
+        capacity_rps, cap.point_steps_per_s, args.requests, rate, ))
     reqs = [serve.Request.from_workload(w) for w in wl.config5(count=args.requests, seed=5, rate_per_s=rate)]
     ex = serve.GpuExecutor(pd, stream=st)
-    res = serve.Server(ex, budget, **kw).run(reqs)
+    res = serve.Server(ex, budget, **kw).run(
+        reqs, progress=lambda done, n, now: log("serve: %d of %d requests done at %.0f s" % (done, n, now)))
     reused = ex.reused
     ex.close()
-    line = {
-        "metric": METRIC, "value": res.point_steps_per_s, "unit": "point-steps/s", "n_gpus": 1,
-        "steps": res.completed, "warmup": args.warmup, "ms_per_step": res.makespan_s / max(res.completed, 1) * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "Poisson stream of %d solve requests (config-4 distributions, 50/50 FP32/FP64), "
-                               "rate %.1f req/s = %.2f x capacity, HBM budget %.0f GiB, %s epochs (%d steps / %.1f ms)" % (
-                                   args.requests, rate, rate / capacity_rps, args.budget_gb, args.policy, args.epoch_steps,
-                                   args.epoch_ms),
-                   "requests": args.requests, "rate_per_s": rate, "budget_bytes": budget,
-                   "epoch_steps": args.epoch_steps, "policy": args.policy, "epoch_ms": args.epoch_ms},
-        "p50_ms": res.p50_ms, "p99_ms": res.p99_ms, "mean_ms": res.mean_ms,
-        "serve": dict(res.as_dict(), handles_reused=reused),
+    return {
+        "workload": "Poisson stream of %d solve requests (batch-workload grid, field and step distributions, "
+                    "50/50 FP32/FP64), rate %.1f req/s = %.2f x capacity, HBM budget %.0f GiB, %s epochs "
+                    "(%d steps / %.1f ms)" % (args.requests, rate, rate / capacity_rps, args.budget_gb, args.policy,
+                                              args.epoch_steps, args.epoch_ms),
+        "requests": args.requests, "rate_per_s": rate, "load": rate / capacity_rps, "value": res.point_steps_per_s,
+        "unit": "point-steps/s", "p50_ms": res.p50_ms, "p99_ms": res.p99_ms, "mean_ms": res.mean_ms,
+        "completed": res.completed, "rejected": res.rejected, "makespan_s": res.makespan_s, "epochs": res.epochs,
+        "mean_active": res.mean_active, "peak_bytes": res.peak_bytes, "budget_bytes": res.budget_bytes,
+        "handles_reused": reused, "policy": args.policy, "epoch_ms": args.epoch_ms, "epoch_steps": args.epoch_steps,
         "capacity": {"requests_per_s": capacity_rps, "point_steps_per_s": cap.point_steps_per_s,
-                     "requests": args.capacity_requests},
-        "roofline": None, "cpu_baseline": None,
+                     "requests": args.capacity_requests, "makespan_s": cap.makespan_s},
     }
-    print(json.dumps(line), flush=True)
+
+
+def summarize_profile(args):
+    """Text summary of rocprofv3 CSV output: per-kernel calls and durations from a
+    --kernel-trace --stats run, and FETCH_SIZE / WRITE_SIZE per dispatch of the
+    propagation kernel from two --pmc runs, scaled by what the counters read for a
+    plain device copy of known size (--calibrate-copy) in the same runs."""
+    import csv
+    import glob
+
+    import numpy as np
+
+    def rows(d, name):
+        out = []
+        for f in sorted(glob.glob(os.path.join(d, "**", "*" + name), recursive=True)):
+            with open(f) as fh:
+                out.extend(csv.DictReader(fh))
+        return out
+
+    lines = ["kernel_code_sha256_16: %s" % kernel_hash()]
+    stats = rows(args.summarize_profile, "kernel_stats.csv")
+    if stats:
+        lines.append("%-100s %6s %14s %14s %14s %14s" % ("kernel", "calls", "total_ns", "average_ns", "min_ns",
+                                                         "max_ns"))
+        for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+            lines.append("%-100s %6s %14s %14.0f %14s %14s" % (r["Name"][:100], r["Calls"], r["TotalDurationNs"],
+                                                               float(r["AverageNs"]), r["MinNs"], r["MaxNs"]))
+    for counter, d in (("FETCH_SIZE", args.fetch_dir), ("WRITE_SIZE", args.write_dir)):
+        if not d:
+            continue
+        per_kernel = {}
+        for r in rows(d, "counter_collection.csv"):
+            if r.get("Counter_Name") != counter:
+                continue
+            per_kernel.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        for k, v in sorted(per_kernel.items()):
+            lines.append("%s %s KiB per dispatch (mean of %d): %.3f" % (k[:100], counter, len(v), float(np.mean(v))))
+    print("\n".join(lines))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["cfg3", "batch", "serve"], default="cfg3")
+    ap.add_argument("--workload", choices=["cfg3", "batch", "serve"], default="cfg3",
+                    help="cfg3 (default): the 2048^2 line with the batch and serve objects; batch / serve: one "
+                         "of the objects alone")
+    ap.add_argument("--no-batch", action="store_true", help="leave the batch object out of the cfg3 line")
+    ap.add_argument("--no-serve", action="store_true", help="leave the serve object out of the cfg3 line")
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-passes", type=int, default=3)
+    ap.add_argument("--batch-warmup", type=int, default=1)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--requests", type=int, default=1000)
+    ap.add_argument("--requests", type=int, default=10000)
     ap.add_argument("--capacity-requests", type=int, default=48)
+    ap.add_argument("--serve-warmup", type=int, default=2)
     ap.add_argument("--load", type=float, default=0.7)
     ap.add_argument("--budget-gb", type=float, default=16.0)
     ap.add_argument("--epoch-steps", type=int, default=2048)
@@ -316,7 +409,14 @@ def main():
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (for counter calibration)")
+    ap.add_argument("--summarize-profile", default="",
+                    help="print a summary of the rocprofv3 --kernel-trace --stats output under this directory "
+                         "and exit (no GPU work)")
+    ap.add_argument("--fetch-dir", default="", help="with --summarize-profile: output of a --pmc FETCH_SIZE run")
+    ap.add_argument("--write-dir", default="", help="with --summarize-profile: output of a --pmc WRITE_SIZE run")
     args = ap.parse_args()
+    if args.summarize_profile:
+        return summarize_profile(args)
     if args.gpus != 1:
         print("bench.py: the benchmark runs on one GPU only (a solve would shard over bands of momentum "
               "rows, one reduction of rho; not implemented here). Use --gpus 1.", file=sys.stderr)
@@ -331,9 +431,11 @@ def main():
     pd.require_native()
     torch.cuda.set_device(0)
     if args.workload == "batch":
-        return run_batch(args)
+        print(json.dumps(dict(batch_object(args, pd, torch, np), metric=METRIC, n_gpus=1)), flush=True)
+        return
     if args.workload == "serve":
-        return run_serve(args)
+        print(json.dumps(dict(serve_object(args, pd, torch, np), metric=METRIC, n_gpus=1)), flush=True)
+        return
     c = wl.config3(n=args.grid, precision=args.precision)
     if args.ellipticity:
         c["field"]["ellipticity"] = args.ellipticity
@@ -350,20 +452,23 @@ def main():
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
-        print("copy calibration: %d bytes read, %d bytes written" % (nb, nb), file=sys.stderr)
+        log("copy calibration: %d bytes read, %d bytes written" % (nb, nb))
 
     sch = args.scheme
     main_form = time_form(pd, torch, c, args.precision, args.steps, args.warmup, args.ppl, args.block,
                           args.table_stage, args.chunk_steps, scheme=sch)
+    log("%s form: %.2f ms per solve" % (args.precision, main_form["t_total"] / args.steps * 1e3))
     other = None
     if not args.no_fp64_form and args.precision != "fp64":
         c64 = dict(c, field=dict(c["field"]), precision="fp64")
         other = time_form(pd, torch, c64, "fp64", args.steps, args.warmup, args.ppl, args.block, args.table_stage,
                           args.chunk_steps, scheme=sch)
+        log("fp64 form: %.2f ms per solve" % (other["t_total"] / args.steps * 1e3))
     fast = None
     if not args.no_fast_form and args.precision == "fp32" and sch.startswith("strang"):
         fast = time_form(pd, torch, dict(c, field=dict(c["field"])), "fp32fast", args.steps, args.warmup, args.ppl,
                          args.block, args.table_stage, args.chunk_steps, scheme=sch)
+        log("fp32fast form: %.2f ms per solve" % (fast["t_total"] / args.steps * 1e3))
 
     # oracle on the 64 x 64 subsample: n(p) error of each form and the CPU baseline
     n_err = {}
@@ -377,6 +482,7 @@ def main():
         t0 = time.perf_counter()
         n_o = oracle.solve_grid(c["field"], c["grid"], c["n_steps"], sch, idx=idx, threads=threads)[0]
         t_cpu = time.perf_counter() - t0
+        log("oracle: %dx%d subsample in %.1f s" % (sub, sub, t_cpu))
         cpu = {"value": idx.shape[0] * c["n_steps"] / t_cpu, "unit": "point-steps/s", "cores": threads,
                "kind": "oracle", "cpu_model": host_cpu_model(),
                "sample": "%dx%d subsample (stride %d) of the %d^2 grid, %d FP64 %s steps, %.1f s" % (
@@ -395,8 +501,8 @@ def main():
     t = main_form["t_total"]
     value = ps_per_solve * K / t
     kern_ms = float(np.mean(main_form["kernel_ms"]))
-    flops, instr = algo(main_form["info"], args.precision)
-    achieved = flops * ps_per_solve / (kern_ms * 1e-3) / 1e12
+    flop_a, flop_e, instr = algo(main_form["info"], args.precision)
+    achieved = flop_a * ps_per_solve / (kern_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     wall_ms = np.array(main_form["wall"]) * 1e3
     line = {
@@ -435,32 +541,40 @@ def main():
         "kernel_ms": kern_ms,
         "n_to_host_ms": main_form["n_to_host_ms"],
         "value_with_n_to_host": ps_per_solve / (t / K + main_form["n_to_host_ms"] * 1e-3),
+        # achieved and frac count the method's own work per point-step (flop_per_point_step);
+        # the FP32 form's accuracy adds are reported as executed work beside it
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      "traffic": traffic_from_profile(args.precision) if (sch == "strang" and not args.ellipticity)
                      else None,
+                     "flop_per_point_step": flop_a, "executed_flop_per_point_step": flop_e,
+                     "executed_tflops": flop_e * ps_per_solve / (kern_ms * 1e-3) / 1e12,
                      "valu_issue_frac": instr * ps_per_solve / (kern_ms * 1e-3) / (
                          CU_CLOCKS_PER_S * LANES_PER_CLK[args.precision])},
         "cpu_baseline": cpu,
     }
     if other is not None:
         okm = float(np.mean(other["kernel_ms"]))
-        f64, i64 = algo(other["info"], "fp64")
+        fa64, fe64, i64 = algo(other["info"], "fp64")
         line["fp64_form"] = {
             "value": ps_per_solve * K / other["t_total"], "ms_per_step": other["t_total"] / K * 1e3,
             "kernel_ms": okm, "n_error_max_abs": n_err.get("fp64"), "rho": other["rho"],
             "rho_rel_diff_fp32_vs_fp64": main_form["rho"] / other["rho"] - 1,
-            "roofline_frac": f64 * ps_per_solve / (okm * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],
+            "roofline_frac": fa64 * ps_per_solve / (okm * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],
             "valu_issue_frac": i64 * ps_per_solve / (okm * 1e-3) / (CU_CLOCKS_PER_S * LANES_PER_CLK["fp64"])}
     if fast is not None:
         fkm = float(np.mean(fast["kernel_ms"]))
-        ff, fi = algo(fast["info"], "fp32fast")
+        faf, fef, fi = algo(fast["info"], "fp32fast")
         line["fp32_fast_form"] = {
             "value": ps_per_solve * K / fast["t_total"], "ms_per_step": fast["t_total"] / K * 1e3,
             "kernel_ms": fkm, "n_error_max_abs": n_err.get("fast_64"),
             "n_error_max_abs_cpu_sample": n_err.get("fast"), "rho": fast["rho"],
-            "roofline_frac": ff * ps_per_solve / (fkm * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
+            "roofline_frac": faf * ps_per_solve / (fkm * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
             "valu_issue_frac": fi * ps_per_solve / (fkm * 1e-3) / (CU_CLOCKS_PER_S * LANES_PER_CLK["fp32"])}
+    if not args.no_batch:
+        line["batch"] = batch_object(args, pd, torch, np)
+    if not args.no_serve:
+        line["serve"] = serve_object(args, pd, torch, np)
     print(json.dumps(line), flush=True)
 
 

@@ -4,7 +4,7 @@ Requests (a grid, a field, a step count, a precision, a scheme and a valley)
 arrive over time.  The server keeps a set of active solves on the device and runs
 them in epochs: each epoch advances active solves in one batched launch sequence
 (pd_batch_step_each: one persistent kernel for the second-order Strang solves of
-fields along x, the others' own launches after it), with every solve's state
+fields along x, the others' own launches beside it), with every solve's state
 resident in device memory between epochs.  Solves that reach their last step are
 projected and reduced in the same epoch and leave the set (their handles are kept
 for later requests of the same shape, within the memory budget); arrivals are admitted
@@ -387,10 +387,13 @@ class Server:
     def _now(self, t0, simulated):
         return self.ex.clock if simulated else time.perf_counter() - t0
 
-    def run(self, requests, simulated: bool = False) -> ServeStats:
+    def run(self, requests, simulated: bool = False, progress=None, progress_every: int = 1000) -> ServeStats:
         """Serve the requests (arrival times in seconds from the start).  With
-        simulated=True the clock is the executor's device-time model (FakeExecutor)."""
+        simulated=True the clock is the executor's device-time model (FakeExecutor).
+        progress(completed, total, now_s), if given, is called after every
+        progress_every completions."""
         reqs = sorted(requests, key=lambda r: r.arrival_s)
+        finished = 0
         pending = collections.deque(reqs)
         waiting = collections.deque()  # arrived, not yet admitted
         t0 = time.perf_counter()
@@ -459,6 +462,9 @@ class Server:
                 r.rho, r.done_s, r.status = rho, now, "done"
                 self.in_use -= r.bytes
                 self.ex.release(name)
+                finished += 1
+                if progress is not None and finished % progress_every == 0:
+                    progress(finished, len(reqs), now)
         end = self._now(t0, simulated)
         done = [r for r in reqs if r.status == "done"]
         lat = np.array([r.latency_s for r in done]) * 1e3 if done else np.zeros(1)
