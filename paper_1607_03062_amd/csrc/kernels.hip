@@ -621,6 +621,27 @@ __device__ __forceinline__ constexpr int mcls(int j) {
   return NS == 5 && j == 2 ? 1 : 0;
 }
 
+// Point q of a lane of the midpoint kernel: the lane owns column i of the band of
+// PPL consecutive rows band * PPL .. band * PPL + PPL - 1, so all its points share
+// p_x and with it the FP64 phase c dt (p_x + A_k) of every step (and its FP32
+// rounding), computed once per lane.  Consecutive lanes take consecutive columns,
+// so loads and stores stay coalesced.  Rows past the last one recompute a valid
+// point (the last row) and store nothing.
+struct BandPoint {
+  long long idx;
+  bool valid;
+};
+
+__device__ __forceinline__ BandPoint band_point(const SolveParams& p, long long band, int i, int ppl, int q) {
+  const long long ny = p.npts / p.nx;
+  long long j = band * ppl + q;
+  BandPoint b;
+  b.valid = j < ny;
+  if (!b.valid) j = ny - 1;
+  b.idx = j * p.nx + i;
+  return b;
+}
+
 // TAN: the tangent form (U / cos(theta), one series); otherwise the cosine form.
 template <typename R, int J, int PPL, int NS, int POL, int TAN>
 __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
@@ -628,18 +649,25 @@ __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
   constexpr int W = NS * (1 + POL);    // table values per step
   constexpr bool kRenorm = sizeof(R) == 4 || TAN;  // renormalise every kRenormEvery steps
   constexpr int kUnroll = NS == 1 ? 4 : 1;
-  const long long base = p.first + (long long)blockIdx.x * blockDim.x * PPL + threadIdx.x;
+  // p.first counts lanes here: lane -> (band of rows, column)
+  long long lane = p.first + (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long bands = (p.npts / p.nx + PPL - 1) / PPL;
+  if (lane >= bands * p.nx) lane = bands * p.nx - 1;  // tail lanes recompute a valid lane's points
+  const long long band = lane / p.nx;
+  const int col = (int)(lane - band * p.nx);
+  const bool lane_valid = p.first + (long long)blockIdx.x * blockDim.x + threadIdx.x < bands * p.nx;
+  const double px = p.px_min + (double)col * p.dx;
   R a1[PPL], b1[PPL], a2[PPL], b2[PPL];
-  double X0[NC][PPL], Y0[NC][PPL], Y2[NC][PPL];
+  double X0[NC], Y0[NC][PPL], Y2[NC][PPL];
+#pragma unroll
+  for (int m = 0; m < NC; ++m) X0[m] = p.hx[m] * px;  // vsign c dt px, shared by the lane's points
 #pragma unroll
   for (int q = 0; q < PPL; ++q) {
-    long long idx = base + (long long)q * blockDim.x;
-    if (idx >= p.npts) idx = p.npts - 1;
-    PointCoords c = coords(p, idx);
+    const long long idx = band_point(p, band, col, PPL, q).idx;
+    const double py = p.py_min + (double)(idx / p.nx) * p.dy;
 #pragma unroll
     for (int m = 0; m < NC; ++m) {
-      X0[m][q] = p.hx[m] * c.px;  // vsign c dt px
-      Y0[m][q] = p.hx[m] * c.py;
+      Y0[m][q] = p.hx[m] * py;
       Y2[m][q] = Y0[m][q] * Y0[m][q];
     }
     if (p.load_state) {
@@ -651,7 +679,7 @@ __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
     } else {
       // v_in = (-Px + i Py, E) / (sqrt(2) E) (Sec. II, Eq. (3), unit norm); the K-
       // spinor of Eq. (4) is the same with P -> -P
-      double Px = p.vsign * (c.px + p.A_in), Py = p.vsign * (c.py + p.Ay_in);
+      double Px = p.vsign * (px + p.A_in), Py = p.vsign * (py + p.Ay_in);
       double E = sqrt(Px * Px + Py * Py);
       double d = 1.4142135623730951 * E;
       bool ok = E > 0.0;
@@ -676,14 +704,15 @@ __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
       for (int j = 0; j < NS; ++j) {
         const double d = row[j];
         const double dy = POL ? row[NS + j] : 0.0;
+        const double X = X0[mcls<NS>(j)] + d;  // vsign c dt (px + A_x), FP64 in both forms, once per lane
+        const float Xs = (float)X;              // its FP32 rounding (FP32 tangent form)
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
-          double X = X0[mcls<NS>(j)][q] + d;  // vsign c dt (px + A_x), FP64 in both forms
           double Y = POL ? Y0[mcls<NS>(j)][q] + dy : Y0[mcls<NS>(j)][q];
           if constexpr (TAN && sizeof(R) == 4) {
             // the series is evaluated in FP32, so (c dt E)^2 is formed from the rounded
             // phases (a relative error of the size of the coefficient's own rounding)
-            float Xr = (float)X, Yr = (float)Y;
+            float Xr = Xs, Yr = (float)Y;
             float x = POL ? fmaf(Xr, Xr, Yr * Yr) : fmaf(Xr, Xr, (float)Y2[mcls<NS>(j)][q]);
             float t1 = TanSeries<J>::minus1(x);  // tan(c dt E) / (c dt E) - 1
             midpoint_update_tan(a1[q], b1[q], a2[q], b2[q], fmaf(t1, Xr, Xr), fmaf(t1, Yr, Yr));
@@ -719,10 +748,8 @@ __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
   if (p.k_end == p.n_steps) {
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
-      long long idx = base + (long long)q * blockDim.x;
-      bool valid = idx < p.npts;
-      if (!valid) idx = p.npts - 1;
-      PointCoords c = coords(p, idx);
+      const BandPoint b = band_point(p, band, col, PPL, q);
+      PointCoords c = coords(p, b.idx);
       double Pxi = c.px + p.A_in, Pyi = c.py + p.Ay_in;
       double Pxo = p.vsign * (c.px + p.A_out), Pyo = p.vsign * (c.py + p.Ay_out);
       double Ei = sqrt(Pxi * Pxi + Pyi * Pyi), Eo = sqrt(Pxo * Pxo + Pyo * Pyo);
@@ -735,18 +762,18 @@ __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
         n = (re * re + im * im) / (2.0 * Eo * Eo);
         if (kRenorm) n = n / (A1 * A1 + B1 * B1 + A2 * A2 + B2 * B2);
       }
-      if (valid) p.n_out[idx] = n;
+      if (lane_valid && b.valid) p.n_out[b.idx] = n;
     }
   } else if (p.store_state) {
     R* st = static_cast<R*>(p.state);
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
-      long long idx = base + (long long)q * blockDim.x;
-      if (idx < p.npts) {
-        st[idx] = a1[q];
-        st[p.npts + idx] = b1[q];
-        st[2 * p.npts + idx] = a2[q];
-        st[3 * p.npts + idx] = b2[q];
+      const BandPoint b = band_point(p, band, col, PPL, q);
+      if (lane_valid && b.valid) {
+        st[b.idx] = a1[q];
+        st[p.npts + b.idx] = b1[q];
+        st[2 * p.npts + b.idx] = a2[q];
+        st[3 * p.npts + b.idx] = b2[q];
       }
     }
   }
@@ -964,11 +991,23 @@ hipError_t strang_variant(int stages, int elliptic, int ppl, int block, const So
                   : strang_ppl<R, FORM, 1, 0, SH>(ppl, block, p, stream);
 }
 
+// The midpoint kernel's lanes cover bands of PPL rows column by column (band_point):
+// ceil(ny / PPL) * nx lanes, launched in slices of at most kMaxLanes, q.first being
+// the slice's first lane.
 template <typename R, int J, int PPL, int NS, int POL, int TAN>
 hipError_t launch_midpoint(int block, const SolveParams& p, hipStream_t stream) {
-  return sliced_launch(p, block, PPL, [&](const SolveParams& q, unsigned nb) {
+  const long long lanes = (p.npts / p.nx + PPL - 1) / PPL * p.nx;
+  const long long blocks = (lanes + block - 1) / block;
+  const long long max_blocks = kMaxLanes / block;
+  SolveParams q = p;
+  for (long long b0 = 0; b0 < blocks; b0 += max_blocks) {
+    q.first = b0 * block;
+    const unsigned nb = (unsigned)(blocks - b0 < max_blocks ? blocks - b0 : max_blocks);
     hipLaunchKernelGGL((midpoint_kernel<R, J, PPL, NS, POL, TAN>), dim3(nb), dim3(block), 0, stream, q);
-  });
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <typename R, int J, int NS, int POL, int TAN>

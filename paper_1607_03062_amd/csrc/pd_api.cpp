@@ -227,9 +227,10 @@ pd_status pd_create_grid(int nx, int ny, double px_min, double px_max, double py
   g->precision = precision;
   g->scheme = scheme;
   // Default launch shape (fastest measured on MI355X for the 2048^2 x 80000
-  // workload): field rows read by the scalar unit, 256-thread blocks, one point
-  // per lane in FP32 and four in FP64.
-  g->points_per_lane = is_fp32(precision) ? 1 : 4;
+  // workload): field rows read by the scalar unit, 256-thread blocks; Strang: one
+  // point per lane in FP32 and four in FP64; midpoint: four, which share their
+  // column's FP64 phase.
+  g->points_per_lane = (is_fp32(precision) && base_scheme(scheme) == PD_SCHEME_STRANG) ? 1 : 4;
   g->block_threads = 256;
   g->table_stage = 2;
   g->chunk_steps = 512;

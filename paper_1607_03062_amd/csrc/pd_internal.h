@@ -175,8 +175,9 @@ constexpr double kShearMaxAngle = 1.5707963267948966;
 // Parameters of one propagation launch (passed by value to the kernels).
 struct SolveParams {
   long long npts;
-  long long first;   // first point of this launch: a grid of more than 2^31 lanes runs as
-                     // several launches over consecutive point ranges
+  long long first;   // first point (Strang) or lane (midpoint: lanes cover bands of rows column
+                     // by column) of this launch: a grid of more than 2^31 lanes runs as
+                     // several launches over consecutive ranges
   int nx;
   double px_min, dx, py_min, dy;
   double A_in, A_out, dt;
