@@ -73,7 +73,9 @@ def algo(info: dict, precision: str):
       (J fma), alpha, beta (2 mul), the update: FP64 3 fma per component (24 flop, 12
       instr), FP32 mul + 2 fma + add per component (24 flop, 16 instr) plus 3 conversions.
     A y component adds Y = Y0 + dy and Y^2 (2 flop; 2 instr, 3 in FP32 tangent form).
-    Every midpoint operation is part of the method's step: algorithmic = executed."""
+    Every midpoint operation is part of the method's step: algorithmic = executed.  The
+    points of a lane share their column, so the phase add (and its FP32 conversion) is one
+    instruction per lane: the instruction count divides it by points_per_lane."""
     stages = info.get("stages", 1) or 1
     ell = info.get("elliptic", 0)
     if info["scheme"] in (0, 2):
@@ -82,12 +84,14 @@ def algo(info: dict, precision: str):
         return stages * fa * r // 3, stages * fe * r // 3, stages * i * r // 3
     J = info["taylor_order"]
     f32 = precision != "fp64"  # fp32fast runs as fp32
+    ppl = info.get("points_per_lane", 1) or 1
     if info["rotation_form"] == 0:
         flops = 3 + (2 * (J - 2) + 1) + 4 + 16 + (2 if ell else 0)
-        instr = 2 + (J - 1) + 2 + 12 + (1 if f32 else 0) + ((3 if f32 else 2) if ell else 0)
+        shared = 2 if f32 else 1  # phase add (+ FP32 conversion), once per lane
+        instr = shared / ppl + 1 + (J - 1) + 2 + 12 + ((3 if f32 else 2) if ell else 0)
     else:
         flops = 3 + (2 * (J - 1) + 1) + 2 * J + 2 + 24 + (2 if ell else 0)
-        instr = 2 + 2 * J + 2 + (16 + 3 if f32 else 12) + (2 if ell else 0)
+        instr = 1.0 / ppl + 1 + 2 * J + 2 + (16 + 3 if f32 else 12) + (2 if ell else 0)
     return stages * flops, stages * flops, stages * instr
 
 
@@ -289,25 +293,43 @@ def serve_object(args, pd, torch, np):
 
     st = torch.cuda.Stream()
     budget = int(args.budget_gb * (1 << 30))
-    kw = dict(epoch_steps=args.epoch_steps, policy=args.policy, epoch_ms=args.epoch_ms)
+    epoch_ms = args.epoch_ms if (args.epoch_ms > 0 or args.policy != "srpt") else 3.0
     # untimed warm-up passes (another draw of 16 requests): the first launches load the
     # code object and instantiate the batch graph, the first allocations map memory
     for i in range(args.serve_warmup):
         warm = [serve.Request.from_workload(w) for w in wl.config5(count=16, seed=54 + 100 * i, rate_per_s=1e9)]
         ex = serve.GpuExecutor(pd, stream=st)
-        serve.Server(ex, budget, **kw).run(warm)
+        serve.Server(ex, budget, epoch_steps=args.epoch_steps, policy=args.policy, epoch_ms=epoch_ms).run(warm)
         ex.close()
-    # capacity: a closed set of requests, all present at t = 0
+    # capacity: a closed set of requests, all present at t = 0; with --epoch-ms 0 (srpt) the
+    # epoch length is tuned on it first, and the chosen length's passes give the capacity
     cap_reqs = [serve.Request.from_workload(w) for w in wl.config5(count=args.capacity_requests, seed=55,
                                                                      rate_per_s=1e9)]
-    ex = serve.GpuExecutor(pd, stream=st)
-    cap = serve.Server(ex, budget, **kw).run(cap_reqs)
-    ex.close()
-    mean_ps = float(np.mean([r.point_steps for r in cap_reqs]))
-    capacity_rps = cap.point_steps_per_s / mean_ps
+    total_ps = float(sum(r.point_steps for r in cap_reqs))
+    tuning = None
+    if args.epoch_ms <= 0 and args.policy == "srpt":
+        cands = [float(c) for c in args.epoch_candidates.split(",")]
+        epoch_ms, spans = serve.tune_epoch_ms(lambda: serve.GpuExecutor(pd, stream=st), budget, cap_reqs,
+                                              candidates=cands, repeats=2, epoch_steps=args.epoch_steps,
+                                              policy=args.policy)
+        tuning = {"candidates_ms": cands, "makespans_s": {"%g" % c: v for c, v in spans.items()},
+                  "chosen_ms": epoch_ms}
+        cap_makespan = float(np.median(spans[epoch_ms]))
+        log("serve: epoch length %g ms chosen (median capacity-pass makespans %s)" % (
+            epoch_ms, {c: "%.3f s" % float(np.median(v)) for c, v in spans.items()}))
+    else:
+        ex = serve.GpuExecutor(pd, stream=st)
+        cap = serve.Server(ex, budget, epoch_steps=args.epoch_steps, policy=args.policy,
+                           epoch_ms=epoch_ms).run(cap_reqs)
+        ex.close()
+        cap_makespan = cap.makespan_s
+    kw = dict(epoch_steps=args.epoch_steps, policy=args.policy, epoch_ms=epoch_ms)
+    cap_ps = total_ps / cap_makespan
+    mean_ps = total_ps / len(cap_reqs)
+    capacity_rps = cap_ps / mean_ps
     rate = args.rate_per_s if args.rate_per_s else args.load * capacity_rps
     log("serve: capacity %.1f requests/s (%.3g point-steps/s); stream of %d requests at %.1f/s" % (
-        capacity_rps, cap.point_steps_per_s, args.requests, rate, ))
+        capacity_rps, cap_ps, args.requests, rate))
     reqs = [serve.Request.from_workload(w) for w in wl.config5(count=args.requests, seed=5, rate_per_s=rate)]
     ex = serve.GpuExecutor(pd, stream=st)
     res = serve.Server(ex, budget, **kw).run(
@@ -317,15 +339,16 @@ def serve_object(args, pd, torch, np):
     return {
         "workload": "Poisson stream of %d solve requests (batch-workload grid, field and step distributions, "
                     "50/50 FP32/FP64), rate %.1f req/s = %.2f x capacity, HBM budget %.0f GiB, %s epochs "
-                    "(%d steps / %.1f ms)" % (args.requests, rate, rate / capacity_rps, args.budget_gb, args.policy,
-                                              args.epoch_steps, args.epoch_ms),
+                    "(%d steps / %g ms)" % (args.requests, rate, rate / capacity_rps, args.budget_gb, args.policy,
+                                            args.epoch_steps, epoch_ms),
         "requests": args.requests, "rate_per_s": rate, "load": rate / capacity_rps, "value": res.point_steps_per_s,
         "unit": "point-steps/s", "p50_ms": res.p50_ms, "p99_ms": res.p99_ms, "mean_ms": res.mean_ms,
         "completed": res.completed, "rejected": res.rejected, "makespan_s": res.makespan_s, "epochs": res.epochs,
         "mean_active": res.mean_active, "peak_bytes": res.peak_bytes, "budget_bytes": res.budget_bytes,
-        "handles_reused": reused, "policy": args.policy, "epoch_ms": args.epoch_ms, "epoch_steps": args.epoch_steps,
-        "capacity": {"requests_per_s": capacity_rps, "point_steps_per_s": cap.point_steps_per_s,
-                     "requests": args.capacity_requests, "makespan_s": cap.makespan_s},
+        "handles_reused": reused, "policy": args.policy, "epoch_ms": epoch_ms, "epoch_steps": args.epoch_steps,
+        "epoch_tuning": tuning,
+        "capacity": {"requests_per_s": capacity_rps, "point_steps_per_s": cap_ps,
+                     "requests": args.capacity_requests, "makespan_s": cap_makespan},
     }
 
 
@@ -387,7 +410,9 @@ def main():
     ap.add_argument("--epoch-steps", type=int, default=2048)
     ap.add_argument("--policy", choices=["lockstep", "srpt"], default="srpt",
                     help="serving: how an epoch shares the device (paper_1607_03062_amd/serve.py)")
-    ap.add_argument("--epoch-ms", type=float, default=3.0, help="serving (srpt): time budget of an epoch")
+    ap.add_argument("--epoch-ms", type=float, default=0.0,
+                    help="serving (srpt): time budget of an epoch (0: tuned on the capacity requests)")
+    ap.add_argument("--epoch-candidates", default="1.5,3,6", help="serving: epoch lengths (ms) the tuner times")
     ap.add_argument("--rate-per-s", type=float, default=0.0,
                     help="serving: arrival rate (default: --load x the capacity measured in the same run)")
     ap.add_argument("--steps", type=int, default=10)

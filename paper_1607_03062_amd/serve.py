@@ -322,7 +322,8 @@ DEFAULT_TILE_STEP_S = 0.43e-6
 class Server:
     def __init__(self, executor, budget_bytes: int, epoch_steps: int = 2048, max_active: int = 4096,
                  backfill: bool = False, policy: str = "srpt", epoch_ms: float = 3.0, rates: dict = None,
-                 tile_step_s: float = DEFAULT_TILE_STEP_S, max_wait_epochs: int = 32, admit_per_epoch: int = 4):
+                 tile_step_s: float = DEFAULT_TILE_STEP_S, max_wait_epochs: int = 32, admit_per_epoch: int = 4,
+                 defer_admissions: bool = True):
         if epoch_steps < 1:
             raise ValueError("epoch_steps must be >= 1")
         if policy not in ("lockstep", "srpt"):
@@ -344,6 +345,10 @@ class Server:
         self.tile_step_s = tile_step_s
         self.max_wait = int(max_wait_epochs)
         self.admit_per_epoch = int(admit_per_epoch)
+        # after an epoch in which requests finished the host has waited for the device, which
+        # is then idle: enqueue the next epoch of the remaining solves before setting up new
+        # admissions, so that their set-up (field sampling, table upload) overlaps it
+        self.defer_admissions = bool(defer_admissions)
         self.waited = {}  # request name -> epochs in a row without steps (srpt)
         self.in_use = 0
         self.peak = 0
@@ -394,6 +399,7 @@ class Server:
         progress_every completions."""
         reqs = sorted(requests, key=lambda r: r.arrival_s)
         finished = 0
+        idle_after_finish = False  # the last epoch finished requests (the host waited for it)
         pending = collections.deque(reqs)
         waiting = collections.deque()  # arrived, not yet admitted
         t0 = time.perf_counter()
@@ -411,10 +417,13 @@ class Server:
                 waiting.append(r)
             # admit in arrival order while memory and slots allow (optionally skipping a blocked
             # head), at most admit_per_epoch before the next epoch: the device then runs that
-            # epoch (enqueued without waiting) while the host sets up the next arrivals
+            # epoch (enqueued without waiting) while the host sets up the next arrivals.  Right
+            # after a finishing epoch the device is idle: then the next epoch goes first.
             blocked = []
             admitted = 0
-            while waiting and len(self.active) < self.max_active and admitted < self.admit_per_epoch:
+            hold = self.defer_admissions and idle_after_finish and self.active
+            while (not hold and waiting and len(self.active) < self.max_active
+                   and admitted < self.admit_per_epoch):
                 r = waiting[0]
                 if self.in_use + r.bytes <= self.budget:
                     waiting.popleft()
@@ -455,6 +464,7 @@ class Server:
             epochs += 1
             active_sum += len(self.active)
             now = self._now(t0, simulated)
+            idle_after_finish = bool(done)
             for name, rho in done:
                 del self.left[name]
                 self.waited.pop(name, None)
@@ -475,3 +485,47 @@ class Server:
                           p99_ms=float(np.percentile(lat, 99)), mean_ms=float(lat.mean()),
                           point_steps_per_s=sum(r.point_steps for r in done) / makespan, epochs=epochs,
                           mean_active=active_sum / max(epochs, 1), peak_bytes=self.peak, budget_bytes=self.budget)
+
+
+def tune_epoch_ms(make_executor, budget_bytes: int, requests, candidates=(1.5, 3.0, 6.0), repeats: int = 2,
+                  simulated: bool = False, cache_path: str = None, cache_key: str = None, **server_kw):
+    """The srpt epoch length (epoch_ms) from timed candidates.  The same closed set of
+    requests (arrival times ignored: all present at t = 0) is served once per candidate and
+    repetition, the repetitions interleaved, each on a fresh executor from make_executor();
+    the candidate with the shortest median makespan (the highest capacity) is kept.  The
+    epoch length changes no result bit (each solve's steps are the same arithmetic however
+    they are grouped into epochs), only how the device is shared.
+
+    With cache_path and cache_key, a value stored for the key is returned without timing,
+    and a newly chosen one is appended (lines "key<TAB>epoch_ms").  Returns (epoch_ms,
+    {candidate: [makespans]}) -- the dict is empty when the value came from the cache."""
+    if cache_path and cache_key:
+        try:
+            with open(cache_path) as fh:
+                hits = [ln.rstrip("\n").split("\t") for ln in fh if ln.startswith(cache_key + "\t")]
+            if hits:
+                return float(hits[-1][1]), {}
+        except OSError:
+            pass
+    cands = [float(c) for c in candidates]
+    if not cands or any(not c > 0 for c in cands) or repeats < 1:
+        raise ValueError("candidates must be positive epoch lengths and repeats >= 1")
+    spans = {c: [] for c in cands}
+    for _ in range(repeats):
+        for c in cands:
+            reqs = [Request(r.name, 0.0, r.grid, r.field, r.n_steps, r.precision, r.scheme, r.valley)
+                    for r in requests]
+            ex = make_executor()
+            try:
+                st = Server(ex, budget_bytes, epoch_ms=c, **server_kw).run(reqs, simulated=simulated)
+            finally:
+                ex.close()
+            if st.completed != len(reqs):
+                raise RuntimeError("epoch tuning: %d of %d requests completed" % (st.completed, len(reqs)))
+            spans[c].append(st.makespan_s)
+    best = min(cands, key=lambda c: (float(np.median(spans[c])), c))
+    if cache_path and cache_key:
+        with open(cache_path, "a") as fh:
+            fh.write("%s\t%r\n" % (cache_key, best))
+    return best, spans
+

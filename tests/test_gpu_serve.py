@@ -69,6 +69,31 @@ def test_results_in_the_mix_equal_alone(gpu, policy):
     ex.close()
 
 
+def test_epoch_length_changes_no_result_bit(gpu):
+    """The same stream served with short and long srpt epochs, and the length the epoch tuner
+    picks from them: every request's n(p) and rho are bit for bit the same."""
+    ws = wl.config5(count=8, seed=7, rate_per_s=1e9, sizes=(64, 96, 128), step_range=(800, 3000))
+
+    def served(epoch_ms):
+        reqs = [serve.Request.from_workload(w) for w in ws]
+        ex = serve.GpuExecutor(gpu, keep_n=True)
+        st = serve.Server(ex, 10 ** 10, epoch_steps=256, epoch_ms=epoch_ms).run(reqs)
+        out = {r.name: (r.rho, ex.n_results[r.name]) for r in reqs}
+        ex.close()
+        assert st.completed == len(reqs)
+        return out
+
+    short, long_ = served(0.2), served(3.0)
+    best, spans = serve.tune_epoch_ms(lambda: serve.GpuExecutor(gpu), 10 ** 10,
+                                      [serve.Request.from_workload(w) for w in ws], candidates=(0.2, 3.0),
+                                      repeats=1, epoch_steps=256)
+    assert best in (0.2, 3.0) and all(len(v) == 1 for v in spans.values())
+    tuned = served(best)
+    for name, (rho, n) in short.items():
+        for other in (long_, tuned):
+            assert other[name][0] == rho and np.array_equal(other[name][1], n), name
+
+
 def test_footprint_matches_allocation(gpu):
     """solve_bytes (used for admission) covers what a chunked solve allocates."""
     c = wl.config1()

@@ -179,8 +179,11 @@ def test_srpt_does_not_starve_a_large_request():
         smalls = [serve.Request("s%d" % i, 8e-4 * i, wl.grid(32, 2.0), wl.sin2(0.1, 0.5, 8), 1000)
                   for i in range(1, 800)]
         ex = serve.FakeExecutor(rate_point_steps_per_s=rate_dev, tile_step_s=tile)
+        # admissions right after finishing epochs (defer_admissions off), so that the small
+        # requests alone could take every epoch and only the aging rule serves the large one
         srv = serve.Server(ex, 10 ** 12, epoch_steps=100, policy="srpt", epoch_ms=1.0,
-                           rates={"fp32": rate_dev, "fp64": rate_dev}, tile_step_s=tile, max_wait_epochs=max_wait)
+                           rates={"fp32": rate_dev, "fp64": rate_dev}, tile_step_s=tile, max_wait_epochs=max_wait,
+                           defer_admissions=False)
         seen = []
         epoch_each = ex.epoch_each
 
@@ -219,6 +222,64 @@ def test_admissions_per_epoch_are_capped():
     assert all(a <= b for a, b in zip(adm, adm[1:]))
     with pytest.raises(ValueError):
         serve.Server(ex, 10 ** 9, admit_per_epoch=0, policy="lockstep")
+
+
+def test_admissions_wait_for_the_epoch_after_a_finish():
+    """After an epoch in which a request finished (the host waited for the device, now idle),
+    the next epoch of the remaining solves is enqueued before new arrivals are set up: the
+    epoch that follows a finish never contains a request admitted after that finish."""
+    ex = serve.FakeExecutor(rate_point_steps_per_s=1e10)
+    reqs = [serve.Request("r%d" % i, 0.0, wl.grid(64, 2.0), wl.sin2(0.1, 0.5, 8), 600 + 500 * i)
+            for i in range(6)]
+    srv = serve.Server(ex, 10 ** 12, epoch_steps=500, admit_per_epoch=2, policy="lockstep")
+    members = []
+    epoch_each = ex.epoch_each
+
+    def record(steps):
+        members.append(set(ex.active))
+        return epoch_each(steps)
+    ex.epoch_each = record
+    finished_after = []
+    release = ex.release
+
+    def on_release(name):
+        finished_after.append((len(members), name))
+        release(name)
+    ex.release = on_release
+    st = srv.run(reqs, simulated=True)
+    assert st.completed == 6
+    for epoch, name in finished_after:
+        if epoch < len(members):
+            # the epoch right after a finish runs the solves that were there before it
+            assert members[epoch] <= members[epoch - 1], (epoch, name)
+    off = serve.Server(serve.FakeExecutor(rate_point_steps_per_s=1e10), 10 ** 12, epoch_steps=500,
+                       admit_per_epoch=2, policy="lockstep", defer_admissions=False)
+    assert off.run([serve.Request(r.name, 0.0, r.grid, r.field, r.n_steps) for r in reqs],
+                   simulated=True).completed == 6
+
+
+def test_epoch_tuner_keeps_the_fastest_candidate_and_caches(tmp_path):
+    """tune_epoch_ms serves the same closed set once per candidate and repetition and keeps
+    the shortest median makespan; a cached value for the key is returned without timing."""
+    reqs = [serve.Request("r%d" % i, 0.5 * i, wl.grid(64 * (1 + i % 4), 2.0), wl.sin2(0.1, 0.5, 8), 2000 + 700 * i)
+            for i in range(12)]
+    made = []
+
+    def make():
+        made.append(1)  # a per-epoch overhead makes the shortest epochs slow
+        return serve.FakeExecutor(rate_point_steps_per_s=2e10, tile_step_s=2e-7, epoch_overhead_s=2e-4)
+    kw = dict(epoch_steps=64, rates={"fp32": 2e10, "fp64": 2e10}, tile_step_s=2e-7)
+    cache = str(tmp_path / "epochs.txt")
+    best, spans = serve.tune_epoch_ms(make, 10 ** 12, reqs, candidates=(0.1, 0.5, 2.0), repeats=2, simulated=True,
+                                      cache_path=cache, cache_key="gfx950 srpt", **kw)
+    assert len(made) == 6 and all(len(v) == 2 for v in spans.values())
+    assert best == min(spans, key=lambda c: (np.median(spans[c]), c)) and best != 0.1
+    assert all(r.status == "pending" for r in reqs)  # the caller's requests are not served
+    again, spans2 = serve.tune_epoch_ms(lambda: pytest.fail("timed despite the cache"), 10 ** 12, reqs,
+                                        cache_path=cache, cache_key="gfx950 srpt")
+    assert again == best and spans2 == {}
+    with pytest.raises(ValueError):
+        serve.tune_epoch_ms(make, 10 ** 12, reqs, candidates=(0.0, 1.0), simulated=True)
 
 
 def test_idle_pool_keeps_reuses_and_evicts():
