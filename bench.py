@@ -292,13 +292,16 @@ def serve_object(args, pd, torch, np):
     from paper_1607_03062_amd import workloads as wl
 
     st = torch.cuda.Stream()
+
+    def make_ex():
+        return serve.GpuExecutor(pd, stream=st, background_setup=not args.no_background_setup)
     budget = int(args.budget_gb * (1 << 30))
     epoch_ms = args.epoch_ms if (args.epoch_ms > 0 or args.policy != "srpt") else 3.0
     # untimed warm-up passes (another draw of 16 requests): the first launches load the
     # code object and instantiate the batch graph, the first allocations map memory
     for i in range(args.serve_warmup):
         warm = [serve.Request.from_workload(w) for w in wl.config5(count=16, seed=54 + 100 * i, rate_per_s=1e9)]
-        ex = serve.GpuExecutor(pd, stream=st)
+        ex = make_ex()
         serve.Server(ex, budget, epoch_steps=args.epoch_steps, policy=args.policy, epoch_ms=epoch_ms).run(warm)
         ex.close()
     # capacity: a closed set of requests, all present at t = 0; with --epoch-ms 0 (srpt) the
@@ -309,21 +312,22 @@ def serve_object(args, pd, torch, np):
     tuning = None
     if args.epoch_ms <= 0 and args.policy == "srpt":
         cands = [float(c) for c in args.epoch_candidates.split(",")]
-        epoch_ms, spans = serve.tune_epoch_ms(lambda: serve.GpuExecutor(pd, stream=st), budget, cap_reqs,
+        epoch_ms, spans = serve.tune_epoch_ms(make_ex, budget, cap_reqs,
                                               candidates=cands, repeats=2, epoch_steps=args.epoch_steps,
-                                              policy=args.policy)
+                                              policy=args.policy, defer_admissions=not args.no_defer_admissions)
         tuning = {"candidates_ms": cands, "makespans_s": {"%g" % c: v for c, v in spans.items()},
                   "chosen_ms": epoch_ms}
         cap_makespan = float(np.median(spans[epoch_ms]))
         log("serve: epoch length %g ms chosen (median capacity-pass makespans %s)" % (
             epoch_ms, {c: "%.3f s" % float(np.median(v)) for c, v in spans.items()}))
     else:
-        ex = serve.GpuExecutor(pd, stream=st)
-        cap = serve.Server(ex, budget, epoch_steps=args.epoch_steps, policy=args.policy,
-                           epoch_ms=epoch_ms).run(cap_reqs)
+        ex = make_ex()
+        cap = serve.Server(ex, budget, epoch_steps=args.epoch_steps, policy=args.policy, epoch_ms=epoch_ms,
+                           defer_admissions=not args.no_defer_admissions).run(cap_reqs)
         ex.close()
         cap_makespan = cap.makespan_s
-    kw = dict(epoch_steps=args.epoch_steps, policy=args.policy, epoch_ms=epoch_ms)
+    kw = dict(epoch_steps=args.epoch_steps, policy=args.policy, epoch_ms=epoch_ms,
+              defer_admissions=not args.no_defer_admissions)
     cap_ps = total_ps / cap_makespan
     mean_ps = total_ps / len(cap_reqs)
     capacity_rps = cap_ps / mean_ps
@@ -331,7 +335,7 @@ def serve_object(args, pd, torch, np):
     log("serve: capacity %.1f requests/s (%.3g point-steps/s); stream of %d requests at %.1f/s" % (
         capacity_rps, cap_ps, args.requests, rate))
     reqs = [serve.Request.from_workload(w) for w in wl.config5(count=args.requests, seed=5, rate_per_s=rate)]
-    ex = serve.GpuExecutor(pd, stream=st)
+    ex = make_ex()
     res = serve.Server(ex, budget, **kw).run(
         reqs, progress=lambda done, n, now: log("serve: %d of %d requests done at %.0f s" % (done, n, now)))
     reused = ex.reused
@@ -346,6 +350,7 @@ def serve_object(args, pd, torch, np):
         "completed": res.completed, "rejected": res.rejected, "makespan_s": res.makespan_s, "epochs": res.epochs,
         "mean_active": res.mean_active, "peak_bytes": res.peak_bytes, "budget_bytes": res.budget_bytes,
         "handles_reused": reused, "policy": args.policy, "epoch_ms": epoch_ms, "epoch_steps": args.epoch_steps,
+        "background_setup": not args.no_background_setup, "defer_admissions": not args.no_defer_admissions,
         "epoch_tuning": tuning,
         "capacity": {"requests_per_s": capacity_rps, "point_steps_per_s": cap_ps,
                      "requests": args.capacity_requests, "makespan_s": cap_makespan},
@@ -377,6 +382,38 @@ def summarize_profile(args):
         for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
             lines.append("%-100s %6s %14s %14.0f %14s %14s" % (r["Name"][:100], r["Calls"], r["TotalDurationNs"],
                                                                float(r["AverageNs"]), r["MinNs"], r["MaxNs"]))
+    trace = rows(args.summarize_profile, "kernel_trace.csv")
+    if trace and args.pass_gap_ms > 0:
+        # passes: runs of kernels separated by device idle gaps longer than pass_gap_ms
+        ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]) for r in trace)
+        passes, cur = [], [ev[0]]
+        for e in ev[1:]:
+            if e[0] - max(x[1] for x in cur) > args.pass_gap_ms * 1e6:
+                passes.append(cur)
+                cur = []
+            cur.append(e)
+        passes.append(cur)
+        lines.append("passes (separated by device idle gaps above %g ms):" % args.pass_gap_ms)
+        for q, ps in enumerate(passes):
+            span = max(x[1] for x in ps) - ps[0][0]
+            busy, end = 0, ps[0][0]
+            gaps = []
+            for a, b, _ in ps:  # union of the kernels' intervals
+                if a > end:
+                    gaps.append(a - end)
+                busy += max(0, b - max(a, end))
+                end = max(end, b)
+            names = {}
+            for a, b, n in ps:
+                names[n] = names.get(n, 0) + 1
+            top = max(names, key=names.get)
+            lines.append("  pass %d: %d kernels, span %.1f ms, device busy %.1f ms (%.3f), idle gaps: %d under 100 us "
+                         "(%.1f ms), %d of 100 us - 1 ms (%.1f ms), %d above 1 ms (%.1f ms); most launched: %s (%d)" % (
+                             q, len(ps), span / 1e6, busy / 1e6, busy / max(span, 1),
+                             sum(g < 1e5 for g in gaps), sum(g for g in gaps if g < 1e5) / 1e6,
+                             sum(1e5 <= g < 1e6 for g in gaps), sum(g for g in gaps if 1e5 <= g < 1e6) / 1e6,
+                             sum(g >= 1e6 for g in gaps), sum(g for g in gaps if g >= 1e6) / 1e6, top[:60],
+                             names[top]))
     for counter, d in (("FETCH_SIZE", args.fetch_dir), ("WRITE_SIZE", args.write_dir)):
         if not d:
             continue
@@ -439,6 +476,13 @@ def main():
                          "and exit (no GPU work)")
     ap.add_argument("--fetch-dir", default="", help="with --summarize-profile: output of a --pmc FETCH_SIZE run")
     ap.add_argument("--write-dir", default="", help="with --summarize-profile: output of a --pmc WRITE_SIZE run")
+    ap.add_argument("--pass-gap-ms", type=float, default=0.0,
+                    help="with --summarize-profile: split the kernel trace into passes at device idle gaps longer "
+                         "than this and report each pass's span and busy time")
+    ap.add_argument("--no-background-setup", action="store_true",
+                    help="serving: set up admitted requests on the scheduling thread (between epochs)")
+    ap.add_argument("--no-defer-admissions", action="store_true",
+                    help="serving: set up admissions right after a finishing epoch (before the next epoch)")
     args = ap.parse_args()
     if args.summarize_profile:
         return summarize_profile(args)

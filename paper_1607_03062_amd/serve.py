@@ -139,7 +139,7 @@ class GpuExecutor:
     """Active solves as pd_grid handles in one pd_batch."""
 
     def __init__(self, pd, stream=None, points_per_lane: int = 0, block_threads: int = 0, keep_n: bool = False,
-                 idle_per_shape: int = 8):
+                 idle_per_shape: int = 8, background_setup: bool = True):
         """Every scheme, precision, field and valley is served; second-order Strang requests
         with fields along x share the batch's persistent kernel (see pd_batch).
 
@@ -147,7 +147,17 @@ class GpuExecutor:
         scheme and valley) and set up again for a later request of the same shape: that
         request then allocates nothing, and the finished one frees nothing (freeing device
         memory waits for the whole device).  Kept handles count against the server's
-        memory budget and are closed when admitted work needs the room."""
+        memory budget and are closed when admitted work needs the room.
+
+        With background_setup, an admitted request's set-up (pd_set_field: field sampling,
+        tables, their upload) runs on a host thread of its own while the device runs
+        epochs, and the request joins the batch at the first epoch boundary after it
+        (collect); the handle is in no batch meanwhile."""
+        import concurrent.futures
+
+        self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=1) if background_setup else None
+        self.setting_up = collections.OrderedDict()  # request name -> (Solver, shape key, n_steps, future)
+        self.joined = []  # names joined to the batch since the last collect()
         self.pd = pd
         self.stream = stream
         self.batch = pd.Batch()
@@ -177,24 +187,55 @@ class GpuExecutor:
         finally:
             s.close()
 
-    def admit(self, req: Request):
-        """Raises PDError if the library refuses the request (e.g. the step-size condition)."""
+    def admit(self, req: Request, background: bool = True):
+        """Set the request up and join it to the batch; with background_setup and
+        background, start the set-up in the background instead (the request is ready once
+        collect() reports it).  A set-up on the calling thread raises PDError if the
+        library refuses the request (e.g. the step-size condition)."""
         key = shape_key(req)
         s = self.idle.take(key)
         if s is None:
             s = self.pd.Solver.for_grid(req.grid, req.precision, req.scheme, req.valley)
         else:
             self.reused += 1
+        if self._pool is not None and background:
+            self.setting_up[req.name] = (s, key, req.n_steps, self._pool.submit(s.set_field, req.field, req.n_steps))
+            return
         try:
             s.set_field(req.field, req.n_steps)
         except Exception:
             s.close()
             raise
-        self.solvers[req.name] = s
-        self.keys[req.name] = key
-        self.order.append(req.name)
-        self.left[req.name] = req.n_steps
+        self._join(req.name, s, key, req.n_steps)
+
+    def _join(self, name, s, key, n_steps):
+        self.solvers[name] = s
+        self.keys[name] = key
+        self.order.append(name)
+        self.left[name] = n_steps
         self.batch.add(s)
+        self.joined.append(name)
+
+    def collect(self, block: bool = False):
+        """Requests whose set-up has finished since the last call, joined to the batch in
+        admission order: (ready names, [(name, exception)] of set-ups the library refused,
+        whose handles are closed).  block: wait for the oldest set-up in flight first."""
+        failed = []
+        if block and self.setting_up:
+            next(iter(self.setting_up.values()))[3].exception()  # waits; errors are read below
+        for name, (s, key, n_steps, fut) in list(self.setting_up.items()):
+            if not fut.done():
+                break  # later ones join after it, keeping admission order
+            del self.setting_up[name]
+            err = fut.exception()
+            if err is not None:
+                s.close()
+                failed.append((name, err))
+            else:
+                self._join(name, s, key, n_steps)
+        ready = list(self.joined)
+        self.joined.clear()
+        return ready, failed
 
     def epoch(self, steps: int):
         """Advance every active solve by up to `steps` steps (see epoch_each)."""
@@ -229,6 +270,11 @@ class GpuExecutor:
             s.close()
 
     def close(self):
+        if self._pool is not None:
+            self._pool.shutdown(wait=True)
+        for s, _, _, _ in self.setting_up.values():
+            s.close()
+        self.setting_up.clear()
         self.batch.close()
         for s in self.solvers.values():
             s.close()
@@ -244,7 +290,10 @@ class FakeExecutor:
     epoch_overhead_s; rho is a fixed function of the request."""
 
     def __init__(self, rate_point_steps_per_s: float = 1e12, bytes_per_point: int = 40, tile_step_s: float = 0.0,
-                 epoch_overhead_s: float = 0.0, idle_per_shape: int = 0):
+                 epoch_overhead_s: float = 0.0, idle_per_shape: int = 0, setup_epochs: int = 0, refuse=None):
+        """setup_epochs > 0 models background set-up: an admitted request becomes ready
+        (collect) only after that many epochs have run; refuse(request) -> True makes its
+        set-up fail."""
         self.rate = rate_point_steps_per_s
         self.bytes_per_point = bytes_per_point
         self.tile_step_s = tile_step_s
@@ -253,6 +302,11 @@ class FakeExecutor:
         self.clock = 0.0                          # simulated device time
         self.idle = IdlePool(idle_per_shape, lambda h: None)  # kept "handles": the finished requests
         self.reused = 0
+        self.joined = []
+        self.setup_epochs = int(setup_epochs)
+        self.refuse = refuse
+        self.setting_up = collections.OrderedDict()  # name -> (request, epochs left)
+        self.epochs_run = 0
 
     @property
     def idle_bytes(self) -> int:
@@ -264,10 +318,32 @@ class FakeExecutor:
     def footprint(self, req: Request) -> int:
         return req.points * self.bytes_per_point + 16 * req.n_steps
 
-    def admit(self, req: Request):
+    def admit(self, req: Request, background: bool = True):
         if self.idle.take(shape_key(req)) is not None:
             self.reused += 1
+        if self.setup_epochs > 0 or self.refuse is not None:
+            self.setting_up[req.name] = (req, self.setup_epochs)
+            return
         self.active[req.name] = [req, 0]
+        self.joined.append(req.name)
+
+    def collect(self, block: bool = False):
+        """Requests whose (modelled) set-up has finished, in admission order; block: the
+        oldest set-up in flight finishes now (the host waits for it)."""
+        failed = []
+        for name, (req, left) in list(self.setting_up.items()):
+            if left > 0 and not (block and not self.joined and not failed):
+                break
+            block = False
+            del self.setting_up[name]
+            if self.refuse is not None and self.refuse(req):
+                failed.append((name, RuntimeError("set-up refused")))
+            else:
+                self.active[name] = [req, 0]
+                self.joined.append(name)
+        ready = list(self.joined)
+        self.joined.clear()
+        return ready, failed
 
     def epoch(self, steps: int):
         return self.epoch_each({name: steps for name in self.active})
@@ -285,6 +361,9 @@ class FakeExecutor:
             if entry[1] == req.n_steps and m > 0:
                 done.append((name, 1e-3 * req.points / (1.0 + req.n_steps)))
         self.clock += max(work / self.rate, longest * self.tile_step_s) + self.epoch_overhead_s
+        self.epochs_run += 1
+        for name, (req, left) in self.setting_up.items():
+            self.setting_up[name] = (req, max(0, left - 1))
         return done
 
     def release(self, name: str):
@@ -354,11 +433,12 @@ class Server:
         self.peak = 0
         self.active = {}
         self.left = {}  # request name -> steps still to run
+        self.ready = set()  # admitted requests whose set-up has finished (members of the batch)
 
     def plan_epoch(self) -> dict:
-        """Steps each active solve advances in the next epoch (absent: none)."""
+        """Steps each ready solve advances in the next epoch (absent: none)."""
         if self.policy == "lockstep":
-            return {name: min(self.epoch_steps, left) for name, left in self.left.items()}
+            return {name: min(self.epoch_steps, left) for name, left in self.left.items() if name in self.ready}
         budget = self.epoch_s
         share = max(self.epoch_steps, int(self.epoch_s / self.tile_step_s))  # steps a tile runs in an epoch
         rate = {name: self.rates.get(r.precision, self.rates["fp32"]) for name, r in self.active.items()}
@@ -368,7 +448,9 @@ class Server:
             w = self.waited.get(n, 0)
             return (0, -w, n) if w >= self.max_wait else (1, self.active[n].points * self.left[n] / rate[n], n)
 
-        order = sorted(self.left, key=key)
+        order = sorted((n for n in self.left if n in self.ready), key=key)
+        if not order:
+            return {}
         plan = {}
         for name in order:
             pts = self.active[name].points
@@ -429,7 +511,9 @@ class Server:
                     waiting.popleft()
                     self.ex.reserve(r, self.budget - self.in_use - r.bytes)  # kept handles give way
                     try:
-                        self.ex.admit(r)
+                        # a lone admission is set up at once (its latency counts); several, as in a
+                        # burst, in the background while the device runs epochs (throughput counts)
+                        self.ex.admit(r, background=admitted > 0 or len(waiting) > 0)
                     except Exception as e:  # refused by the solver: reported, not retried
                         r.status, r.reason, r.done_s = "rejected", str(e), now
                         continue
@@ -445,6 +529,16 @@ class Server:
                     break
             for r in reversed(blocked):
                 waiting.appendleft(r)
+            # requests whose set-up finished join the next epoch; with none ready, wait for one
+            ready, failed = self.ex.collect(block=bool(self.active) and not self.ready)
+            self.ready.update(ready)
+            for name, err in failed:  # refused by the solver during set-up: reported, not retried
+                r = self.active.pop(name)
+                del self.left[name]
+                self.in_use -= r.bytes
+                r.status, r.reason, r.done_s = "rejected", str(err), self._now(t0, simulated)
+            if self.active and not self.ready:
+                continue
             if not self.active:
                 if pending:
                     if simulated:
@@ -457,7 +551,7 @@ class Server:
                 break
             plan = self.plan_epoch()
             done = self.ex.epoch_each(plan)
-            for name in self.left:
+            for name in self.ready:
                 self.waited[name] = 0 if plan.get(name, 0) > 0 else self.waited.get(name, 0) + 1
             for name, m in plan.items():
                 self.left[name] -= m
@@ -467,6 +561,7 @@ class Server:
             idle_after_finish = bool(done)
             for name, rho in done:
                 del self.left[name]
+                self.ready.discard(name)
                 self.waited.pop(name, None)
                 r = self.active.pop(name)
                 r.rho, r.done_s, r.status = rho, now, "done"

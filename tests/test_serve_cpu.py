@@ -80,10 +80,10 @@ def test_backfill_admits_smaller_requests_past_a_blocked_head():
 
 def test_request_refused_at_admission_is_rejected_and_frees_nothing():
     class Picky(serve.FakeExecutor):
-        def admit(self, req):
+        def admit(self, req, background=True):
             if req.name == "bad":
                 raise RuntimeError("dt * E_max exceeds pi")
-            super().admit(req)
+            super().admit(req, background)
 
     ex = Picky()
     reqs = stream(count=6)
@@ -145,6 +145,7 @@ def test_srpt_epoch_plan():
         r = serve.Request(name, 0.0, wl.grid(n, 2.0), wl.sin2(0.1, 0.5, 8), steps)
         srv.active[name] = r
         srv.left[name] = steps
+        srv.ready.add(name)
     plan = srv.plan_epoch()
     # remaining work: b 3.1e5 < a 1.3e6 < c 1.6e7 < d 5.9e8 point-steps; budget 1e6 point-steps
     assert plan["b"] == 300 and plan["a"] == 1000
@@ -258,6 +259,29 @@ def test_admissions_wait_for_the_epoch_after_a_finish():
                    simulated=True).completed == 6
 
 
+def test_requests_join_when_their_set_up_finishes():
+    """Background set-up: an admitted request joins the epochs only once its set-up has
+    finished (here two epochs later), never before; a set-up the library refuses rejects
+    the request and frees its memory; everything else completes."""
+    reqs = [serve.Request("r%d" % i, 0.0, wl.grid(64, 2.0), wl.sin2(0.1, 0.5, 8), 900 + 300 * i)
+            for i in range(8)]
+    ex = serve.FakeExecutor(rate_point_steps_per_s=1e10, setup_epochs=2, refuse=lambda r: r.name == "r5")
+    srv = serve.Server(ex, 10 ** 12, epoch_steps=300, admit_per_epoch=3, policy="lockstep")
+    planned = []
+    epoch_each = ex.epoch_each
+
+    def record(steps):
+        planned.append((set(k for k, m in steps.items() if m > 0), set(ex.active), set(ex.setting_up)))
+        return epoch_each(steps)
+    ex.epoch_each = record
+    st = srv.run(reqs, simulated=True)
+    assert st.completed == 7 and st.rejected == 1
+    assert reqs[5].status == "rejected" and "refused" in reqs[5].reason
+    for stepped, joined, setting_up in planned:
+        assert stepped <= joined and not (stepped & setting_up)
+    assert srv.in_use == 0 and not srv.active and not srv.ready
+
+
 def test_epoch_tuner_keeps_the_fastest_candidate_and_caches(tmp_path):
     """tune_epoch_ms serves the same closed set once per candidate and repetition and keeps
     the shortest median makespan; a cached value for the key is returned without timing."""
@@ -315,8 +339,8 @@ def test_kept_handles_are_reused_within_the_budget(slack):
     over = []
     admit = ex.admit
 
-    def checked(r):
-        admit(r)  # the server adds r.bytes to in_use after this returns
+    def checked(r, background=True):
+        admit(r, background)  # the server adds r.bytes to in_use after this returns
         over.append(srv.in_use + r.bytes + ex.idle_bytes - budget)
     ex.admit = checked
     st = srv.run(reqs, simulated=True)
