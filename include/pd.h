@@ -326,8 +326,11 @@ pd_status pd_autotune(pd_grid g, long long trial_steps, int use_cache, void* str
    steps come first.  Every item does the same arithmetic as the single-grid
    kernel with the scalar-unit table path.  The other members (fourth-order or
    midpoint schemes, fields with a y component) run their own single-solve
-   launches, with their own launch shapes, right after it in the same sequence.
-   Each grid's n(p) and rho are therefore bit-identical to its solve alone.  Densities of the grids that finish
+   launches, with their own launch shapes, concurrently with it on a stream of the
+   batch's own (default priority) that is forked from the caller's stream by an
+   event and joined back into it before the densities, so the sequence stays
+   ordered on the caller's stream.  Each grid's n(p) and rho are therefore
+   bit-identical to its solve alone.  Densities of the grids that finish
    are reduced in the same launch sequence (per grid, same fixed order as
    pd_density).  Grids must stay alive while they are members and must not be
    used with pd_propagate while a batch call on them is in flight. */
@@ -359,9 +362,12 @@ pd_status pd_batch_members(pd_batch b, pd_grid* out, int capacity);
    block_threads {64, 128, 256}; 0 keeps the current value. */
 pd_status pd_batch_set_launch(pd_batch b, int points_per_lane, int block_threads);
 /* Run every member's whole solve from t_i: counter reset, the persistent
-   kernel and the batched density, captured into a HIP graph on the first call
-   and replayed while the membership, the members' fields and the launch shape
-   are unchanged (the graph holds kernel nodes only).  Members end with
+   kernel (and the other members' launches beside it) and the batched density,
+   captured into a HIP graph on the first call and replayed while the membership,
+   the members' fields and the launch shape are unchanged (the graph holds kernel
+   nodes only).  The graph reads descriptors of its own, which epochs
+   (pd_batch_step, pd_batch_step_each, pd_batch_autotune) between two calls do not
+   touch; a new capture waits for the last replay first.  Members end with
    steps_done = N and n(p) in their buffers (pd_density works on them).
    rho_out: host array of pd_batch_size(b) doubles, in member order (may be
    NULL; if given, the call waits for stream). */

@@ -307,9 +307,10 @@ pd_status step_members(pd_batch b, const long long* max_steps, double* rho_out, 
   const size_t n = b->grids.size();
   hipError_t e;
   // the epoch descriptors are rewritten below: the previous epoch, on whatever stream
-  // it ran, must have finished reading them
-  if (!capturing(st) && (e = hipStreamWaitEvent(st, b->epoch_done, 0)) != hipSuccess)
-    return hip_error(e, "hipStreamWaitEvent");
+  // it ran, must have finished reading them (the completion events are recorded and
+  // waited for outside stream capture only)
+  const bool cap = capturing(st);
+  if (!cap && (e = hipStreamWaitEvent(st, b->epoch_done, 0)) != hipSuccess) return hip_error(e, "hipStreamWaitEvent");
   if ((s = ensure_device(&b->epoch.d_rho, &b->epoch.cap_rho, n)) != PD_OK) return s;
   std::vector<long long> begin(n), end(n);
   for (size_t i = 0; i < n; ++i) {
@@ -321,7 +322,7 @@ pd_status step_members(pd_batch b, const long long* max_steps, double* rho_out, 
   if ((s = make_plan(b, b->epoch.d_rho, begin, end, &plan)) != PD_OK) return s;
   if ((s = upload(b, b->epoch, plan, st)) != PD_OK) return s;
   if ((s = enqueue(b, b->epoch, plan, st)) != PD_OK) return s;
-  if ((e = hipEventRecord(b->epoch_done, st)) != hipSuccess) return hip_error(e, "hipEventRecord");
+  if (!cap && (e = hipEventRecord(b->epoch_done, st)) != hipSuccess) return hip_error(e, "hipEventRecord");
   for (pd_grid g : b->grids)
     if ((s = mark_use(g, st)) != PD_OK) return s;
   b->n_items_last = (int)plan.items.size();
@@ -446,7 +447,7 @@ pd_status pd_batch_run(pd_batch b, double* rho_out, void* stream) {
   }
   hipError_t e = hipGraphLaunch(b->exec, st);
   if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
-  if ((e = hipEventRecord(b->whole_done, st)) != hipSuccess) return hip_error(e, "hipEventRecord");
+  if (!capturing(st) && (e = hipEventRecord(b->whole_done, st)) != hipSuccess) return hip_error(e, "hipEventRecord");
   for (pd_grid g : b->grids) {
     g->steps_done = g->field.n_steps;
     if ((s = mark_use(g, st)) != PD_OK) return s;
