@@ -414,6 +414,17 @@ def summarize_profile(args):
                              sum(1e5 <= g < 1e6 for g in gaps), sum(g for g in gaps if 1e5 <= g < 1e6) / 1e6,
                              sum(g >= 1e6 for g in gaps), sum(g for g in gaps if g >= 1e6) / 1e6, top[:60],
                              names[top]))
+    for d in args.counter_dir:
+        # every counter of a --pmc run, per kernel: mean per dispatch and number of dispatches
+        per = {}
+        for r in rows(d, "counter_collection.csv"):
+            key = (r["Kernel_Name"], r["Counter_Name"])
+            per.setdefault(key, {}).setdefault(r.get("Dispatch_Id", len(per)), 0.0)
+            per[key][r.get("Dispatch_Id", len(per))] += float(r["Counter_Value"])
+        lines.append("counters of %s (per dispatch, summed over the dimensions):" % d)
+        for (k, c), v in sorted(per.items()):
+            lines.append("  %s %s: %.6e (mean of %d dispatches)" % (k[:100], c, float(np.mean(list(v.values()))),
+                                                                   len(v)))
     for counter, d in (("FETCH_SIZE", args.fetch_dir), ("WRITE_SIZE", args.write_dir)):
         if not d:
             continue
@@ -476,6 +487,8 @@ def main():
                          "and exit (no GPU work)")
     ap.add_argument("--fetch-dir", default="", help="with --summarize-profile: output of a --pmc FETCH_SIZE run")
     ap.add_argument("--write-dir", default="", help="with --summarize-profile: output of a --pmc WRITE_SIZE run")
+    ap.add_argument("--counter-dir", action="append", default=[],
+                    help="with --summarize-profile: output of a --pmc run; every counter per kernel (repeatable)")
     ap.add_argument("--pass-gap-ms", type=float, default=0.0,
                     help="with --summarize-profile: split the kernel trace into passes at device idle gaps longer "
                          "than this and report each pass's span and busy time")
