@@ -94,6 +94,33 @@ def test_epoch_length_changes_no_result_bit(gpu):
             assert other[name][0] == rho and np.array_equal(other[name][1], n), name
 
 
+def test_request_refused_during_background_set_up(gpu):
+    """In a burst (set-ups on the background thread), a request whose step count violates the
+    step condition dt E_max <= pi (Sec. III) is refused by the library during its set-up: it
+    is rejected with the library's message, frees its memory, and the others complete with
+    the results of their solves alone."""
+    ws = wl.config5(count=6, seed=9, rate_per_s=1e9, sizes=(64, 96), step_range=(800, 2000))
+    bad = dict(ws[2], name="too_few_steps", n_steps=5)
+    reqs = [serve.Request.from_workload(w) for w in ws[:2] + [bad] + ws[2:]]
+    ex = serve.GpuExecutor(gpu, keep_n=True)
+    srv = serve.Server(ex, 10 ** 10, epoch_steps=256, epoch_ms=1.0)
+    st = srv.run(reqs)
+    assert st.completed == len(ws) and st.rejected == 1 and srv.in_use == 0
+    r_bad = next(r for r in reqs if r.name == "too_few_steps")
+    assert r_bad.status == "rejected" and "exceeds pi" in r_bad.reason, r_bad.reason
+    for r in reqs:
+        if r.status != "done":
+            continue
+        s = gpu.Solver.for_grid(r.grid, r.precision, r.scheme, r.valley)
+        s.set_field(r.field, r.n_steps)
+        s.propagate(-1)
+        n = np.empty(s.nx * s.ny)
+        rho = s.density(n_out=n)
+        s.close()
+        assert r.rho == rho and np.array_equal(ex.n_results[r.name], n), r.name
+    ex.close()
+
+
 def test_footprint_matches_allocation(gpu):
     """solve_bytes (used for admission) covers what a chunked solve allocates."""
     c = wl.config1()
