@@ -583,13 +583,16 @@ class Server:
 
 
 def tune_epoch_ms(make_executor, budget_bytes: int, requests, candidates=(1.5, 3.0, 6.0), repeats: int = 2,
-                  simulated: bool = False, cache_path: str = None, cache_key: str = None, **server_kw):
+                  simulated: bool = False, cache_path: str = None, cache_key: str = None, tolerance: float = 0.02,
+                  **server_kw):
     """The srpt epoch length (epoch_ms) from timed candidates.  The same closed set of
     requests (arrival times ignored: all present at t = 0) is served once per candidate and
-    repetition, the repetitions interleaved, each on a fresh executor from make_executor();
-    the candidate with the shortest median makespan (the highest capacity) is kept.  The
-    epoch length changes no result bit (each solve's steps are the same arithmetic however
-    they are grouped into epochs), only how the device is shared.
+    repetition, the repetitions interleaved, each on a fresh executor from make_executor().
+    The shortest candidate whose median makespan is within `tolerance` of the shortest
+    median is kept: a longer epoch runs a small request's steps in fewer, later epochs, so
+    it is taken only for capacity it really adds.  The epoch length changes no result bit
+    (each solve's steps are the same arithmetic however they are grouped into epochs), only
+    how the device is shared.
 
     With cache_path and cache_key, a value stored for the key is returned without timing,
     and a newly chosen one is appended (lines "key<TAB>epoch_ms").  Returns (epoch_ms,
@@ -603,8 +606,8 @@ def tune_epoch_ms(make_executor, budget_bytes: int, requests, candidates=(1.5, 3
         except OSError:
             pass
     cands = [float(c) for c in candidates]
-    if not cands or any(not c > 0 for c in cands) or repeats < 1:
-        raise ValueError("candidates must be positive epoch lengths and repeats >= 1")
+    if not cands or any(not c > 0 for c in cands) or repeats < 1 or not tolerance >= 0:
+        raise ValueError("candidates must be positive epoch lengths, repeats >= 1 and tolerance >= 0")
     spans = {c: [] for c in cands}
     for _ in range(repeats):
         for c in cands:
@@ -618,7 +621,8 @@ def tune_epoch_ms(make_executor, budget_bytes: int, requests, candidates=(1.5, 3
             if st.completed != len(reqs):
                 raise RuntimeError("epoch tuning: %d of %d requests completed" % (st.completed, len(reqs)))
             spans[c].append(st.makespan_s)
-    best = min(cands, key=lambda c: (float(np.median(spans[c])), c))
+    fastest = min(float(np.median(spans[c])) for c in cands)
+    best = min(c for c in cands if float(np.median(spans[c])) <= fastest * (1.0 + tolerance))
     if cache_path and cache_key:
         with open(cache_path, "a") as fh:
             fh.write("%s\t%r\n" % (cache_key, best))
