@@ -320,13 +320,15 @@ pd_status pd_autotune(pd_grid g, long long trial_steps, int use_cache, void* str
 
    A batch holds grids (any sizes, schemes, fields, step counts, precisions and
    valleys, each with its field set).  Its second-order Strang members with
-   fields along x share one persistent kernel: each block takes the next work
-   item -- one tile of block_threads * points_per_lane points of one grid -- from
-   a device counter until none is left; the items of the grids with the most
-   steps come first.  Every item does the same arithmetic as the single-grid
-   kernel with the scalar-unit table path.  The other members (fourth-order or
-   midpoint schemes, fields with a y component) run their own single-solve
-   launches, with their own launch shapes, concurrently with it on a stream of the
+   fields along x and fewer tiles than the persistent kernel has resident blocks
+   share that kernel: each block takes the next work item -- one tile of
+   block_threads * points_per_lane points of one grid -- from a device counter
+   until none is left; the items of the grids with the most steps come first.
+   Every item does the same arithmetic as the single-grid kernel with the
+   scalar-unit table path.  The other members (those that fill the device by
+   themselves, fourth-order or midpoint schemes, fields with a y component) run
+   their own single-solve launches, with their own launch shapes, concurrently
+   with it on a stream of the
    batch's own (default priority) that is forked from the caller's stream by an
    event and joined back into it before the densities, so the sequence stays
    ordered on the caller's stream.  Each grid's n(p) and rho are therefore

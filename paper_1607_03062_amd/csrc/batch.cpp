@@ -62,6 +62,11 @@ struct pd_batch_s {
   int graph_ppl = 0, graph_block = 0;
   int n_items_last = 0;
   int n_separate_last = 0;
+
+  // blocks of the persistent kernel resident at once (its launch size) for the launch
+  // shape slots_ppl x slots_block
+  long long slots = 0;
+  int slots_ppl = 0, slots_block = 0;
 };
 
 namespace {
@@ -126,8 +131,33 @@ struct Plan {
   long long density_tiles = 0;
 };
 
-// Members the persistent kernel runs: second-order Strang, no y component.
-bool persistent_member(pd_grid g) { return g->scheme == PD_SCHEME_STRANG && !g->field.elliptic; }
+// Blocks of the persistent kernel resident on the device at once for the batch's
+// launch shape: the number it is launched with (at most one per work item).
+long long persistent_slots(pd_batch b) {
+  if (b->slots <= 0 || b->slots_ppl != b->points_per_lane || b->slots_block != b->block_threads) {
+    const int per_cu = batch_blocks_per_cu(b->points_per_lane, b->block_threads);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || cus <= 0)
+      cus = 1;
+    b->slots = (long long)cus * per_cu;
+    b->slots_ppl = b->points_per_lane;
+    b->slots_block = b->block_threads;
+  }
+  return b->slots;
+}
+
+// Members the persistent kernel runs: second-order Strang, no y component, with
+// fewer tiles than it has resident blocks.  A member with at least that many tiles
+// fills the device by itself; its own launch (its grid's shape, blocks scheduled by
+// the hardware) then runs at the rate of the solve alone, where the persistent
+// kernel's equal items would leave a partly filled last round of blocks (a lone
+// 2048^2 member in a 3000-step epoch ran at 0.90 of that rate, against 0.96 in its
+// own launch).
+bool persistent_member(pd_batch b, pd_grid g) {
+  if (g->scheme != PD_SCHEME_STRANG || g->field.elliptic) return false;
+  const long long tile = (long long)b->block_threads * b->points_per_lane;
+  return (g->grid.points() + tile - 1) / tile < persistent_slots(b);
+}
 
 // Descriptors for advancing member i over steps [begin[i], end[i]) (no work
 // where begin == end); jobs for the members whose end reaches their last step,
@@ -149,7 +179,7 @@ pd_status make_plan(pd_batch b, double* rho_copies, const std::vector<long long>
     plan->solves[i].precision = g->precision;
     plan->solves[i].form = g->form;
     if (begin[i] < end[i]) {
-      if (persistent_member(g))
+      if (persistent_member(b, g))
         order.push_back(i);
       else
         plan->separate.emplace_back(i, g->solve_params(begin[i], end[i], st));  // its own launch shape
@@ -223,11 +253,7 @@ pd_status enqueue(pd_batch b, BatchDescriptors& D, const Plan& plan, hipStream_t
     if ((e = hipStreamWaitEvent(b->side_stream, b->fork, 0)) != hipSuccess) return hip_error(e, "hipStreamWaitEvent");
   }
   if (!plan.items.empty()) {
-    int per_cu = batch_blocks_per_cu(b->points_per_lane, b->block_threads);
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || cus <= 0)
-      cus = 1;
-    long long blocks = std::min<long long>((long long)cus * per_cu, (long long)plan.items.size());
+    long long blocks = std::min<long long>(persistent_slots(b), (long long)plan.items.size());
     e = launch_batch(b->points_per_lane, b->block_threads, (int)blocks, D.d_solves, D.d_items,
                      (int)plan.items.size(), D.d_counter, stream);
     if (e != hipSuccess) return hip_error(e, "batch launch");
