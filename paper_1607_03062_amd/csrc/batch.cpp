@@ -14,18 +14,19 @@
 
 using namespace pdx;
 
-// Device descriptors of one launch sequence: solves, work items, density jobs, the
-// work counter and one rho per member.
+// Device descriptors of one launch sequence in one allocation that one copy fills:
+// the work counter (zero in every upload, so an epoch needs no reset kernel), the
+// solves, the work items and the density jobs, each at a 256-byte boundary; and
+// one rho per member.
 struct BatchDescriptors {
+  unsigned char* d_block = nullptr;
+  size_t cap_block = 0;
+  unsigned int* d_counter = nullptr;  // the pointers below point into d_block
   BatchSolve* d_solves = nullptr;
-  size_t cap_solves = 0;
   BatchItem* d_items = nullptr;
-  size_t cap_items = 0;
   DensityJob* d_jobs = nullptr;
-  size_t cap_jobs = 0;
   double* d_rho = nullptr;  // one rho per member, in member order
   size_t cap_rho = 0;
-  unsigned int* d_counter = nullptr;
 };
 
 struct pd_batch_s {
@@ -214,38 +215,43 @@ pd_status make_plan(pd_batch b, double* rho_copies, const std::vector<long long>
   return PD_OK;
 }
 
-// Copy the plan's descriptors to the set D through the pinned staging buffer.
+// Copy the plan's descriptors, and a zero work counter, to the set D through the
+// pinned staging buffer: one copy.
 pd_status upload(pd_batch b, BatchDescriptors& D, const Plan& plan, hipStream_t stream) {
-  pd_status s;
-  if ((s = ensure_device(&D.d_solves, &D.cap_solves, std::max<size_t>(plan.solves.size(), 1))) != PD_OK) return s;
-  if ((s = ensure_device(&D.d_items, &D.cap_items, std::max<size_t>(plan.items.size(), 1))) != PD_OK) return s;
-  if ((s = ensure_device(&D.d_jobs, &D.cap_jobs, std::max<size_t>(plan.jobs.size(), 1))) != PD_OK) return s;
+  const auto round_up = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t a = plan.solves.size() * sizeof(BatchSolve), c = plan.items.size() * sizeof(BatchItem),
                d = plan.jobs.size() * sizeof(DensityJob);
+  const size_t o_solves = 256, o_items = o_solves + round_up(a), o_jobs = o_items + round_up(c),
+               total = o_jobs + round_up(std::max<size_t>(d, 1));
+  pd_status s;
+  if ((s = ensure_device(&D.d_block, &D.cap_block, total)) != PD_OK) return s;
+  D.d_counter = reinterpret_cast<unsigned int*>(D.d_block);
+  D.d_solves = reinterpret_cast<BatchSolve*>(D.d_block + o_solves);
+  D.d_items = reinterpret_cast<BatchItem*>(D.d_block + o_items);
+  D.d_jobs = reinterpret_cast<DensityJob*>(D.d_block + o_jobs);
   // the previous upload from the staging buffer must have been consumed
   hipError_t e = hipEventSynchronize(b->staged);
   if (e != hipSuccess) return hip_error(e, "hipEventSynchronize");
-  if ((s = ensure_pinned(&b->h_stage, &b->cap_stage, a + c + d + 1)) != PD_OK) return s;
-  std::memcpy(b->h_stage, plan.solves.data(), a);
-  std::memcpy(b->h_stage + a, plan.items.data(), c);
-  std::memcpy(b->h_stage + a + c, plan.jobs.data(), d);
-  if (a && (e = hipMemcpyAsync(D.d_solves, b->h_stage, a, hipMemcpyHostToDevice, stream)) != hipSuccess)
-    return hip_error(e, "hipMemcpyAsync(solves)");
-  if (c && (e = hipMemcpyAsync(D.d_items, b->h_stage + a, c, hipMemcpyHostToDevice, stream)) != hipSuccess)
-    return hip_error(e, "hipMemcpyAsync(items)");
-  if (d && (e = hipMemcpyAsync(D.d_jobs, b->h_stage + a + c, d, hipMemcpyHostToDevice, stream)) != hipSuccess)
-    return hip_error(e, "hipMemcpyAsync(jobs)");
+  if ((s = ensure_pinned(&b->h_stage, &b->cap_stage, total)) != PD_OK) return s;
+  std::memset(b->h_stage, 0, total);
+  std::memcpy(b->h_stage + o_solves, plan.solves.data(), a);
+  std::memcpy(b->h_stage + o_items, plan.items.data(), c);
+  std::memcpy(b->h_stage + o_jobs, plan.jobs.data(), d);
+  if ((e = hipMemcpyAsync(D.d_block, b->h_stage, o_jobs + d, hipMemcpyHostToDevice, stream)) != hipSuccess)
+    return hip_error(e, "hipMemcpyAsync(descriptors)");
   if ((e = hipEventRecord(b->staged, stream)) != hipSuccess) return hip_error(e, "hipEventRecord");
   return PD_OK;
 }
 
-// Enqueue one launch sequence on `stream`: the persistent kernel over the plan's
+// Enqueue one launch sequence on `stream` (reset_counter: clear the work counter
+// with a kernel first, for a graph that is replayed without a new upload): the
+// persistent kernel over the plan's
 // items and, concurrently on the side stream (forked from and joined back into
 // `stream` with events, so the sequence stays one stream-ordered unit and one
 // captured graph), the other members' own launches; then the batched density.
 // The side launches take the compute units that the persistent kernel's blocks
 // leave as its queue drains.
-pd_status enqueue(pd_batch b, BatchDescriptors& D, const Plan& plan, hipStream_t stream) {
+pd_status enqueue(pd_batch b, BatchDescriptors& D, const Plan& plan, bool reset_counter, hipStream_t stream) {
   hipError_t e;
   const bool fork = !plan.separate.empty();
   if (fork) {
@@ -255,7 +261,7 @@ pd_status enqueue(pd_batch b, BatchDescriptors& D, const Plan& plan, hipStream_t
   if (!plan.items.empty()) {
     long long blocks = std::min<long long>(persistent_slots(b), (long long)plan.items.size());
     e = launch_batch(b->points_per_lane, b->block_threads, (int)blocks, D.d_solves, D.d_items,
-                     (int)plan.items.size(), D.d_counter, stream);
+                     (int)plan.items.size(), D.d_counter, reset_counter, stream);
     if (e != hipSuccess) return hip_error(e, "batch launch");
   }
   // the other members: the single-solve kernels, exactly as a solve alone
@@ -305,8 +311,6 @@ pd_status prepare_device(pd_batch b) {
   if (b->device < 0) return set_error(PD_ERR_STATE, "a member grid has no field");
   DeviceScope scope(b->device);
   hipError_t e;
-  for (BatchDescriptors* D : {&b->epoch, &b->whole})
-    if ((e = hipMalloc(&D->d_counter, sizeof(unsigned int))) != hipSuccess) return hip_error(e, "hipMalloc(counter)");
   for (hipEvent_t* ev : {&b->staged, &b->fork, &b->join, &b->epoch_done, &b->whole_done})
     if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) return hip_error(e, "hipEventCreate");
   // both streams at the default priority
@@ -347,7 +351,7 @@ pd_status step_members(pd_batch b, const long long* max_steps, double* rho_out, 
   Plan plan;
   if ((s = make_plan(b, b->epoch.d_rho, begin, end, &plan)) != PD_OK) return s;
   if ((s = upload(b, b->epoch, plan, st)) != PD_OK) return s;
-  if ((s = enqueue(b, b->epoch, plan, st)) != PD_OK) return s;
+  if ((s = enqueue(b, b->epoch, plan, false, st)) != PD_OK) return s;
   if (!cap && (e = hipEventRecord(b->epoch_done, st)) != hipSuccess) return hip_error(e, "hipEventRecord");
   for (pd_grid g : b->grids)
     if ((s = mark_use(g, st)) != PD_OK) return s;
@@ -450,7 +454,7 @@ pd_status pd_batch_run(pd_batch b, double* rho_out, void* stream) {
     // two branches, batched density (kernel nodes only).
     if ((e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
       return hip_error(e, "hipStreamBeginCapture");
-    pd_status se = enqueue(b, b->whole, plan, b->capture_stream);
+    pd_status se = enqueue(b, b->whole, plan, true, b->capture_stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(b->capture_stream, &graph);
     if (se != PD_OK) {
@@ -526,11 +530,8 @@ void pd_batch_destroy(pd_batch b) {
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     if (b->side_stream) (void)hipStreamDestroy(b->side_stream);
     for (BatchDescriptors* D : {&b->epoch, &b->whole}) {
-      free_dev(D->d_solves);
-      free_dev(D->d_items);
-      free_dev(D->d_jobs);
+      free_dev(D->d_block);
       free_dev(D->d_rho);
-      free_dev(D->d_counter);
     }
     if (b->h_stage) (void)hipHostFree(b->h_stage);
     if (b->h_rho) (void)hipHostFree(b->h_rho);
