@@ -407,8 +407,15 @@ def test_config3_precision_form(gpu, cfg3_subsample_oracle):
     assert abs(rho32 / rho64 - 1) <= 1e-5
     m = n32.reshape(2048, 2048)
     assert np.all(m[1024] == 0.0)
-    # the fast FP32 form (alternating plain shears) on the same subsample
+    # every point of the grid: the FP64 form stands in for the oracle there (it is within
+    # 1e-12 of it on the subsample above); the FP32 form is within 1e-5 everywhere
+    full32 = np.max(np.abs(n32 - n64))
+    print("config3 fp32 max |dn| over the full grid (against fp64) = %.3e" % full32)
+    assert full32 <= FP32_N_ABS
+    # the fast FP32 form (alternating plain shears) on the same subsample; over the full
+    # grid it exceeds 1e-5 at a few points, which is why it is not the default
     nf, rhof, _ = run(gpu, c["grid"], c["field"], c["n_steps"], "fp32fast")
     errf = np.max(np.abs(nf[idx] - n_o))
-    print("config3 fp32fast max |dn| on subsample = %.3e" % errf)
+    print("config3 fp32fast max |dn| on subsample = %.3e, over the full grid (against fp64) = %.3e" % (
+        errf, np.max(np.abs(nf - n64))))
     assert errf <= FP32_N_ABS
