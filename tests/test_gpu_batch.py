@@ -162,6 +162,46 @@ def test_epochs_with_a_step_limit_per_member(gpu):
     b.close()
 
 
+def test_members_that_fill_the_device_run_their_own_launch(gpu):
+    """A member with at least as many tiles as the persistent kernel has resident blocks
+    (a 2048^2 grid has 4096 tiles of 4 x 256 points; MI355X holds 768 such blocks) runs its
+    single-solve kernel on the side stream; the small members share the persistent kernel.
+    Either way every member ends bit-identical to its solve alone, in a whole-solve run and
+    in epochs with a step limit per member."""
+    field = wl.sin2(0.2, 0.7, 2)
+    spec = [(wl.grid(2048, 3.0), "fp32", 1500), (wl.grid(2048, 3.0), "fp64", 1100),
+            (wl.grid(64, 2.0), "fp32", 1300), (wl.grid(96, 2.5), "fp64", 900), (wl.grid(128, 2.0), "fp32fast", 1700)]
+    ms = []
+    for g, prec, N in spec:
+        s = gpu.Solver.for_grid(g, prec)
+        s.set_field(field, N)
+        ms.append(({"name": "%d^2 %s" % (g["nx"], prec)}, s))
+    ref = [alone(s) for _, s in ms]
+    b = gpu.Batch([s for _, s in ms])
+    b.set_launch(4, 256)
+    check_members(ms, ref, b.run(), "run")
+    info = b.info()
+    small_tiles = sum(-(-(g["nx"] * g["ny"]) // 1024) for g, _, _ in spec[2:])
+    assert info["separate_launches"] == 2 and info["work_items"] == small_tiles, info
+    for _, s in ms:
+        s.rewind()
+    rng = np.random.default_rng(5)
+    done = [None] * len(ms)
+    for _ in range(60):
+        lim = [int(v) for v in rng.choice([0, 200, 450, 800], size=len(ms))]
+        rho, fin = b.step_each(lim)
+        for i in range(len(ms)):
+            if not np.isnan(rho[i]):
+                done[i] = rho[i]
+        if fin.all():
+            break
+    assert fin.all()
+    check_members(ms, ref, done, "epochs")
+    b.close()
+    for _, s in ms:
+        s.close()
+
+
 def mixed_members(pd, count=6):
     """Strang members of every precision (persistent kernel) and members that run their own
     launches on the side stream: midpoint, fourth order, a y component, the K- valley."""
