@@ -393,9 +393,11 @@ class ServeStats:
 
 
 # Device rates (point-steps/s) the srpt policy prices work with, and the time one
-# 1024-point tile takes per step on a full device (MI355X measurements, Strang).
+# 1024-point tile of a small member takes per step while the members that fill the
+# device run their own launches beside it (MI355X measurements, Strang; 0.09-0.11 us
+# with the device to itself).  It caps the steps a solve gets in one epoch.
 DEFAULT_RATES = {"fp32": 5.0e12, "fp32fast": 6.5e12, "fp64": 3.4e12}
-DEFAULT_TILE_STEP_S = 0.43e-6
+DEFAULT_TILE_STEP_S = 0.15e-6
 
 
 class Server:
