@@ -9,13 +9,14 @@ resident in HBM before the timed region (pd_set_field once, pd_rewind per
 step).  The FP64 form and the fast FP32 form (alternating plain shears, PD_FP32_FAST) of the
 same workload are timed beside it, and all are checked against the FP64 CPU
 oracle on the 64 x 64 subsample (stride 32) and on the larger sample whose
-oracle run is also the CPU baseline.
+oracle run is also the CPU baseline; the two FP32 forms also against the FP64
+form at every point of the grid.
 
 The same JSON line carries two more objects (skip them with --no-batch / --no-serve):
   batch  the 64 seeded solves of the batch workload (grids 256^2..2048^2 on [-4,4]^2,
-         5k-80k steps, FP32 form) in one persistent graph-captured launch per pass,
-         autotuned, with its own roofline and the oracle on every member's 64 x 64
-         subsample (error and CPU baseline);
+         5k-80k steps, FP32 form) in one graph-captured launch sequence per pass,
+         autotuned, with its own roofline, the oracle on every member's 64 x 64
+         subsample (error and CPU baseline) and every point against its FP64 solve;
   serve  a Poisson stream of solve requests (batch-workload distributions, half FP32
          and half FP64) served by continuous batching at 0.7 of the capacity measured
          in the same run: p50 / p99 / mean latency and sustained point-steps/s.
