@@ -15,9 +15,8 @@
 using namespace pdx;
 
 // Device descriptors of one launch sequence in one allocation that one copy fills:
-// the work counter (zero in every upload, so an epoch needs no reset kernel), the
-// solves, the work items and the density jobs, each at a 256-byte boundary; and
-// one rho per member.
+// the work counter, the solves, the work items and the density jobs, each at a
+// 256-byte boundary; and one rho per member.
 struct BatchDescriptors {
   unsigned char* d_block = nullptr;
   size_t cap_block = 0;
@@ -215,8 +214,8 @@ pd_status make_plan(pd_batch b, double* rho_copies, const std::vector<long long>
   return PD_OK;
 }
 
-// Copy the plan's descriptors, and a zero work counter, to the set D through the
-// pinned staging buffer: one copy.
+// Copy the plan's descriptors to the set D through the pinned staging buffer: one
+// copy (the counter's slot goes along; a kernel clears it before each launch).
 pd_status upload(pd_batch b, BatchDescriptors& D, const Plan& plan, hipStream_t stream) {
   const auto round_up = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t a = plan.solves.size() * sizeof(BatchSolve), c = plan.items.size() * sizeof(BatchItem),
@@ -243,15 +242,13 @@ pd_status upload(pd_batch b, BatchDescriptors& D, const Plan& plan, hipStream_t 
   return PD_OK;
 }
 
-// Enqueue one launch sequence on `stream` (reset_counter: clear the work counter
-// with a kernel first, for a graph that is replayed without a new upload): the
-// persistent kernel over the plan's
+// Enqueue one launch sequence on `stream`: the persistent kernel over the plan's
 // items and, concurrently on the side stream (forked from and joined back into
 // `stream` with events, so the sequence stays one stream-ordered unit and one
 // captured graph), the other members' own launches; then the batched density.
 // The side launches take the compute units that the persistent kernel's blocks
 // leave as its queue drains.
-pd_status enqueue(pd_batch b, BatchDescriptors& D, const Plan& plan, bool reset_counter, hipStream_t stream) {
+pd_status enqueue(pd_batch b, BatchDescriptors& D, const Plan& plan, hipStream_t stream) {
   hipError_t e;
   const bool fork = !plan.separate.empty();
   if (fork) {
@@ -261,7 +258,7 @@ pd_status enqueue(pd_batch b, BatchDescriptors& D, const Plan& plan, bool reset_
   if (!plan.items.empty()) {
     long long blocks = std::min<long long>(persistent_slots(b), (long long)plan.items.size());
     e = launch_batch(b->points_per_lane, b->block_threads, (int)blocks, D.d_solves, D.d_items,
-                     (int)plan.items.size(), D.d_counter, reset_counter, stream);
+                     (int)plan.items.size(), D.d_counter, stream);
     if (e != hipSuccess) return hip_error(e, "batch launch");
   }
   // the other members: the single-solve kernels, exactly as a solve alone
@@ -351,7 +348,7 @@ pd_status step_members(pd_batch b, const long long* max_steps, double* rho_out, 
   Plan plan;
   if ((s = make_plan(b, b->epoch.d_rho, begin, end, &plan)) != PD_OK) return s;
   if ((s = upload(b, b->epoch, plan, st)) != PD_OK) return s;
-  if ((s = enqueue(b, b->epoch, plan, false, st)) != PD_OK) return s;
+  if ((s = enqueue(b, b->epoch, plan, st)) != PD_OK) return s;
   if (!cap && (e = hipEventRecord(b->epoch_done, st)) != hipSuccess) return hip_error(e, "hipEventRecord");
   for (pd_grid g : b->grids)
     if ((s = mark_use(g, st)) != PD_OK) return s;
@@ -454,7 +451,7 @@ pd_status pd_batch_run(pd_batch b, double* rho_out, void* stream) {
     // two branches, batched density (kernel nodes only).
     if ((e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
       return hip_error(e, "hipStreamBeginCapture");
-    pd_status se = enqueue(b, b->whole, plan, true, b->capture_stream);
+    pd_status se = enqueue(b, b->whole, plan, b->capture_stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(b->capture_stream, &graph);
     if (se != PD_OK) {

@@ -1160,12 +1160,10 @@ hipError_t launch_batch_density(const DensityJob* jobs, int n_jobs, long long to
 }
 
 hipError_t launch_batch(int ppl, int block, int grid_blocks, const BatchSolve* solves, const BatchItem* items,
-                        int n_items, unsigned int* counter, bool reset_counter, hipStream_t stream) {
-  if (reset_counter) {
-    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, stream, counter);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
+                        int n_items, unsigned int* counter, hipStream_t stream) {
+  hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, stream, counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   switch (ppl) {
     case 1:
       hipLaunchKernelGGL(batch_kernel<1>, dim3(grid_blocks), dim3(block), 0, stream, solves, items, n_items, counter);

@@ -246,10 +246,8 @@ constexpr long long kStaticPartials = kStaticMaxPoints / 2048;
 // Device address of the static scratch on `device` (kStaticPartials partials, then
 // one sum), looked up on the first call for that device.
 hipError_t static_scratch(int device, double** out);
-// reset_counter: clear *counter with a one-thread kernel before the persistent launch
 hipError_t launch_batch(int points_per_lane, int block_threads, int grid_blocks, const BatchSolve* solves,
-                        const BatchItem* items, int n_items, unsigned int* counter, bool reset_counter,
-                        hipStream_t stream);
+                        const BatchItem* items, int n_items, unsigned int* counter, hipStream_t stream);
 hipError_t launch_batch_density(const DensityJob* jobs, int n_jobs, long long total_tiles, hipStream_t stream);
 int batch_blocks_per_cu(int points_per_lane, int block_threads);
 long long density_partials(long long npts);
