@@ -68,8 +68,9 @@ def algo(info: dict, precision: str):
     rotation) when the field has a y component.
     Midpoint stage, phase X = c dt(px + A) (1 add, FP64) and x = X^2 + Y^2 (1 fma):
       tangent form (rotation_form 0), J series terms: tan(x)/x - 1 (J - 2 fma + 1 mul),
-      alpha, beta (2 fma), the update mul + fma + add per component (16 flop, 12 instr);
-      in FP32 plus the conversion of X (x is formed in FP32);
+      alpha, beta (2 fma), the update: FP32 mul + fma + add per component (16 flop, 12
+      instr), FP64 2 fma per component (16 flop, 8 instr); in FP32 plus the conversion of
+      X (x is formed in FP32);
       cosine form (rotation_form 1), order J: cos - 1 (J - 1 fma + 1 mul) and sin(x)/x
       (J fma), alpha, beta (2 mul), the update: FP64 3 fma per component (24 flop, 12
       instr), FP32 mul + 2 fma + add per component (24 flop, 16 instr) plus 3 conversions.
@@ -89,7 +90,7 @@ def algo(info: dict, precision: str):
     if info["rotation_form"] == 0:
         flops = 3 + (2 * (J - 2) + 1) + 4 + 16 + (2 if ell else 0)
         shared = 2 if f32 else 1  # phase add (+ FP32 conversion), once per lane
-        instr = shared / ppl + 1 + (J - 1) + 2 + 12 + ((3 if f32 else 2) if ell else 0)
+        instr = shared / ppl + 1 + (J - 1) + 2 + (12 if f32 else 8) + ((3 if f32 else 2) if ell else 0)
     else:
         flops = 3 + (2 * (J - 1) + 1) + 2 * J + 2 + 24 + (2 if ell else 0)
         instr = 1.0 / ppl + 1 + 2 * J + 2 + (16 + 3 if f32 else 12) + (2 if ell else 0)
