@@ -293,11 +293,38 @@ __device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM, NS, POL, S
       const Row r = tab[k];
       L.template step_at<false>(r.v, k);
     }
-    for (; k + kGroup <= seg; k += kGroup) {
-      Row r[kGroup];
+    // whole groups: a 32-bit trip count, so the loop test stays on the scalar unit, and
+    // two row sets in turn.  Each set is loaded right after the other set's first step
+    // (scalar loads complete out of order, so the wait before a set's first use covers
+    // every load in flight) and its latency is hidden behind that set's other steps; the
+    // scheduling barriers keep the loads there.  The clamped index re-reads the last
+    // group instead of branching.
+    while (k + kGroup <= seg) {
+      const long long left = (seg - k) / kGroup;
+      const int n = left < (1 << 30) ? (int)left : (1 << 30);
+      const Row* __restrict__ g = tab + k;
+      Row a[kGroup], b[kGroup];
 #pragma unroll
-      for (int u = 0; u < kGroup; ++u) r[u] = tab[k + u];
-      group_steps<Lanes, Row, 0, kGroup>(L, r);
+      for (int u = 0; u < kGroup; ++u) a[u] = g[u];
+      int i = 0;
+      for (; i + 1 < n; i += 2) {
+        group_steps<Lanes, Row, 0, 1>(L, a);
+        __builtin_amdgcn_sched_barrier(0);
+        const Row* __restrict__ gb = g + (long long)(i + 1) * kGroup;
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) b[u] = gb[u];
+        __builtin_amdgcn_sched_barrier(0);
+        group_steps<Lanes, Row, 1, kGroup>(L, a);
+        group_steps<Lanes, Row, 0, 1>(L, b);
+        __builtin_amdgcn_sched_barrier(0);
+        const Row* __restrict__ ga = g + (long long)(i + 2 < n ? i + 2 : n - 1) * kGroup;
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) a[u] = ga[u];
+        __builtin_amdgcn_sched_barrier(0);
+        group_steps<Lanes, Row, 1, kGroup>(L, b);
+      }
+      if (i < n) group_steps<Lanes, Row, 0, kGroup>(L, a);
+      k += (long long)n * kGroup;
     }
     for (; k < seg; ++k) {
       const Row r = tab[k];
