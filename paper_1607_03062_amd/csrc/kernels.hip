@@ -737,9 +737,8 @@ __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
       long long next = (k / kRenormEvery + 1) * kRenormEvery;
       seg = next < p.k_end ? next : p.k_end;
     }
-#pragma unroll kUnroll
-    for (; k < seg; ++k) {
-      const double* row = tab + k * W;
+    // one step: the stages of table row `row` (W values)
+    auto one_step = [&](const double* row) {
 #pragma unroll
       for (int j = 0; j < NS; ++j) {
         const double d = row[j];
@@ -770,7 +769,48 @@ __global__ void __launch_bounds__(256) midpoint_kernel(const SolveParams p) {
           }
         }
       }
+    };
+    if constexpr (NS == 1) {
+      // groups of kUnroll steps as in the Strang kernel: a 32-bit trip count (a scalar
+      // loop test) and two row sets in turn, each loaded right after the other set's
+      // first step and pinned there, so its latency is hidden behind that set's other
+      // steps; the clamped index re-reads the last group instead of branching
+      constexpr int kG = kUnroll, kV = kUnroll * W;
+      while (k + kG <= seg) {
+        const long long left = (seg - k) / kG;
+        const int n = left < (1 << 30) ? (int)left : (1 << 30);
+        const double* __restrict__ g = tab + k * W;
+        double ra[kV], rb[kV];
+#pragma unroll
+        for (int u = 0; u < kV; ++u) ra[u] = g[u];
+        int i = 0;
+        for (; i + 1 < n; i += 2) {
+          one_step(ra);
+          __builtin_amdgcn_sched_barrier(0);
+          const double* __restrict__ gb = g + (long long)(i + 1) * kV;
+#pragma unroll
+          for (int u = 0; u < kV; ++u) rb[u] = gb[u];
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 1; u < kG; ++u) one_step(ra + u * W);
+          one_step(rb);
+          __builtin_amdgcn_sched_barrier(0);
+          const double* __restrict__ ga = g + (long long)(i + 2 < n ? i + 2 : n - 1) * kV;
+#pragma unroll
+          for (int u = 0; u < kV; ++u) ra[u] = ga[u];
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 1; u < kG; ++u) one_step(rb + u * W);
+        }
+        if (i < n) {
+#pragma unroll
+          for (int u = 0; u < kG; ++u) one_step(ra + u * W);
+        }
+        k += (long long)n * kG;
+      }
     }
+#pragma unroll kUnroll
+    for (; k < seg; ++k) one_step(tab + k * W);
     if (kRenorm && (k % kRenormEvery) == 0 && k < p.n_steps) {
 #pragma unroll
       for (int q = 0; q < PPL; ++q) {
