@@ -124,6 +124,20 @@ def test_chunked_equals_single_launch(gpu, precision, scheme):
     assert np.array_equal(single[0], bound[0])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32fast"])
+@pytest.mark.parametrize("scheme", ["strang", "midpoint"])
+def test_short_chunks_cover_every_group_count(gpu, precision, scheme):
+    """The step loops run whole groups of steps (8 or 16 Strang steps, 4 midpoint steps) from
+    two row sets in turn, then single steps.  Chunks of 1-40 steps starting at every phase
+    give ranges with no whole group, one, an odd and an even number of them, each with and
+    without single steps around them; the result is the single launch bit for bit."""
+    chunks = [5, 8, 16, 24, 17, 15, 9, 33, 64, 7, 40, 3, 32, 1, 31, 48, 4, 12, 20, 2]
+    N = sum(chunks)
+    single = run(gpu, RAGGED, RAGGED_FIELD, N, precision, scheme)
+    chunked = run(gpu, RAGGED, RAGGED_FIELD, N, precision, scheme, chunks=chunks)
+    assert np.array_equal(single[0], chunked[0]) and single[1] == chunked[1]
+
+
 @pytest.mark.parametrize("precision,scheme,N,k", [("fp32", "strang", 3000, 1500), ("fp64", "strang", 2777, 1024),
                                                   ("fp64", "midpoint", 3000, 2047), ("fp32", "midpoint", 2600, 700),
                                                   ("fp32", "strang4", 600, 333), ("fp32fast", "strang", 3000, 701)])
