@@ -328,10 +328,9 @@ pd_status pd_autotune(pd_grid g, long long trial_steps, int use_cache, void* str
    scalar-unit table path.  The other members (those that fill the device by
    themselves, fourth-order or midpoint schemes, fields with a y component) run
    their own single-solve launches, with their own launch shapes, concurrently
-   with it on a stream of the
-   batch's own (default priority) that is forked from the caller's stream by an
-   event and joined back into it before the densities, so the sequence stays
-   ordered on the caller's stream.  Each grid's n(p) and rho are therefore
+   with it on a stream of the batch's own (default priority) that is forked from
+   the caller's stream by an event and joined back into it before the densities,
+   so the sequence stays ordered on the caller's stream.  Each grid's n(p) and rho are therefore
    bit-identical to its solve alone.  Densities of the grids that finish
    are reduced in the same launch sequence (per grid, same fixed order as
    pd_density).  Grids must stay alive while they are members and must not be
@@ -376,8 +375,9 @@ pd_status pd_batch_set_launch(pd_batch b, int points_per_lane, int block_threads
 pd_status pd_batch_run(pd_batch b, double* rho_out, void* stream);
 /* One epoch of continuous batching: advance every member that is not complete
    by up to max_steps steps from where it stands (state kept in each grid's
-   device state buffer between calls), in one persistent launch, and reduce the
-   densities of the members that complete.  rho_out[i] (host, may be NULL) is
+   device state buffer between calls), in one launch sequence as in
+   pd_batch_run but not captured, and reduce the densities of the members that
+   complete.  rho_out[i] (host, may be NULL) is
    written for members that complete in this call; finished_out[i] (host, may
    be NULL) is 1 for every complete member.  Waits for stream if rho_out is
    given. */
