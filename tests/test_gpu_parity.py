@@ -124,6 +124,22 @@ def test_chunked_equals_single_launch(gpu, precision, scheme):
     assert np.array_equal(single[0], bound[0])
 
 
+def test_every_point_of_a_long_solve_against_the_oracle(gpu):
+    """256^2 on [-4,4]^2 under a 12-cycle sin^2 pulse (E0 = 0.25, omega = 0.4), 30000 Strang
+    steps: every one of the 65536 points against the FP64 oracle (Sec. II Eq. (1), Sec. III
+    Eqs. (9)-(12)), within 1e-12 in FP64 and 1e-5 in the FP32 form, and rho within 1e-12
+    relative in FP64."""
+    grid, field, N = wl.grid(256, 4.0), wl.sin2(0.25, 0.4, 12), 30000
+    n_o = oracle.solve_grid(field, grid, N)[0]
+    n64, rho64, _ = run(gpu, grid, field, N, "fp64")
+    assert np.max(np.abs(n64 - n_o)) <= FP64_N_ABS
+    assert abs(rho64 / oracle.density(grid, n_o) - 1) <= 1e-12
+    n32, _, _ = run(gpu, grid, field, N, "fp32")
+    err32 = np.max(np.abs(n32 - n_o))
+    print("every point, 256^2 x 30000: fp32 max |dn| = %.3e, fp64 %.3e" % (err32, np.max(np.abs(n64 - n_o))))
+    assert err32 <= FP32_N_ABS
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32fast"])
 @pytest.mark.parametrize("scheme", ["strang", "midpoint"])
 def test_short_chunks_cover_every_group_count(gpu, precision, scheme):
