@@ -13,7 +13,10 @@ n(p), partials; pd_info.solve_bytes) fits in the memory budget, at most
 `admit_per_epoch` at a time so that a burst of arrivals is set up on the host while
 the device runs the epochs of those already admitted.  A request larger
 than the whole budget is rejected.  Latency is the time from a request's arrival
-to its density being on the host.
+to its density being on the host.  A request withdrawn by the client (Server.cancel,
+or its cancel_s) or past its deadline_s leaves at the next epoch boundary, queued or
+part-way through, with status "cancelled" or "expired"; its memory goes back to the
+budget and its handle is kept like a finished one.
 
 How an epoch shares the device is the policy:
   lockstep  every active solve advances `epoch_steps` steps;
@@ -28,7 +31,8 @@ How an epoch shares the device is the policy:
             advancing even when a flow of small ones could fill every epoch.
 
 The device work is in libpd; this module is the host-side scheduler.  The
-executor interface (footprint / reserve / admit / epoch_each / release, and
+executor interface (footprint / reserve / admit / collect / epoch_each / release /
+abandon, and
 idle_bytes: the memory of kept handles) has a GPU implementation over the C ABI
 and a CPU fake with a cost model, used to test the scheduling without a GPU.
 """
@@ -36,6 +40,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import threading
 import time
 
 import numpy as np
@@ -51,6 +56,10 @@ class Request:
     precision: str = "fp32"
     scheme: str = "strang"
     valley: str = "both"
+    # seconds after arrival: the result is wanted by deadline_s (past it the request
+    # expires, unserved or part-way through); the client withdraws it at cancel_s
+    deadline_s: float = float("inf")
+    cancel_s: float = float("inf")
     # filled by the server
     admitted_s: float = float("nan")
     done_s: float = float("nan")
@@ -256,6 +265,26 @@ class GpuExecutor:
                 done.append((name, float(rho[i])))
         return done
 
+    def abandon(self, name: str):
+        """Drop an admitted request that will not complete (cancelled or expired): a set-up
+        still in flight is waited for; the handle leaves the batch and is kept for a later
+        request of its shape (set up again from step 0) or closed."""
+        if name in self.setting_up:
+            s, key, n_steps, fut = self.setting_up.pop(name)
+            if fut.exception() is not None:
+                s.close()
+                return
+        else:
+            s = self.solvers.pop(name)
+            key = self.keys.pop(name)
+            self.order.remove(name)
+            del self.left[name]
+            if name in self.joined:
+                self.joined.remove(name)
+            self.batch.remove(s)
+        if not self.idle.put(key, s, int(s.info()["device_bytes"])):
+            s.close()
+
     def release(self, name: str):
         s = self.solvers.pop(name)
         if self.keep_n:
@@ -370,6 +399,15 @@ class FakeExecutor:
         req = self.active.pop(name)[0]
         self.idle.put(shape_key(req), req, self.footprint(req))
 
+    def abandon(self, name: str):
+        if name in self.setting_up:
+            req = self.setting_up.pop(name)[0]
+        else:
+            req = self.active.pop(name)[0]
+            if name in self.joined:
+                self.joined.remove(name)
+        self.idle.put(shape_key(req), req, self.footprint(req))
+
     def close(self):
         self.idle.clear()
 
@@ -387,6 +425,8 @@ class ServeStats:
     mean_active: float
     peak_bytes: int
     budget_bytes: int
+    cancelled: int = 0
+    expired: int = 0
 
     def as_dict(self) -> dict:
         return dataclasses.asdict(self)
@@ -436,6 +476,36 @@ class Server:
         self.active = {}
         self.left = {}  # request name -> steps still to run
         self.ready = set()  # admitted requests whose set-up has finished (members of the batch)
+        self._cancel = set()  # names withdrawn by cancel(), from any thread
+        self._cancel_lock = threading.Lock()
+
+    def cancel(self, name: str):
+        """Withdraw a request (waiting or active) from another thread while run() serves;
+        it leaves at the next epoch boundary with status "cancelled"."""
+        with self._cancel_lock:
+            self._cancel.add(name)
+
+    def _withdrawn(self, r: "Request", now: float):
+        with self._cancel_lock:
+            if r.name in self._cancel:
+                return "cancelled", "cancelled by the client"
+        if now >= r.arrival_s + r.cancel_s:
+            return "cancelled", "cancelled by the client at %.3f s" % (r.arrival_s + r.cancel_s)
+        if now > r.arrival_s + r.deadline_s:
+            return "expired", "deadline %.3f s after arrival passed" % r.deadline_s
+        return None
+
+    def _retire(self, r: "Request", status: str, reason: str, now: float):
+        """An admitted request that will not complete leaves the batch; its memory goes back
+        to the budget."""
+        name = r.name
+        del self.left[name]
+        self.ready.discard(name)
+        self.waited.pop(name, None)
+        self.active.pop(name)
+        self.in_use -= r.bytes
+        self.ex.abandon(name)
+        r.status, r.reason, r.done_s = status, reason, now
 
     def plan_epoch(self) -> dict:
         """Steps each ready solve advances in the next epoch (absent: none)."""
@@ -493,12 +563,30 @@ class Server:
             now = self._now(t0, simulated)
             while pending and pending[0].arrival_s <= now:
                 r = pending.popleft()
+                w = self._withdrawn(r, now)
+                if w is not None:
+                    r.status, r.reason = w
+                    r.done_s = now
+                    continue
                 r.bytes = self.ex.footprint(r)
                 if r.bytes > self.budget:
                     r.status, r.reason = "rejected", "footprint %d bytes exceeds the budget %d" % (r.bytes, self.budget)
                     r.done_s = now
                     continue
                 waiting.append(r)
+            # cancelled and expired requests leave the queue, or the batch at this epoch
+            # boundary (their memory goes back to the budget, the handle is kept for reuse)
+            for r in list(waiting):
+                w = self._withdrawn(r, now)
+                if w is not None:
+                    waiting.remove(r)
+                    r.status, r.reason = w
+                    r.done_s = now
+            for name in list(self.active):
+                r = self.active[name]
+                w = self._withdrawn(r, now)
+                if w is not None:
+                    self._retire(r, w[0], w[1], now)
             # admit in arrival order while memory and slots allow (optionally skipping a blocked
             # head), at most admit_per_epoch before the next epoch: the device then runs that
             # epoch (enqueued without waiting) while the host sets up the next arrivals.  Right
@@ -578,6 +666,8 @@ class Server:
         first = min((r.arrival_s for r in reqs), default=0.0)
         makespan = max(end - first, 1e-12)
         return ServeStats(completed=len(done), rejected=sum(r.status == "rejected" for r in reqs),
+                          cancelled=sum(r.status == "cancelled" for r in reqs),
+                          expired=sum(r.status == "expired" for r in reqs),
                           makespan_s=makespan, p50_ms=float(np.percentile(lat, 50)),
                           p99_ms=float(np.percentile(lat, 99)), mean_ms=float(lat.mean()),
                           point_steps_per_s=sum(r.point_steps for r in done) / makespan, epochs=epochs,

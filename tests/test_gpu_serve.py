@@ -210,3 +210,38 @@ def test_set_field_waits_for_its_own_work_only(gpu):
     rho_f = fresh.density(n_out=n_f)
     fresh.close()
     assert rho == rho_f and np.array_equal(n, n_f)
+
+
+def test_cancelled_and_expired_requests_leave_the_device(gpu):
+    """A large request cancelled part-way through and another past its deadline leave the
+    batch at an epoch boundary; the requests served beside them, and a later request of
+    the cancelled one's shape that takes over its kept handle (set up again from step 0),
+    equal their solves alone bit for bit and the oracle; all memory returns to the budget."""
+    field = wl.sin2(0.2, 0.6, 4)
+    big = dict(grid=wl.grid(1024, 3.0), field=field, n_steps=60000, precision="fp64")
+    reqs = [serve.Request("cancelled", 0.0, cancel_s=0.004, **big),
+            serve.Request("expires", 0.0, wl.grid(512, 3.0), field, 80000, precision="fp32", deadline_s=0.003),
+            serve.Request("small_a", 0.0, wl.grid(96, 2.0), field, 2500, precision="fp32"),
+            serve.Request("small_b", 0.001, wl.grid(128, 2.0), field, 1800, precision="fp64"),
+            serve.Request("same_shape_later", 0.25, wl.grid(1024, 3.0), field, 1500, precision="fp64")]
+    ex = serve.GpuExecutor(gpu, keep_n=True)
+    srv = serve.Server(ex, 10 ** 10, epoch_steps=512, policy="srpt", epoch_ms=1.0)
+    st = srv.run(reqs)
+    print("serve:", st.as_dict(), "handles reused:", ex.reused, [(r.name, r.status, r.done_s) for r in reqs],
+          flush=True)
+    by = {r.name: r for r in reqs}
+    assert by["cancelled"].status == "cancelled" and by["expires"].status == "expired"
+    assert st.cancelled == 1 and st.expired == 1 and st.completed == 3
+    assert srv.in_use == 0 and ex.reused >= 1
+    for name in ("small_a", "small_b", "same_shape_later"):
+        r = by[name]
+        s = gpu.Solver.for_grid(r.grid, r.precision, r.scheme, r.valley)
+        s.set_field(r.field, r.n_steps)
+        s.propagate(-1)
+        n = np.empty(s.nx * s.ny)
+        rho = s.density(n_out=n)
+        s.close()
+        assert r.status == "done" and r.rho == rho and np.array_equal(ex.n_results[name], n), name
+        if r.grid["nx"] <= 128:
+            check_against_oracle(r, ex.n_results[name])
+    ex.close()

@@ -355,3 +355,51 @@ def test_kept_handles_are_reused_within_the_budget(slack):
     assert max(over) <= 0 and st.peak_bytes <= budget
     shapes = {serve.shape_key(r) for r in reqs}
     assert len(ex.idle.entries) <= 2 * len(shapes)
+
+
+def _req(name, arrival, n, steps, **kw):
+    return serve.Request(name, arrival, wl.grid(n, 2.0), wl.sin2(0.1, 0.5, 4), steps, **kw)
+
+
+@pytest.mark.parametrize("policy", ["srpt", "lockstep"])
+def test_cancelled_and_expired_requests_leave_and_free_their_memory(policy):
+    """A request cancelled part-way through (cancel_s), one cancelled before it arrives
+    (Server.cancel), one that expires in the queue and one that expires part-way through
+    all leave with their status; the others complete as usual, the memory returns to the
+    budget (in_use 0 at the end), and a later request of the cancelled one's shape reuses
+    its kept handle."""
+    ex = serve.FakeExecutor(rate_point_steps_per_s=1e9, idle_per_shape=2)
+    reqs = [_req("long_cancelled", 0.0, 256, 40000, cancel_s=0.5),
+            _req("blocker", 0.001, 256, 20000),
+            _req("running_expires", 0.002, 128, 200000, deadline_s=1.0),
+            _req("queued_expires", 0.003, 512, 1000, deadline_s=0.05),
+            _req("withdrawn", 0.004, 64, 1000),
+            _req("after", 5.0, 256, 2000)]
+    first3 = sum(ex.footprint(r) for r in reqs[:3])
+    assert first3 + ex.footprint(reqs[3]) > first3 + first3 // 10  # the 512^2 one has to wait
+    srv = serve.Server(ex, first3 + first3 // 10, epoch_steps=256, policy=policy, epoch_ms=3.0,
+                       rates={"fp32": 1e9})
+    srv.cancel("withdrawn")
+    st = srv.run(reqs, simulated=True)
+    by = {r.name: r for r in reqs}
+    assert by["long_cancelled"].status == "cancelled" and not np.isfinite(by["long_cancelled"].rho)
+    assert abs(by["long_cancelled"].done_s - 0.5) < 0.05  # at the first epoch boundary past 0.5 s
+    assert by["withdrawn"].status == "cancelled" and by["withdrawn"].admitted_s != by["withdrawn"].admitted_s
+    assert by["queued_expires"].status == "expired" and by["queued_expires"].admitted_s != by["queued_expires"].admitted_s
+    assert by["running_expires"].status == "expired" and by["running_expires"].admitted_s >= 0
+    assert 1.0 < by["running_expires"].done_s < 1.1
+    assert by["blocker"].status == "done" and by["after"].status == "done"
+    assert st.completed == 2 and st.cancelled == 2 and st.expired == 2 and st.rejected == 0
+    assert srv.in_use == 0 and not srv.active and not srv.left and not srv.ready
+    assert ex.reused >= 1  # "after" took a kept 256^2 handle
+    assert st.peak_bytes <= srv.budget
+
+
+def test_cancel_during_background_set_up():
+    """A request withdrawn while its set-up is still in flight is abandoned from there."""
+    ex = serve.FakeExecutor(rate_point_steps_per_s=1e10, setup_epochs=3)
+    reqs = [_req("a", 0.0, 128, 30000), _req("b", 0.0, 128, 30000, cancel_s=0.002), _req("c", 0.0, 64, 500)]
+    srv = serve.Server(ex, 10 ** 12, epoch_steps=512, policy="srpt", epoch_ms=1.0)
+    st = srv.run(reqs, simulated=True)
+    assert [r.status for r in reqs] == ["done", "cancelled", "done"]
+    assert st.cancelled == 1 and srv.in_use == 0 and not ex.setting_up and not ex.active
