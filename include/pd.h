@@ -405,6 +405,16 @@ const char* pd_last_error(void);
 /* Library version string. */
 const char* pd_version(void);
 
+/* Test hook for callers' error handling, for tests only: arm one fault.  "alloc@K":
+   the K-th device allocation of the library from now on fails (PD_ERR_NOMEM from
+   the call that needed it); "launch@K": the K-th launch sequence (pd_propagate,
+   pd_batch_run, pd_batch_step, pd_batch_step_each) fails with PD_ERR_DEVICE
+   before it enqueues anything, leaving every grid where it stood.  The fault fires
+   once, then disarms; NULL or "" disarms.  The environment variable PD_FAULT with
+   the same syntax arms a fault at the library's first allocation or launch.
+   PD_ERR_INVALID for any other text.  Process-wide. */
+pd_status pd_set_fault(const char* spec);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,7 @@ from ._lib import (  # noqa: F401
     Batch,
     Solver,
     load,
+    set_fault,
 )
 
 

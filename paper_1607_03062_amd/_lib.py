@@ -123,6 +123,7 @@ SIGNATURES = [
     ("pd_destroy_grid", None, [_vp]),
     ("pd_last_error", ctypes.c_char_p, []),
     ("pd_version", ctypes.c_char_p, []),
+    ("pd_set_fault", ctypes.c_int, [ctypes.c_char_p]),
     ("pd_autotune", ctypes.c_int, [_vp, ctypes.c_longlong, ctypes.c_int, _vp]),
     ("pd_batch_create", ctypes.c_int, [ctypes.POINTER(_vp)]),
     ("pd_batch_add", ctypes.c_int, [_vp, _vp]),
@@ -186,6 +187,12 @@ def stream_handle(stream) -> int | None:
     if isinstance(stream, int):
         return stream
     return int(stream.cuda_stream)
+
+
+def set_fault(spec: str | None):
+    """Arm one injected fault for tests of error handling ("alloc@K" or "launch@K";
+    None disarms); see pd_set_fault."""
+    check(load().pd_set_fault(spec.encode() if spec else None), "pd_set_fault")
 
 
 def make_field(field: dict, n_steps: int):

@@ -84,7 +84,7 @@ pd_status ensure_device(T** p, size_t* cap, size_t n) {
   free_dev(*p);
   *p = nullptr;
   *cap = 0;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), want * sizeof(T));
+  hipError_t e = device_malloc(reinterpret_cast<void**>(p), want * sizeof(T));
   if (e != hipSuccess) return hip_error(e, "hipMalloc(batch descriptors)");
   *cap = want;
   return PD_OK;
@@ -336,6 +336,7 @@ pd_status step_members(pd_batch b, const long long* max_steps, double* rho_out, 
   // the epoch descriptors are rewritten below: the previous epoch, on whatever stream
   // it ran, must have finished reading them (the completion events are recorded and
   // waited for outside stream capture only)
+  if (fault_now(kFaultLaunch)) return set_error(PD_ERR_DEVICE, "injected launch fault (PD_FAULT)");
   const bool cap = capturing(st);
   if (!cap && (e = hipStreamWaitEvent(st, b->epoch_done, 0)) != hipSuccess) return hip_error(e, "hipStreamWaitEvent");
   if ((s = ensure_device(&b->epoch.d_rho, &b->epoch.cap_rho, n)) != PD_OK) return s;
@@ -434,6 +435,7 @@ pd_status pd_batch_run(pd_batch b, double* rho_out, void* stream) {
   DeviceScope scope(b->device);
   if (!scope.ok) return set_error(PD_ERR_DEVICE, "cannot select device %d", b->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (fault_now(kFaultLaunch)) return set_error(PD_ERR_DEVICE, "injected launch fault (PD_FAULT)");
   if (!graph_current(b)) {
     drop_graph(b);
     // the graph's descriptors are rewritten below: the last replay must be done with them

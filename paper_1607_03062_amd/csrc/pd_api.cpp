@@ -3,6 +3,8 @@
 
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -22,6 +24,34 @@ std::atomic<long long> g_versions{0};
 // Versions come from one process-wide counter, so a handle created at the
 // address of a destroyed one never matches the old handle's version.
 long long next_version() { return ++g_versions; }
+
+// The armed fault: its kind (-1: none) and how many events of that kind are left
+// until it fires.
+std::mutex g_fault_mu;
+int g_fault_kind = -1;
+long long g_fault_left = 0;
+bool g_fault_read = false;
+
+// "alloc@K" / "launch@K" (K >= 1), or empty / NULL for none; false if malformed.
+bool parse_fault(const char* spec, int* kind, long long* left) {
+  *kind = -1;
+  *left = 0;
+  if (!spec || !*spec) return true;
+  const char* at = std::strchr(spec, '@');
+  if (!at) return false;
+  const std::string what(spec, (size_t)(at - spec));
+  char* end = nullptr;
+  const long long k = std::strtoll(at + 1, &end, 10);
+  if (!end || end == at + 1 || *end != '\0' || k < 1) return false;
+  if (what == "alloc")
+    *kind = pdx::kFaultAlloc;
+  else if (what == "launch")
+    *kind = pdx::kFaultLaunch;
+  else
+    return false;
+  *left = k;
+  return true;
+}
 }  // namespace
 
 namespace pdx {
@@ -34,6 +64,23 @@ pd_status set_error(pd_status s, const char* fmt, ...) {
   va_end(ap);
   g_error = buf;
   return s;
+}
+
+bool fault_now(FaultKind kind) {
+  std::lock_guard<std::mutex> lock(g_fault_mu);
+  if (!g_fault_read) {
+    g_fault_read = true;
+    if (!parse_fault(std::getenv("PD_FAULT"), &g_fault_kind, &g_fault_left)) g_fault_kind = -1;
+  }
+  if (g_fault_kind != (int)kind) return false;
+  if (--g_fault_left > 0) return false;
+  g_fault_kind = -1;
+  return true;
+}
+
+hipError_t device_malloc(void** p, size_t bytes) {
+  if (fault_now(kFaultAlloc)) return hipErrorOutOfMemory;
+  return hipMalloc(p, bytes);
 }
 
 pd_status hip_error(hipError_t e, const char* what) {
@@ -61,7 +108,7 @@ pd_status grid_state_buffer(pd_grid g, void** out) {
     return PD_OK;
   }
   if (!g->d_state_own) {
-    hipError_t e = hipMalloc(&g->d_state_own, g->state_bytes());
+    hipError_t e = device_malloc(&g->d_state_own, g->state_bytes());
     if (e != hipSuccess) return hip_error(e, "hipMalloc(state)");
   }
   *out = g->d_state_own;
@@ -201,6 +248,18 @@ const char* pd_last_error(void) { return g_error.c_str(); }
 
 const char* pd_version(void) { return "libpd 0.1.0 gfx950"; }
 
+pd_status pd_set_fault(const char* spec) {
+  int kind = -1;
+  long long left = 0;
+  if (!parse_fault(spec, &kind, &left))
+    return fail(PD_ERR_INVALID, "fault spec must be \"alloc@K\" or \"launch@K\" with K >= 1, got \"%s\"", spec);
+  std::lock_guard<std::mutex> lock(g_fault_mu);
+  g_fault_read = true;  // the call replaces whatever PD_FAULT armed
+  g_fault_kind = kind;
+  g_fault_left = left;
+  return ok();
+}
+
 pd_status pd_create_grid(int nx, int ny, double px_min, double px_max, double py_min, double py_max, int precision,
                          int scheme, pd_grid* out) {
   if (!out) return fail(PD_ERR_INVALID, "null output handle pointer");
@@ -332,7 +391,7 @@ pd_status pd_set_field(pd_grid g, const pd_field* f, long long n_steps) {
   if (rows.size() > g->table_capacity) {
     release(g->d_table);
     g->table_bytes = g->table_capacity = 0;
-    e = hipMalloc(&g->d_table, rows.size());
+    e = device_malloc(&g->d_table, rows.size());
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(field table)");
     g->table_capacity = rows.size();
   }
@@ -341,13 +400,13 @@ pd_status pd_set_field(pd_grid g, const pd_field* f, long long n_steps) {
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(field table)");
   long long npts = g->grid.points();
   if (!g->d_n) {
-    e = hipMalloc(&g->d_n, (size_t)npts * sizeof(double));
+    e = device_malloc(reinterpret_cast<void**>(&g->d_n), (size_t)npts * sizeof(double));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(n)");
   }
   if (!g->d_partial) {
-    e = hipMalloc(&g->d_partial, (size_t)density_partials(npts) * sizeof(double));
+    e = device_malloc(reinterpret_cast<void**>(&g->d_partial), (size_t)density_partials(npts) * sizeof(double));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(partials)");
-    e = hipMalloc(&g->d_rho, sizeof(double));
+    e = device_malloc(reinterpret_cast<void**>(&g->d_rho), sizeof(double));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(rho)");
   }
   g->field = std::move(t);
@@ -450,6 +509,7 @@ pd_status pd_propagate(pd_grid g, long long max_steps, void* stream) {
     if (s != PD_OK) return s;
   }
   const SolveParams p = g->solve_params(k_begin, k_end, st);
+  if (fault_now(kFaultLaunch)) return fail(PD_ERR_DEVICE, "injected launch fault (PD_FAULT)");
   hipError_t e = launch_propagate(g->scheme, g->precision, g->points_per_lane, g->block_threads, g->taylor,
                                   g->field.elliptic ? 1 : 0, p, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "propagate launch");

@@ -327,6 +327,15 @@ struct DeviceScope {
 // Error reporting shared by the C entry points (pd_api.cpp).
 pd_status set_error(pd_status s, const char* fmt, ...);
 pd_status hip_error(hipError_t e, const char* what);
+
+// Test hook for the error paths: PD_FAULT (read at the first query) or pd_set_fault
+// arms one fault, "alloc@K" or "launch@K": the K-th device allocation, or the K-th
+// launch sequence (pd_propagate, a batch run or epoch), counted from the arming, fails
+// once, before anything is enqueued.
+enum FaultKind { kFaultAlloc = 0, kFaultLaunch = 1 };
+bool fault_now(FaultKind kind);
+// hipMalloc, or hipErrorOutOfMemory when an allocation fault is due
+hipError_t device_malloc(void** p, size_t bytes);
 // The chunk state buffer of a handle, allocated on first use.
 pd_status grid_state_buffer(pd_grid g, void** out);
 // Note work just enqueued on `stream` that uses g's device buffers (the handle's

@@ -16,7 +16,9 @@ than the whole budget is rejected.  Latency is the time from a request's arrival
 to its density being on the host.  A request withdrawn by the client (Server.cancel,
 or its cancel_s) or past its deadline_s leaves at the next epoch boundary, queued or
 part-way through, with status "cancelled" or "expired"; its memory goes back to the
-budget and its handle is kept like a finished one.
+budget and its handle is kept like a finished one.  If an epoch's launch fails (the
+library reports it; nothing was advanced), the solves planned in it leave with status
+"failed" and their handles are closed; the others go on.
 
 How an epoch shares the device is the policy:
   lockstep  every active solve advances `epoch_steps` steps;
@@ -265,10 +267,10 @@ class GpuExecutor:
                 done.append((name, float(rho[i])))
         return done
 
-    def abandon(self, name: str):
-        """Drop an admitted request that will not complete (cancelled or expired): a set-up
-        still in flight is waited for; the handle leaves the batch and is kept for a later
-        request of its shape (set up again from step 0) or closed."""
+    def abandon(self, name: str, keep: bool = True):
+        """Drop an admitted request that will not complete (cancelled, expired, or failed): a
+        set-up still in flight is waited for; the handle leaves the batch and, with keep, is
+        kept for a later request of its shape (set up again from step 0), else closed."""
         if name in self.setting_up:
             s, key, n_steps, fut = self.setting_up.pop(name)
             if fut.exception() is not None:
@@ -282,7 +284,7 @@ class GpuExecutor:
             if name in self.joined:
                 self.joined.remove(name)
             self.batch.remove(s)
-        if not self.idle.put(key, s, int(s.info()["device_bytes"])):
+        if not (keep and self.idle.put(key, s, int(s.info()["device_bytes"]))):
             s.close()
 
     def release(self, name: str):
@@ -319,10 +321,12 @@ class FakeExecutor:
     epoch_overhead_s; rho is a fixed function of the request."""
 
     def __init__(self, rate_point_steps_per_s: float = 1e12, bytes_per_point: int = 40, tile_step_s: float = 0.0,
-                 epoch_overhead_s: float = 0.0, idle_per_shape: int = 0, setup_epochs: int = 0, refuse=None):
+                 epoch_overhead_s: float = 0.0, idle_per_shape: int = 0, setup_epochs: int = 0, refuse=None,
+                 fail_epochs=()):
         """setup_epochs > 0 models background set-up: an admitted request becomes ready
         (collect) only after that many epochs have run; refuse(request) -> True makes its
-        set-up fail."""
+        set-up fail; the epoch_each calls numbered in fail_epochs (from 1) raise, as a
+        failed launch would, advancing nothing."""
         self.rate = rate_point_steps_per_s
         self.bytes_per_point = bytes_per_point
         self.tile_step_s = tile_step_s
@@ -336,6 +340,8 @@ class FakeExecutor:
         self.refuse = refuse
         self.setting_up = collections.OrderedDict()  # name -> (request, epochs left)
         self.epochs_run = 0
+        self.fail_epochs = set(fail_epochs)
+        self.epoch_calls = 0
 
     @property
     def idle_bytes(self) -> int:
@@ -378,6 +384,9 @@ class FakeExecutor:
         return self.epoch_each({name: steps for name in self.active})
 
     def epoch_each(self, steps: dict):
+        self.epoch_calls += 1
+        if self.epoch_calls in self.fail_epochs:
+            raise RuntimeError("injected epoch failure")
         work = 0.0
         longest = 0
         done = []
@@ -399,14 +408,15 @@ class FakeExecutor:
         req = self.active.pop(name)[0]
         self.idle.put(shape_key(req), req, self.footprint(req))
 
-    def abandon(self, name: str):
+    def abandon(self, name: str, keep: bool = True):
         if name in self.setting_up:
             req = self.setting_up.pop(name)[0]
         else:
             req = self.active.pop(name)[0]
             if name in self.joined:
                 self.joined.remove(name)
-        self.idle.put(shape_key(req), req, self.footprint(req))
+        if keep:
+            self.idle.put(shape_key(req), req, self.footprint(req))
 
     def close(self):
         self.idle.clear()
@@ -427,6 +437,7 @@ class ServeStats:
     budget_bytes: int
     cancelled: int = 0
     expired: int = 0
+    failed: int = 0
 
     def as_dict(self) -> dict:
         return dataclasses.asdict(self)
@@ -495,16 +506,16 @@ class Server:
             return "expired", "deadline %.3f s after arrival passed" % r.deadline_s
         return None
 
-    def _retire(self, r: "Request", status: str, reason: str, now: float):
+    def _retire(self, r: "Request", status: str, reason: str, now: float, keep: bool = True):
         """An admitted request that will not complete leaves the batch; its memory goes back
-        to the budget."""
+        to the budget (keep: its handle is kept for reuse, else closed)."""
         name = r.name
         del self.left[name]
         self.ready.discard(name)
         self.waited.pop(name, None)
         self.active.pop(name)
         self.in_use -= r.bytes
-        self.ex.abandon(name)
+        self.ex.abandon(name, keep=keep)
         r.status, r.reason, r.done_s = status, reason, now
 
     def plan_epoch(self) -> dict:
@@ -640,7 +651,16 @@ class Server:
                     raise RuntimeError("a waiting request can never be admitted")
                 break
             plan = self.plan_epoch()
-            done = self.ex.epoch_each(plan)
+            try:
+                done = self.ex.epoch_each(plan)
+            except Exception as e:  # the epoch's launch failed and advanced nothing
+                # its planned members are retired as failed and their handles closed (after a
+                # real device fault their state cannot be trusted); the others go on
+                now = self._now(t0, simulated)
+                for name in plan:
+                    self._retire(self.active[name], "failed", "epoch failed: %s" % e, now, keep=False)
+                epochs += 1
+                continue
             for name in self.ready:
                 self.waited[name] = 0 if plan.get(name, 0) > 0 else self.waited.get(name, 0) + 1
             for name, m in plan.items():
@@ -668,6 +688,7 @@ class Server:
         return ServeStats(completed=len(done), rejected=sum(r.status == "rejected" for r in reqs),
                           cancelled=sum(r.status == "cancelled" for r in reqs),
                           expired=sum(r.status == "expired" for r in reqs),
+                          failed=sum(r.status == "failed" for r in reqs),
                           makespan_s=makespan, p50_ms=float(np.percentile(lat, 50)),
                           p99_ms=float(np.percentile(lat, 99)), mean_ms=float(lat.mean()),
                           point_steps_per_s=sum(r.point_steps for r in done) / makespan, epochs=epochs,

@@ -419,3 +419,18 @@ def test_precision_values():
         s.close()
     h = _lib._vp()
     assert _lib.load().pd_create_grid(8, 8, -1.0, 1.0, -1.0, 1.0, 3, 0, ctypes.byref(h)) == _lib.PD_ERR_INVALID
+
+
+@pytest.mark.parametrize("spec,ok", [("alloc@1", True), ("launch@3", True), ("alloc@1000000", True), ("", True),
+                                     (None, True), ("alloc", False), ("alloc@0", False), ("launch@-2", False),
+                                     ("launch@", False), ("launch@2x", False), ("free@1", False), ("@1", False)])
+def test_fault_spec(spec, ok):
+    """pd_set_fault arms "alloc@K" / "launch@K" (K >= 1) and disarms on NULL or ""; any other
+    text is PD_ERR_INVALID with a message naming the accepted forms (host-side only)."""
+    lib = pd.require_native()
+    st = lib.pd_set_fault(spec.encode() if spec is not None else None)
+    if ok:
+        assert st == _lib.PD_OK
+    else:
+        assert st == _lib.PD_ERR_INVALID and "alloc@K" in lib.pd_last_error().decode()
+    assert lib.pd_set_fault(None) == _lib.PD_OK  # disarm for the other tests

@@ -403,3 +403,28 @@ def test_cancel_during_background_set_up():
     st = srv.run(reqs, simulated=True)
     assert [r.status for r in reqs] == ["done", "cancelled", "done"]
     assert st.cancelled == 1 and srv.in_use == 0 and not ex.setting_up and not ex.active
+
+
+@pytest.mark.parametrize("policy", ["srpt", "lockstep"])
+def test_failed_epochs_retire_their_members_only(policy):
+    """Epochs whose launch fails (they advance nothing) retire the solves planned in them
+    with status "failed" and close their handles; every other request completes with its
+    full work, and the memory returns to the budget."""
+    reqs = stream(count=24, rate=500.0)
+    ex = serve.FakeExecutor(rate_point_steps_per_s=2e10, idle_per_shape=2, fail_epochs={3, 10})
+    planned = []
+    orig = ex.epoch_each
+
+    def spy(steps):
+        planned.append(sorted(n for n, m in steps.items() if m > 0))
+        return orig(steps)
+    ex.epoch_each = spy
+    budget = 4 * max(ex.footprint(r) for r in reqs)
+    srv = serve.Server(ex, budget, epoch_steps=512, policy=policy, epoch_ms=0.5, rates={"fp32": 2e10, "fp64": 2e10})
+    st = srv.run(reqs, simulated=True)
+    failed = {r.name for r in reqs if r.status == "failed"}
+    assert failed == set(planned[2]) | set(planned[9]) and failed
+    assert st.failed == len(failed) and st.completed == len(reqs) - len(failed)
+    assert all(r.status == "done" for r in reqs if r.name not in failed)
+    assert all("injected epoch failure" in r.reason for r in reqs if r.name in failed)
+    assert srv.in_use == 0 and not srv.active and not ex.active
