@@ -415,6 +415,13 @@ const char* pd_version(void);
    PD_ERR_INVALID for any other text.  Process-wide. */
 pd_status pd_set_fault(const char* spec);
 
+/* Environment: PD_TRACE (set and not "0") makes pd_set_field, pd_propagate,
+   pd_density, pd_density_static, pd_snapshot, pd_autotune and the batch run, step
+   and autotune calls each write "pd_trace <name> <ms> ms" to stderr as they return:
+   the host time of the call (launches are asynchronous; a call that waits for the
+   device includes the wait).  PD_AUTOTUNE_CACHE names the autotuner's cache file
+   (pd_autotune). */
+
 #ifdef __cplusplus
 }
 #endif

@@ -106,6 +106,7 @@ pd_status time_best(F run, hipStream_t st, int reps, float* best_ms) {
 extern "C" {
 
 pd_status pd_autotune(pd_grid g, long long trial_steps, int use_cache, void* stream) {
+  TraceCall trace("pd_autotune");
   if (!g) return set_error(PD_ERR_INVALID, "null handle");
   if (!g->field_set) return set_error(PD_ERR_STATE, "pd_autotune before pd_set_field");
   if (trial_steps < 1) return set_error(PD_ERR_INVALID, "trial_steps must be >= 1");
@@ -151,6 +152,7 @@ pd_status pd_autotune(pd_grid g, long long trial_steps, int use_cache, void* str
 }
 
 pd_status pd_batch_autotune(pd_batch b, long long trial_steps, void* stream) {
+  TraceCall trace("pd_batch_autotune");
   if (!b) return set_error(PD_ERR_INVALID, "null handle");
   if (trial_steps < 1) return set_error(PD_ERR_INVALID, "trial_steps must be >= 1");
   const int n = pd_batch_size(b);

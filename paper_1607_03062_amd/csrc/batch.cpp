@@ -428,6 +428,7 @@ pd_status pd_batch_set_launch(pd_batch b, int points_per_lane, int block_threads
 }
 
 pd_status pd_batch_run(pd_batch b, double* rho_out, void* stream) {
+  TraceCall trace("pd_batch_run");
   if (!b) return set_error(PD_ERR_INVALID, "null handle");
   pd_status s = PD_OK;
   if (!b->grids.empty() && b->device < 0 && b->grids[0]->field_set && (s = prepare_device(b)) != PD_OK) return s;
@@ -485,6 +486,7 @@ pd_status pd_batch_run(pd_batch b, double* rho_out, void* stream) {
 }
 
 pd_status pd_batch_step(pd_batch b, long long max_steps, double* rho_out, int* finished_out, void* stream) {
+  TraceCall trace("pd_batch_step");
   if (!b) return set_error(PD_ERR_INVALID, "null handle");
   if (max_steps < 1) return set_error(PD_ERR_INVALID, "max_steps must be >= 1");
   std::vector<long long> limits(b->grids.size(), max_steps);
@@ -493,6 +495,7 @@ pd_status pd_batch_step(pd_batch b, long long max_steps, double* rho_out, int* f
 
 pd_status pd_batch_step_each(pd_batch b, const long long* max_steps, double* rho_out, int* finished_out,
                              void* stream) {
+  TraceCall trace("pd_batch_step_each");
   if (!b) return set_error(PD_ERR_INVALID, "null handle");
   if (!max_steps && !b->grids.empty()) return set_error(PD_ERR_INVALID, "null max_steps");
   for (size_t i = 0; i < b->grids.size(); ++i)

@@ -78,6 +78,16 @@ bool fault_now(FaultKind kind) {
   return true;
 }
 
+bool trace_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("PD_TRACE");
+    return v && *v && std::strcmp(v, "0") != 0;
+  }();
+  return on;
+}
+
+void trace_line(const char* name, double ms) { std::fprintf(stderr, "pd_trace %s %.3f ms\n", name, ms); }
+
 hipError_t device_malloc(void** p, size_t bytes) {
   if (fault_now(kFaultAlloc)) return hipErrorOutOfMemory;
   return hipMalloc(p, bytes);
@@ -357,6 +367,7 @@ pd_status pd_set_valley(pd_grid g, int valley) {
 }
 
 pd_status pd_set_field(pd_grid g, const pd_field* f, long long n_steps) {
+  TraceCall trace("pd_set_field");
   FieldTables t;
   long long masked = 0;
   int taylor = 0, form = 0;
@@ -492,6 +503,7 @@ pd_status pd_rewind(pd_grid g) {
 }
 
 pd_status pd_propagate(pd_grid g, long long max_steps, void* stream) {
+  TraceCall trace("pd_propagate");
   if (!g) return fail(PD_ERR_INVALID, "null handle");
   if (!g->field_set) return fail(PD_ERR_STATE, "pd_propagate before pd_set_field");
   const long long N = g->field.n_steps;
@@ -550,6 +562,7 @@ pd_status reduce_and_copy(pd_grid g, double* n_out, int n_out_on_device, double*
 }  // namespace
 
 pd_status pd_density(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, void* stream) {
+  TraceCall trace("pd_density");
   if (!g) return fail(PD_ERR_INVALID, "null handle");
   if (!g->field_set || g->steps_done != g->field.n_steps)
     return fail(PD_ERR_STATE, "pd_density before the last step (%lld of %lld done)", g->steps_done,
@@ -560,6 +573,7 @@ pd_status pd_density(pd_grid g, double* n_out, int n_out_on_device, double* rho_
 }
 
 pd_status pd_density_static(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, void* stream) {
+  TraceCall trace("pd_density_static");
   if (!g) return fail(PD_ERR_INVALID, "null handle");
   const long long npts = g->grid.points();
   if (npts > kStaticMaxPoints)
@@ -609,6 +623,7 @@ pd_status pd_density_static(pd_grid g, double* n_out, int n_out_on_device, doubl
 }
 
 pd_status pd_snapshot(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, void* stream) {
+  TraceCall trace("pd_snapshot");
   if (!g) return fail(PD_ERR_INVALID, "null handle");
   if (!g->field_set) return fail(PD_ERR_STATE, "pd_snapshot before pd_set_field");
   DeviceScope scope(g->device);

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <chrono>
+
 #include <algorithm>
 #include <string>
 #include <thread>
@@ -336,6 +338,24 @@ enum FaultKind { kFaultAlloc = 0, kFaultLaunch = 1 };
 bool fault_now(FaultKind kind);
 // hipMalloc, or hipErrorOutOfMemory when an allocation fault is due
 hipError_t device_malloc(void** p, size_t bytes);
+
+// PD_TRACE (set and not "0"): every traced entry point writes one line to stderr as it
+// returns, "pd_trace <name> <ms> ms", with the host time spent in the call (launches
+// are asynchronous: the time a call waits for the device is included only where it
+// waits).  Read once per process.
+bool trace_on();
+void trace_line(const char* name, double ms);
+struct TraceCall {
+  const char* name;
+  bool on;
+  std::chrono::steady_clock::time_point t0;
+  explicit TraceCall(const char* n) : name(n), on(trace_on()) {
+    if (on) t0 = std::chrono::steady_clock::now();
+  }
+  ~TraceCall() {
+    if (on) trace_line(name, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+  }
+};
 // The chunk state buffer of a handle, allocated on first use.
 pd_status grid_state_buffer(pd_grid g, void** out);
 // Note work just enqueued on `stream` that uses g's device buffers (the handle's

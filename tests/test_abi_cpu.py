@@ -434,3 +434,22 @@ def test_fault_spec(spec, ok):
     else:
         assert st == _lib.PD_ERR_INVALID and "alloc@K" in lib.pd_last_error().decode()
     assert lib.pd_set_fault(None) == _lib.PD_OK  # disarm for the other tests
+
+
+def test_trace_lines_on_request():
+    """PD_TRACE=1 makes traced entry points write "pd_trace <name> <ms> ms" to stderr as
+    they return (here pd_set_field, which fails without a device); without it they write
+    nothing."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_1607_03062_amd as pd\n"
+            "from paper_1607_03062_amd import workloads as wl\n"
+            "s = pd.Solver.for_grid(wl.grid(8, 1.0), 'fp32')\n"
+            "try:\n    s.set_field(wl.sin2(0.1, 0.5, 2), 100)\nexcept Exception:\n    pass\n") % ROOT
+    env = dict(os.environ, HIP_VISIBLE_DEVICES="", PD_TRACE="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert re.search(r"^pd_trace pd_set_field [0-9.]+ ms$", out.stderr, flags=re.M), out.stderr
+    env["PD_TRACE"] = "0"
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert "pd_trace" not in out.stderr
