@@ -290,6 +290,30 @@ pd_status pd_bind_state(pd_grid g, void* dev_ptr, size_t bytes);
    solve's state gives that solve's continuation, not this one's. */
 pd_status pd_resume(pd_grid g, long long steps_done);
 
+/* Checkpoint to host memory: copy the state of a solve in progress (0 < steps
+   done < N, as a chunked pd_propagate left it) into the caller's host buffer of
+   `bytes` >= pd_state_bytes(g) bytes, and the number of steps it belongs to into
+   *steps_done (may be NULL).  The layout is the library's own, point index fastest
+   within each state component; it is valid only for a handle with the same grid,
+   field, step count, precision, scheme and valley.  The call waits for the
+   handle's earlier work, copies on `stream`, and returns when the copy is done.
+   PD_ERR_STATE if no solve is in progress; PD_ERR_INVALID for a null pointer or a
+   short buffer. */
+pd_status pd_save_state(pd_grid g, void* host, size_t bytes, long long* steps_done, void* stream);
+
+/* Restart from a checkpoint: after pd_set_field with the saved solve's field and
+   step count, copy the state saved by pd_save_state (exactly pd_state_bytes(g)
+   bytes) into the handle's state buffer (the bound one, else its own, allocated
+   here if needed) and continue as after steps_done steps: the rest of the solve is
+   bit-identical to the uninterrupted one (the state evolves step by step,
+   Sec. III, with every per-step choice keyed to the absolute step index).  The call
+   waits for the handle's earlier work, copies on `stream`, and returns when the
+   copy is done.  1 <= steps_done <= N - 1.  PD_ERR_STATE before pd_set_field;
+   PD_ERR_INVALID for a null pointer, a size other than the handle's state size or
+   steps_done out of range; PD_ERR_NOMEM if the state buffer cannot be allocated.
+   As with pd_resume, the content is the caller's responsibility. */
+pd_status pd_load_state(pd_grid g, const void* host, size_t bytes, long long steps_done, void* stream);
+
 /* Override the launch shape of the propagation kernel: points_per_lane in
    {1, 2, 4}; block_threads in {64, 128, 256}; table_stage 1 = the per-step
    field rows are staged through LDS in time chunks (read from VGPRs), 2 = read

@@ -3,6 +3,7 @@ runs in the library's HIP kernels).  Names follow include/pd.h."""
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -118,6 +119,8 @@ SIGNATURES = [
     ("pd_state_bytes", ctypes.c_size_t, [_vp]),
     ("pd_solve_bytes", ctypes.c_size_t, [_vp, ctypes.c_longlong]),
     ("pd_bind_state", ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    ("pd_save_state", ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_longlong), _vp]),
+    ("pd_load_state", ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_longlong, _vp]),
     ("pd_set_launch", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     ("pd_get_info", ctypes.c_int, [_vp, ctypes.POINTER(pd_info)]),
     ("pd_destroy_grid", None, [_vp]),
@@ -187,6 +190,10 @@ def stream_handle(stream) -> int | None:
     if isinstance(stream, int):
         return stream
     return int(stream.cuda_stream)
+
+
+def version_string() -> str:
+    return load().pd_version().decode()
 
 
 def set_fault(spec: str | None):
@@ -264,7 +271,9 @@ class Solver:
                                  PRECISIONS[precision], SCHEMES[scheme], ctypes.byref(h)), "pd_create_grid")
         self._h = h
         self.nx, self.ny = int(nx), int(ny)
-        self.precision, self.scheme = precision, scheme
+        self.px, self.py = (float(px[0]), float(px[1])), (float(py[0]), float(py[1]))
+        self.precision, self.scheme, self.valley = precision, scheme, "both"
+        self.field, self.n_steps = None, None
         if valley != "both":
             self.set_valley(valley)
 
@@ -274,6 +283,7 @@ class Solver:
 
     def set_valley(self, valley: str):
         check(load().pd_set_valley(self._h, VALLEYS[valley]), "pd_set_valley")
+        self.valley = valley
         return self
 
     @property
@@ -289,6 +299,7 @@ class Solver:
     def set_field(self, field: dict, n_steps: int):
         f, keep = make_field(field, n_steps)
         check(load().pd_set_field(self._h, ctypes.byref(f), int(n_steps)), "pd_set_field")
+        self.field, self.n_steps = field, int(n_steps)
         return self
 
     def rewind(self):
@@ -336,6 +347,72 @@ class Solver:
 
     def state_bytes(self) -> int:
         return int(load().pd_state_bytes(self._h))
+
+    def save_state(self, stream=None):
+        """(state bytes as a uint8 array, steps done) of the solve in progress (pd_save_state)."""
+        buf = np.empty(self.state_bytes(), dtype=np.uint8)
+        done = ctypes.c_longlong()
+        check(load().pd_save_state(self._h, buf.ctypes.data, buf.nbytes, ctypes.byref(done), stream_handle(stream)),
+              "pd_save_state")
+        return buf, done.value
+
+    def load_state(self, state, steps_done: int, stream=None):
+        """Continue as after steps_done steps from a state saved by save_state (pd_load_state)."""
+        buf = np.ascontiguousarray(state, dtype=np.uint8)
+        check(load().pd_load_state(self._h, buf.ctypes.data, buf.nbytes, int(steps_done), stream_handle(stream)),
+              "pd_load_state")
+        return self
+
+    def _checkpoint_meta(self) -> dict:
+        return {"grid": {"nx": self.nx, "ny": self.ny, "px": list(self.px), "py": list(self.py)},
+                "precision": self.precision, "scheme": self.scheme, "valley": self.valley}
+
+    def save_checkpoint(self, path, stream=None):
+        """Write the solve in progress to `path` (.npz, no pickled objects): its state after
+        the steps done so far, with the grid, precision, scheme, valley, field and step count
+        it belongs to.  Restart it with Solver.from_checkpoint or load_checkpoint."""
+        if self.field is None:
+            raise PDError(PD_ERR_STATE, "save_checkpoint", "no field set")
+        state, done = self.save_state(stream)
+        scalars = {k: v for k, v in self.field.items() if k not in ("A_mid", "Ay_mid")}
+        meta = dict(self._checkpoint_meta(), field=scalars, n_steps=self.n_steps, steps_done=done,
+                    library=version_string())
+        arrays = {"state": state, "meta": np.array(json.dumps(meta, default=float))}
+        for k in ("A_mid", "Ay_mid"):
+            if self.field.get(k) is not None:
+                arrays[k] = np.ascontiguousarray(self.field[k], dtype=np.float64)
+        with open(path, "wb") as fh:
+            np.savez(fh, **arrays)
+        return done
+
+    @staticmethod
+    def _read_checkpoint(path):
+        with np.load(path, allow_pickle=False) as z:
+            meta = json.loads(str(z["meta"]))
+            field = dict(meta["field"])
+            for k in ("A_mid", "Ay_mid"):
+                if k in z.files:
+                    field[k] = z[k]
+            return meta, field, z["state"]
+
+    def load_checkpoint(self, path, stream=None):
+        """Set the checkpoint's field on this handle (same grid, precision, scheme and valley
+        as the saved solve, else PDError) and continue from its state."""
+        meta, field, state = self._read_checkpoint(path)
+        mine = self._checkpoint_meta()
+        for key in mine:
+            if meta[key] != mine[key]:
+                raise PDError(PD_ERR_INVALID, "load_checkpoint",
+                              "checkpoint %s %r does not match the handle's %r" % (key, meta[key], mine[key]))
+        self.set_field(field, meta["n_steps"])
+        return self.load_state(state, meta["steps_done"], stream)
+
+    @classmethod
+    def from_checkpoint(cls, path, stream=None):
+        """A new handle that continues the solve saved in `path`."""
+        meta = cls._read_checkpoint(path)[0]
+        return cls.for_grid(meta["grid"], meta["precision"], meta["scheme"], meta["valley"]).load_checkpoint(
+            path, stream)
 
     def solve_bytes(self, n_steps: int) -> int:
         return int(load().pd_solve_bytes(self._h, int(n_steps)))

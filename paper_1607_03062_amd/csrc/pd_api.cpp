@@ -179,6 +179,21 @@ pd_status fail(pd_status s, const char* fmt, A... a) {
 pd_status ok() { return PD_OK; }
 pd_status hip_fail(hipError_t e, const char* what) { return hip_error(e, what); }
 
+// Wait for the handle's earlier work: its completion event, or the whole device if
+// that work was enqueued under stream capture (no event could be recorded then).
+pd_status wait_own_work(pd_grid g) {
+  hipError_t e = hipSuccess;
+  if (g->wait_device) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    g->wait_device = false;
+  } else if (g->last_use) {
+    e = hipEventSynchronize(g->last_use);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  }
+  return PD_OK;
+}
+
 void release(void*& p) {
   if (p) (void)hipFree(p);
   p = nullptr;
@@ -388,16 +403,8 @@ pd_status pd_set_field(pd_grid g, const pd_field* f, long long n_steps) {
   DeviceScope scope(g->device);
   if (!scope.ok) return fail(PD_ERR_DEVICE, "cannot select device %d", g->device);
   hipError_t e;
-  // Work of an earlier solve on this handle may still read the table or the state:
-  // wait for it (for the whole device only if it was enqueued under stream capture).
-  if (g->wait_device) {
-    e = hipDeviceSynchronize();
-    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    g->wait_device = false;
-  } else if (g->last_use) {
-    e = hipEventSynchronize(g->last_use);
-    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-  }
+  // Work of an earlier solve on this handle may still read the table or the state.
+  if ((s = wait_own_work(g)) != PD_OK) return s;
   g->field_set = false;
   if (rows.size() > g->table_capacity) {
     release(g->d_table);
@@ -470,6 +477,53 @@ pd_status pd_resume(pd_grid g, long long steps_done) {
   if (!g->d_state_bound) return fail(PD_ERR_STATE, "pd_resume needs a state buffer bound with pd_bind_state");
   if (steps_done < 1 || steps_done >= g->field.n_steps)
     return fail(PD_ERR_INVALID, "steps_done = %lld outside 1 .. N - 1 (N = %lld)", steps_done, g->field.n_steps);
+  g->steps_done = steps_done;
+  return ok();
+}
+
+pd_status pd_save_state(pd_grid g, void* host, size_t bytes, long long* steps_done, void* stream) {
+  TraceCall trace("pd_save_state");
+  if (!g || !host) return fail(PD_ERR_INVALID, "null argument");
+  if (!g->field_set || g->steps_done == 0 || g->steps_done == g->field.n_steps)
+    return fail(PD_ERR_STATE, "pd_save_state: no solve in progress (%lld of %lld steps done)", g->steps_done,
+                g->field_set ? g->field.n_steps : 0LL);
+  if (bytes < g->state_bytes())
+    return fail(PD_ERR_INVALID, "host buffer of %zu bytes is smaller than the %zu-byte state", bytes, g->state_bytes());
+  DeviceScope scope(g->device);
+  if (!scope.ok) return fail(PD_ERR_DEVICE, "cannot select device %d", g->device);
+  // 0 < steps done < N: the last propagation wrote the state buffer in use
+  void* st = g->d_state_bound ? g->d_state_bound : g->d_state_own;
+  if (!st) return fail(PD_ERR_STATE, "pd_save_state: the handle holds no state");
+  pd_status s = wait_own_work(g);
+  if (s != PD_OK) return s;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(host, st, g->state_bytes(), hipMemcpyDeviceToHost, hs);
+  if (e != hipSuccess) return hip_fail(e, "copy of the state");
+  if ((e = hipStreamSynchronize(hs)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  if (steps_done) *steps_done = g->steps_done;
+  return ok();
+}
+
+pd_status pd_load_state(pd_grid g, const void* host, size_t bytes, long long steps_done, void* stream) {
+  TraceCall trace("pd_load_state");
+  if (!g || !host) return fail(PD_ERR_INVALID, "null argument");
+  if (!g->field_set) return fail(PD_ERR_STATE, "pd_load_state before pd_set_field");
+  if (steps_done < 1 || steps_done >= g->field.n_steps)
+    return fail(PD_ERR_INVALID, "steps_done = %lld outside 1 .. N - 1 (N = %lld)", steps_done, g->field.n_steps);
+  if (bytes != g->state_bytes())
+    return fail(PD_ERR_INVALID, "state of %zu bytes, the handle's is %zu (another grid, precision or scheme?)", bytes,
+                g->state_bytes());
+  DeviceScope scope(g->device);
+  if (!scope.ok) return fail(PD_ERR_DEVICE, "cannot select device %d", g->device);
+  // earlier work on the handle may still read or write the state buffer
+  pd_status s = wait_own_work(g);
+  if (s != PD_OK) return s;
+  void* st = nullptr;
+  if ((s = grid_state_buffer(g, &st)) != PD_OK) return s;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(st, host, bytes, hipMemcpyHostToDevice, hs);
+  if (e != hipSuccess) return hip_fail(e, "copy of the state");
+  if ((e = hipStreamSynchronize(hs)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   g->steps_done = steps_done;
   return ok();
 }

@@ -130,6 +130,15 @@ static void check_grids(void) {
       expect(pd_bind_state(g, (void*)(size_t)4096, 16) == PD_ERR_INVALID, "state buffer too small rejected");
       expect(pd_bind_state(g, NULL, 0) == PD_OK, "binding NULL unbinds");
       expect(pd_resume(g, 5) == PD_ERR_STATE, "resume before a field");
+      {
+        static unsigned char host[33 * 17 * 4 * 8];
+        long long done = -1;
+        expect(pd_save_state(g, host, sizeof host, &done, NULL) == PD_ERR_STATE && done == -1,
+               "save before a field");
+        expect(pd_save_state(g, NULL, sizeof host, &done, NULL) == PD_ERR_INVALID, "save to NULL");
+        expect(pd_load_state(g, host, pd_state_bytes(g), 5, NULL) == PD_ERR_STATE, "load before a field");
+        expect(pd_load_state(g, NULL, pd_state_bytes(g), 5, NULL) == PD_ERR_INVALID, "load from NULL");
+      }
       expect(pd_rewind(g) == PD_ERR_STATE, "rewind before a field");
       expect(pd_density(g, NULL, 0, NULL, NULL) != PD_OK, "density before a field");
       expect(pd_get_info(g, NULL) == PD_ERR_INVALID, "NULL info to pd_get_info");

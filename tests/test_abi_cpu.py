@@ -3,6 +3,7 @@ exports every entry point declared in include/pd.h, validates its arguments,
 samples the field like the oracle does, and reports device failures as
 status codes."""
 import ctypes
+import json
 import math
 import os
 import re
@@ -101,6 +102,9 @@ def test_null_handles():
     assert lib.pd_density(None, None, 0, None, None) == _lib.PD_ERR_INVALID
     assert lib.pd_density_static(None, None, 0, None, None) == _lib.PD_ERR_INVALID
     assert lib.pd_state_bytes(None) == 0
+    buf = np.zeros(64, dtype=np.uint8)
+    assert lib.pd_save_state(None, buf.ctypes.data, 64, None, None) == _lib.PD_ERR_INVALID
+    assert lib.pd_load_state(None, buf.ctypes.data, 64, 1, None) == _lib.PD_ERR_INVALID
     lib.pd_destroy_grid(None)
 
 
@@ -279,6 +283,12 @@ def test_state_errors_without_device():
     with pytest.raises(pd.PDError) as e:
         s.resume(10)  # before pd_set_field
     assert e.value.status == _lib.PD_ERR_STATE and "pd_set_field" in e.value.message
+    with pytest.raises(pd.PDError) as e:
+        s.save_state()  # no solve in progress
+    assert e.value.status == _lib.PD_ERR_STATE
+    with pytest.raises(pd.PDError) as e:
+        s.load_state(np.zeros(s.state_bytes(), dtype=np.uint8), 10)  # before pd_set_field
+    assert e.value.status == _lib.PD_ERR_STATE
     s.set_launch(4, 64, 1, 256)
     info = s.info()
     assert (info["points_per_lane"], info["block_threads"], info["table_stage"], info["chunk_steps"]) == (4, 64, 1, 256)
@@ -453,3 +463,28 @@ def test_trace_lines_on_request():
     env["PD_TRACE"] = "0"
     out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
     assert "pd_trace" not in out.stderr
+
+
+def test_checkpoint_file_is_checked_before_any_device_work(tmp_path):
+    """A checkpoint file is plain .npz (no pickled objects); load_checkpoint refuses one
+    written for another grid, precision, scheme or valley before it touches the device."""
+    meta = {"grid": {"nx": 8, "ny": 8, "px": [-1.0, 1.0], "py": [-1.0, 1.0]}, "precision": "fp32",
+            "scheme": "strang", "valley": "both", "field": wl.sin2(0.1, 0.5, 8), "n_steps": 4000,
+            "steps_done": 100}
+    path = tmp_path / "ck.npz"
+    with open(path, "wb") as fh:
+        np.savez(fh, state=np.zeros(8 * 8 * 3 * 4, dtype=np.uint8), meta=np.array(json.dumps(meta)))
+    with np.load(path, allow_pickle=False) as z:
+        assert json.loads(str(z["meta"]))["steps_done"] == 100
+    for kwargs in ({"precision": "fp64"}, {"scheme": "midpoint"}, {"valley": "K-"}):
+        args = dict({"precision": "fp32", "scheme": "strang", "valley": "both"}, **kwargs)
+        s = pd.Solver(8, 8, (-1, 1), (-1, 1), **args)
+        with pytest.raises(pd.PDError) as e:
+            s.load_checkpoint(path)
+        assert e.value.status == _lib.PD_ERR_INVALID and "does not match" in e.value.message
+        s.close()
+    s = pd.Solver(8, 9, (-1, 1), (-1, 1), "fp32")
+    with pytest.raises(pd.PDError) as e:
+        s.load_checkpoint(path)
+    assert "grid" in e.value.message
+    s.close()

@@ -194,6 +194,78 @@ def test_checkpoint_and_resume(gpu, precision, scheme, N, k):
     assert np.array_equal(n, single[0]) and rho == single[1]
 
 
+@pytest.mark.parametrize("precision,scheme,field_kind,valley,N,k", [
+    ("fp64", "strang", "sin2", "both", 2777, 1500), ("fp32", "midpoint", "sin2", "K-", 2600, 1031),
+    ("fp32", "strang4", "elliptic", "both", 600, 333), ("fp32fast", "strang", "table", "K+", 3000, 2049)])
+def test_checkpoint_file_restart(gpu, tmp_path, precision, scheme, field_kind, valley, N, k):
+    """save_checkpoint after k steps writes the state (pd_save_state) with the solve's grid,
+    precision, scheme, valley and field to an .npz file; the handle is closed; a new handle
+    from the file (pd_load_state) finishes the solve: n(p) and rho bit-identical to the
+    uninterrupted solve, which matches the oracle.  A second restart loads the same file
+    into an existing handle with a caller-bound state buffer.  A handle of another precision
+    refuses the file; a state of the wrong size and a step count outside 1 .. N - 1 are
+    refused by the library."""
+    import torch
+
+    if field_kind == "table":
+        t_f = 3 * 2 * math.pi / 0.6
+        tt = (np.arange(N) + 0.5) * t_f / N
+        field = {"kind": "table", "A_mid": 0.2 * np.sin(0.5 * tt) * np.sin(math.pi * tt / t_f) ** 2,
+                 "t_i": 0.0, "t_f": t_f, "A_in": 0.0, "A_out": 0.0}
+    else:
+        field = dict(RAGGED_FIELD, ellipticity=0.5) if field_kind == "elliptic" else RAGGED_FIELD
+    print("checkpoint file: %s %s %s %s N=%d k=%d" % (precision, scheme, field_kind, valley, N, k), flush=True)
+    s0 = gpu.Solver.for_grid(RAGGED, precision, scheme, valley).set_field(field, N)
+    s0.propagate(-1)
+    n_single = np.empty(RAGGED["nx"] * RAGGED["ny"])
+    rho_single = s0.density(n_out=n_single)
+    s0.close()
+    vsign = -1 if valley == "K-" else 1
+    if scheme != "strang4":
+        n_o = oracle.solve_grid(field, RAGGED, N, scheme, valley=vsign)[0]
+        assert np.max(np.abs(n_single - n_o)) <= (FP64_N_ABS if precision == "fp64" else FP32_N_ABS)
+
+    s = gpu.Solver.for_grid(RAGGED, precision, scheme, valley).set_field(field, N)
+    with pytest.raises(gpu.PDError):
+        s.save_checkpoint(tmp_path / "early.npz")  # nothing to save before the first step
+    s.propagate(k)
+    path = tmp_path / "ck.npz"
+    assert s.save_checkpoint(path) == k
+    state, done = s.save_state()
+    s.close()
+    assert done == k and state.nbytes == RAGGED["nx"] * RAGGED["ny"] * (3 if "strang" in scheme else 4) * (
+        8 if precision == "fp64" else 4)
+
+    r = gpu.Solver.from_checkpoint(path)
+    assert r.info()["steps_done"] == k and r.valley == valley and r.precision == precision
+    r.propagate(-1)
+    n = np.empty_like(n_single)
+    rho = r.density(n_out=n)
+    r.close()
+    assert np.array_equal(n, n_single) and rho == rho_single
+
+    q = gpu.Solver.for_grid(RAGGED, precision, scheme, valley)
+    buf = torch.zeros(state.nbytes // 4 + 64, dtype=torch.float32, device="cuda")
+    q.bind_state(buf)
+    q.load_checkpoint(path)
+    for bad_k in (0, N):
+        with pytest.raises(gpu.PDError):
+            q.load_state(state, bad_k)
+    with pytest.raises(gpu.PDError):
+        q.load_state(state[:-4], k)
+    q.propagate(700)
+    q.propagate(-1)
+    n2 = np.empty_like(n_single)
+    rho2 = q.density(n_out=n2)
+    q.close()
+    assert np.array_equal(n2, n_single) and rho2 == rho_single
+
+    other = gpu.Solver.for_grid(RAGGED, "fp64" if precision != "fp64" else "fp32", scheme, valley)
+    with pytest.raises(gpu.PDError):
+        other.load_checkpoint(path)
+    other.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_midpoint_step_forms(gpu, precision):
     """Both forms of the midpoint step match the oracle: the tangent form (step angles
