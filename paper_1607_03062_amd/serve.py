@@ -17,8 +17,13 @@ to its density being on the host.  A request withdrawn by the client (Server.can
 or its cancel_s) or past its deadline_s leaves at the next epoch boundary, queued or
 part-way through, with status "cancelled" or "expired"; its memory goes back to the
 budget and its handle is kept like a finished one.  If an epoch's launch fails (the
-library reports it; nothing was advanced), the solves planned in it leave with status
-"failed" and their handles are closed; the others go on.
+library reports it; nothing was advanced), the solves planned in it lose their handles
+(after a real device fault their device state cannot be trusted); each is queued again,
+ahead of later arrivals, while it has retries left (`max_retries`), else it leaves with
+status "failed"; the others go on.  A retried solve restarts from its last checkpoint
+(with `checkpoint_every_s`, the server copies each active solve's state to host memory,
+pd_save_state, at most that often), else from step 0; either way its result is the
+uninterrupted solve's, bit for bit.
 
 How an epoch shares the device is the policy:
   lockstep  every active solve advances `epoch_steps` steps;
@@ -34,7 +39,7 @@ How an epoch shares the device is the policy:
 
 The device work is in libpd; this module is the host-side scheduler.  The
 executor interface (footprint / reserve / admit / collect / epoch_each / release /
-abandon, and
+abandon / checkpoint, and
 idle_bytes: the memory of kept handles) has a GPU implementation over the C ABI
 and a CPU fake with a cost model, used to test the scheduling without a GPU.
 """
@@ -69,6 +74,12 @@ class Request:
     bytes: int = 0
     status: str = "pending"
     reason: str = ""
+    retries: int = 0  # failed epochs survived
+    # the last checkpoint: (state bytes on the host, steps done), or None; a retry resumes
+    # from it; resumed_from is the step the last admission started at
+    checkpoint: tuple = None
+    checkpoint_s: float = float("-inf")
+    resumed_from: int = 0
 
     @property
     def points(self) -> int:
@@ -209,23 +220,38 @@ class GpuExecutor:
             s = self.pd.Solver.for_grid(req.grid, req.precision, req.scheme, req.valley)
         else:
             self.reused += 1
+        left = req.n_steps - (req.checkpoint[1] if req.checkpoint else 0)
         if self._pool is not None and background:
-            self.setting_up[req.name] = (s, key, req.n_steps, self._pool.submit(s.set_field, req.field, req.n_steps))
+            self.setting_up[req.name] = (s, key, left, self._pool.submit(self._set_up, s, req))
             return
         try:
-            s.set_field(req.field, req.n_steps)
+            self._set_up(s, req)
         except Exception:
             s.close()
             raise
-        self._join(req.name, s, key, req.n_steps)
+        self._join(req.name, s, key, left)
 
-    def _join(self, name, s, key, n_steps):
+    def _set_up(self, s, req: Request):
+        """The field; then, for a request that resumes, its checkpointed state (pd_load_state)."""
+        s.set_field(req.field, req.n_steps)
+        if req.checkpoint:
+            s.load_state(req.checkpoint[0], req.checkpoint[1], self.stream)
+
+    def _join(self, name, s, key, left):
         self.solvers[name] = s
         self.keys[name] = key
         self.order.append(name)
-        self.left[name] = n_steps
+        self.left[name] = left
         self.batch.add(s)
         self.joined.append(name)
+
+    def checkpoint(self, name: str):
+        """(state bytes on the host, steps done) of an active solve part-way through, or None
+        (pd_save_state: waits for the solve's enqueued epochs)."""
+        s = self.solvers.get(name)
+        if s is None or not 0 < s.n_steps - self.left[name] < s.n_steps:
+            return None
+        return s.save_state(self.stream)
 
     def collect(self, block: bool = False):
         """Requests whose set-up has finished since the last call, joined to the batch in
@@ -359,8 +385,14 @@ class FakeExecutor:
         if self.setup_epochs > 0 or self.refuse is not None:
             self.setting_up[req.name] = (req, self.setup_epochs)
             return
-        self.active[req.name] = [req, 0]
+        self.active[req.name] = [req, req.checkpoint[1] if req.checkpoint else 0]
         self.joined.append(req.name)
+
+    def checkpoint(self, name: str):
+        entry = self.active.get(name)
+        if entry is None or not 0 < entry[1] < entry[0].n_steps:
+            return None
+        return (None, entry[1])
 
     def collect(self, block: bool = False):
         """Requests whose (modelled) set-up has finished, in admission order; block: the
@@ -374,7 +406,7 @@ class FakeExecutor:
             if self.refuse is not None and self.refuse(req):
                 failed.append((name, RuntimeError("set-up refused")))
             else:
-                self.active[name] = [req, 0]
+                self.active[name] = [req, req.checkpoint[1] if req.checkpoint else 0]
                 self.joined.append(name)
         ready = list(self.joined)
         self.joined.clear()
@@ -438,6 +470,8 @@ class ServeStats:
     cancelled: int = 0
     expired: int = 0
     failed: int = 0
+    retried: int = 0      # solves queued again after a failed epoch
+    checkpoints: int = 0  # states copied to host memory
 
     def as_dict(self) -> dict:
         return dataclasses.asdict(self)
@@ -455,7 +489,7 @@ class Server:
     def __init__(self, executor, budget_bytes: int, epoch_steps: int = 2048, max_active: int = 4096,
                  backfill: bool = False, policy: str = "srpt", epoch_ms: float = 3.0, rates: dict = None,
                  tile_step_s: float = DEFAULT_TILE_STEP_S, max_wait_epochs: int = 32, admit_per_epoch: int = 4,
-                 defer_admissions: bool = True):
+                 defer_admissions: bool = True, max_retries: int = 0, checkpoint_every_s: float = None):
         if epoch_steps < 1:
             raise ValueError("epoch_steps must be >= 1")
         if policy not in ("lockstep", "srpt"):
@@ -466,6 +500,8 @@ class Server:
             raise ValueError("max_wait_epochs must be >= 1")
         if admit_per_epoch < 1:
             raise ValueError("admit_per_epoch must be >= 1")
+        if max_retries < 0 or (checkpoint_every_s is not None and not checkpoint_every_s >= 0):
+            raise ValueError("max_retries and checkpoint_every_s must be >= 0")
         self.ex = executor
         self.budget = int(budget_bytes)
         self.epoch_steps = int(epoch_steps)
@@ -481,6 +517,12 @@ class Server:
         # is then idle: enqueue the next epoch of the remaining solves before setting up new
         # admissions, so that their set-up (field sampling, table upload) overlaps it
         self.defer_admissions = bool(defer_admissions)
+        # recovery: a solve in a failed epoch is queued again up to max_retries times, from
+        # its last checkpoint (taken at most every checkpoint_every_s seconds; None: never)
+        self.max_retries = int(max_retries)
+        self.checkpoint_every_s = checkpoint_every_s
+        self.retried = 0
+        self.checkpoints = 0
         self.waited = {}  # request name -> epochs in a row without steps (srpt)
         self.in_use = 0
         self.peak = 0
@@ -517,6 +559,8 @@ class Server:
         self.in_use -= r.bytes
         self.ex.abandon(name, keep=keep)
         r.status, r.reason, r.done_s = status, reason, now
+        if status != "failed":  # a failed solve may still resume from its checkpoint
+            r.checkpoint = None
 
     def plan_epoch(self) -> dict:
         """Steps each ready solve advances in the next epoch (absent: none)."""
@@ -621,7 +665,8 @@ class Server:
                     r.admitted_s, r.status = now, "active"
                     admitted += 1
                     self.active[r.name] = r
-                    self.left[r.name] = r.n_steps
+                    r.resumed_from = r.checkpoint[1] if r.checkpoint else 0
+                    self.left[r.name] = r.n_steps - r.resumed_from
                     self.in_use += r.bytes
                     self.peak = max(self.peak, self.in_use + self.ex.idle_bytes)
                 elif self.backfill:
@@ -654,11 +699,23 @@ class Server:
             try:
                 done = self.ex.epoch_each(plan)
             except Exception as e:  # the epoch's launch failed and advanced nothing
-                # its planned members are retired as failed and their handles closed (after a
-                # real device fault their state cannot be trusted); the others go on
+                # its planned members lose their handles (after a real device fault their
+                # state cannot be trusted); those with retries left are queued again ahead
+                # of later arrivals, to resume from their last checkpoint; the others fail
                 now = self._now(t0, simulated)
+                again = []
                 for name in plan:
-                    self._retire(self.active[name], "failed", "epoch failed: %s" % e, now, keep=False)
+                    r = self.active[name]
+                    self._retire(r, "failed", "epoch failed: %s" % e, now, keep=False)
+                    if r.retries < self.max_retries:
+                        r.retries += 1
+                        r.status, r.done_s = "waiting", float("nan")
+                        again.append(r)
+                        self.retried += 1
+                    else:
+                        r.checkpoint = None
+                for r in reversed(again):
+                    waiting.appendleft(r)
                 epochs += 1
                 continue
             for name in self.ready:
@@ -669,12 +726,22 @@ class Server:
             active_sum += len(self.active)
             now = self._now(t0, simulated)
             idle_after_finish = bool(done)
+            if self.checkpoint_every_s is not None:
+                finishing = {name for name, _ in done}
+                for name, m in plan.items():
+                    r = self.active[name]
+                    if m > 0 and name not in finishing and now - r.checkpoint_s >= self.checkpoint_every_s:
+                        ck = self.ex.checkpoint(name)
+                        if ck is not None:
+                            r.checkpoint, r.checkpoint_s = ck, now
+                            self.checkpoints += 1
             for name, rho in done:
                 del self.left[name]
                 self.ready.discard(name)
                 self.waited.pop(name, None)
                 r = self.active.pop(name)
                 r.rho, r.done_s, r.status = rho, now, "done"
+                r.checkpoint = None
                 self.in_use -= r.bytes
                 self.ex.release(name)
                 finished += 1
@@ -688,7 +755,8 @@ class Server:
         return ServeStats(completed=len(done), rejected=sum(r.status == "rejected" for r in reqs),
                           cancelled=sum(r.status == "cancelled" for r in reqs),
                           expired=sum(r.status == "expired" for r in reqs),
-                          failed=sum(r.status == "failed" for r in reqs),
+                          failed=sum(r.status == "failed" for r in reqs), retried=self.retried,
+                          checkpoints=self.checkpoints,
                           makespan_s=makespan, p50_ms=float(np.percentile(lat, 50)),
                           p99_ms=float(np.percentile(lat, 99)), mean_ms=float(lat.mean()),
                           point_steps_per_s=sum(r.point_steps for r in done) / makespan, epochs=epochs,

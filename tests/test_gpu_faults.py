@@ -1,7 +1,7 @@
 """Injected faults (pd_set_fault) on the GPU: a failed device allocation or launch
 sequence is reported as a status, leaves every grid where it stood, and the work around
 it still ends bit for bit as without the fault; the serving loop retires what the fault
-touched and serves the rest."""
+touched, or retries it from its last checkpoint, and serves the rest."""
 import numpy as np
 import pytest
 
@@ -128,6 +128,48 @@ def test_serving_retires_what_a_fault_touched(gpu, faults):
     st = serve.Server(ex, 10 ** 10, epoch_steps=512, policy="srpt").run(reqs)
     rejected = [r for r in reqs if r.status == "rejected"]
     assert len(rejected) == 1 and "hipMalloc" in rejected[0].reason and st.completed == 3
+    ex.close()
+
+
+@pytest.mark.parametrize("checkpoints", [True, False])
+def test_serving_retries_a_failed_epoch(gpu, faults, checkpoints):
+    """With max_retries the five solves of the failed third epoch are queued again on new
+    handles: from the state the server copied to host memory after the second epoch
+    (pd_save_state, then pd_load_state into the new handle), or from step 0 without
+    checkpoints.  Every request completes, each equal to its solve alone bit for bit and
+    to the FP64 oracle on its full grid (FP64 1e-12 per point and relative on rho; FP32
+    1e-5 per point), and all memory returns to the budget."""
+    import oracle
+
+    ws = wl.config5(count=10, seed=11, rate_per_s=1e9, sizes=(64, 96, 128), step_range=(1000, 4000))
+    reqs = [serve.Request.from_workload(w) for w in ws]
+    for r in reqs[5:]:
+        r.arrival_s = 0.2
+    ex = serve.GpuExecutor(gpu, keep_n=True, background_setup=False)
+    srv = serve.Server(ex, 10 ** 10, epoch_steps=512, policy="lockstep", max_retries=1,
+                       checkpoint_every_s=0.0 if checkpoints else None)
+    faults("launch@3")
+    st = srv.run(reqs)
+    print("serve with a launch fault and retries:", st.as_dict(),
+          [(r.name, r.n_steps, r.status, r.retries, r.resumed_from) for r in reqs], flush=True)
+    assert st.completed == 10 and st.failed == 0 and st.retried == 5
+    assert [r.retries for r in reqs] == [1] * 5 + [0] * 5
+    # admitted four in the first epoch and one in the second: 1024 or 512 steps done before
+    # the failed epoch, where a checkpoint resumes them
+    if checkpoints:
+        assert sorted(r.resumed_from for r in reqs[:5]) == [512] + [1024] * 4
+    else:
+        assert all(r.resumed_from == 0 for r in reqs)
+    assert srv.in_use == 0 and not srv.active
+    for r in reqs:
+        n, rho = clean_like(gpu, r)
+        assert r.rho == rho and np.array_equal(ex.n_results[r.name], n), r.name
+        n_o = oracle.solve_grid(r.field, r.grid, r.n_steps, r.scheme)[0]
+        err = float(np.max(np.abs(n - n_o)))
+        if r.precision == "fp64":
+            assert err <= 1e-12 and abs(rho / oracle.density(r.grid, n_o) - 1) <= 1e-12, (r.name, err)
+        else:
+            assert err <= 1e-5, (r.name, err)
     ex.close()
 
 

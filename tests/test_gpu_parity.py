@@ -253,7 +253,7 @@ def test_checkpoint_file_restart(gpu, tmp_path, precision, scheme, field_kind, v
             q.load_state(state, bad_k)
     with pytest.raises(gpu.PDError):
         q.load_state(state[:-4], k)
-    q.propagate(700)
+    q.propagate((N - k) // 2)
     q.propagate(-1)
     n2 = np.empty_like(n_single)
     rho2 = q.density(n_out=n2)

@@ -428,3 +428,61 @@ def test_failed_epochs_retire_their_members_only(policy):
     assert all(r.status == "done" for r in reqs if r.name not in failed)
     assert all("injected epoch failure" in r.reason for r in reqs if r.name in failed)
     assert srv.in_use == 0 and not srv.active and not ex.active
+
+
+@pytest.mark.parametrize("checkpoints", [True, False])
+@pytest.mark.parametrize("policy", ["srpt", "lockstep"])
+def test_failed_epochs_are_retried(policy, checkpoints):
+    """With max_retries the solves of a failed epoch are queued again and complete.  With a
+    checkpoint after every epoch each resumes where the failed epoch would have started
+    it, so its successful epochs add up to exactly its step count; without checkpoints it
+    restarts from step 0 and its successful epochs add up to its step count plus the
+    steps it had done before the failure."""
+    reqs = stream(count=24, rate=500.0)
+    ex = serve.FakeExecutor(rate_point_steps_per_s=2e10, idle_per_shape=2, fail_epochs={3, 10})
+    log = []  # (planned steps, failed)
+    orig = ex.epoch_each
+
+    def spy(steps):
+        planned = {n: m for n, m in steps.items() if m > 0}
+        try:
+            out = orig(steps)
+        except RuntimeError:
+            log.append((planned, True))
+            raise
+        log.append((planned, False))
+        return out
+    ex.epoch_each = spy
+    budget = 4 * max(ex.footprint(r) for r in reqs)
+    srv = serve.Server(ex, budget, epoch_steps=512, policy=policy, epoch_ms=0.5, rates={"fp32": 2e10, "fp64": 2e10},
+                       max_retries=2, checkpoint_every_s=0.0 if checkpoints else None)
+    st = srv.run(reqs, simulated=True)
+    hit = set(log[2][0]) | set(log[9][0])
+    assert hit and log[2][1] and log[9][1]
+    assert st.completed == len(reqs) and st.failed == 0 and st.retried == len(log[2][0]) + len(log[9][0])
+    assert {r.name for r in reqs if r.retries} == hit
+    for r in reqs:
+        ran = sum(p.get(r.name, 0) for p, failed in log if not failed)
+        # successful steps before the last failed epoch that planned it
+        last = max((i for i, (p, failed) in enumerate(log) if failed and r.name in p), default=-1)
+        before = sum(p.get(r.name, 0) for p, failed in log[:max(last, 0)] if not failed)
+        assert r.retries == sum(1 for p, failed in log if failed and r.name in p)
+        if r.name not in hit:
+            assert ran == r.n_steps
+        elif checkpoints:
+            assert ran == r.n_steps and r.resumed_from == before, r.name
+        else:
+            assert ran == r.n_steps + before and r.resumed_from == 0, r.name
+        assert r.checkpoint is None  # host copies released when the request left
+    assert (st.checkpoints > 0) == checkpoints
+    assert srv.in_use == 0 and not srv.active and not ex.active
+
+
+def test_retries_are_bounded():
+    """A solve whose every epoch fails is retried max_retries times, then fails."""
+    reqs = stream(count=1, rate=500.0)
+    ex = serve.FakeExecutor(rate_point_steps_per_s=2e10, fail_epochs=set(range(1, 100)))
+    srv = serve.Server(ex, 4 * ex.footprint(reqs[0]), epoch_steps=512, max_retries=3, checkpoint_every_s=0.0)
+    st = srv.run(reqs, simulated=True)
+    assert st.failed == 1 and st.retried == 3 and reqs[0].retries == 3 and ex.epoch_calls == 4
+    assert reqs[0].status == "failed" and reqs[0].checkpoint is None
