@@ -28,6 +28,7 @@ The same JSON line carries two more objects (skip them with --no-batch / --no-se
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -117,6 +118,35 @@ def kernel_hash(path: str = KERNEL_SRC) -> str:
     text = re.sub(r"//[^\n]*", "", text)
     code = "".join(text.split())
     return hashlib.sha256(code.encode()).hexdigest()[:16]
+
+
+def environment(torch, pd) -> dict:
+    """Where a line was measured: the device, its peak clock, the software versions, the
+    kernel source hash and the host CPUs the process may use."""
+    props = torch.cuda.get_device_properties(0)
+    env = {"gpu": props.name, "arch": props.gcnArchName, "compute_units": props.multi_processor_count,
+           "hbm_gib": round(props.total_memory / 2 ** 30, 1), "peak_clock_ghz": None, "hip": torch.version.hip,
+           "rocm": None, "torch": torch.__version__, "libpd": pd.version(), "kernel_code_sha256_16": kernel_hash(),
+           "host_cpus": len(os.sched_getaffinity(0))}
+    try:
+        with open(os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), ".info", "version")) as fh:
+            env["rocm"] = fh.read().strip()
+    except OSError:
+        pass
+    # the HIP runtime torch already loaded (the same handle, not a second copy)
+    try:
+        with open("/proc/self/maps") as fh:
+            hip_path = next((ln.split()[-1] for ln in fh if ln.rstrip().endswith("libamdhip64.so")
+                             or "libamdhip64.so." in ln.split()[-1]), None)
+        if hip_path:
+            khz = ctypes.c_int()
+            attr_clock_rate = 5  # hipDeviceAttributeClockRate: peak clock in kHz
+            if ctypes.CDLL(hip_path).hipDeviceGetAttribute(ctypes.byref(khz), attr_clock_rate,
+                                                           torch.cuda.current_device()) == 0:
+                env["peak_clock_ghz"] = khz.value / 1e6
+    except (OSError, StopIteration, AttributeError):
+        pass
+    return env
 
 
 def traffic_from_profile(precision: str):
@@ -702,6 +732,7 @@ def main():
         line["batch"] = batch_object(args, pd, torch, np)
     if not args.no_serve:
         line["serve"] = serve_object(args, pd, torch, np)
+    line["env"] = environment(torch, pd)
     print(json.dumps(line), flush=True)
 
 

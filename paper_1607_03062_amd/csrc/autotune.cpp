@@ -8,6 +8,9 @@
 // points_per_lane, block_threads, table_stage and chunk_steps.
 #include <hip/hip_runtime_api.h>
 
+#include <fcntl.h>
+#include <unistd.h>
+
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -64,11 +67,18 @@ bool cache_lookup(const std::string& key, Shape* out) {
   return found;
 }
 
+// One line per store, written by a single append-mode write so that lines stored at the
+// same time by several threads or processes do not interleave.
 void cache_store(const std::string& key, const Shape& s, float ms) {
   const char* path = std::getenv("PD_AUTOTUNE_CACHE");
   if (!path || !*path) return;
-  std::ofstream out(path, std::ios::app);
-  out << key << '\t' << s.ppl << ' ' << s.block << ' ' << s.stage << ' ' << s.chunk << ' ' << ms << '\n';
+  std::ostringstream line;
+  line << key << '\t' << s.ppl << ' ' << s.block << ' ' << s.stage << ' ' << s.chunk << ' ' << ms << '\n';
+  const std::string text = line.str();
+  const int fd = ::open(path, O_WRONLY | O_APPEND | O_CREAT, 0644);
+  if (fd < 0) return;
+  (void)!::write(fd, text.data(), text.size());
+  ::close(fd);
 }
 
 // Time `run` (which enqueues work on `st`) as the fastest of `reps` repetitions.
