@@ -1,0 +1,106 @@
+"""Precision-budget model of the FP32 form (test infrastructure, CPU only).
+
+The FP32 form of the Strang scheme evolves each point's Bloch vector r = psi^dagger sigma psi
+by plane rotations (the split steps of Sec. III, Eqs. (11)-(12): rotation by 2 dt P_x
+about x, and dt p_y per half step about y, P = p + A(t_k+1/2)), with the state and the
+rotation coefficients in FP32 and everything else in FP64.  This module emulates that
+arithmetic in numpy float32, so that the error of the FP32 form against the FP64 oracle
+can be predicted on the CPU before the kernels run:
+
+  * coefficients t = tan(theta/2), s = sin(theta) computed in FP64 and rounded to FP32;
+    the per-point ones take four FP32 values in turn (step k uses value k mod 4) whose
+    mean is within 1/8 ulp of the FP64 value;
+  * every rotation as three shears, each state component rounded once per rotation
+    (u1 = u - t v; v' = v + s u1; u' = u - t (v + v'); a fused multiply-add is one
+    rounding, emulated as an exact FP64 product and sum rounded to FP32);
+  * the state renormalised in FP64 every 1024 steps; the initial state and the
+    projection n = (1 + r.P_out/|P_out|) / 2 (Sec. II, Eqs. (1), (3)) in FP64.
+
+With arithmetic=np.float64 the same steps are evaluated in FP64 and must reproduce the
+oracle to rounding; that pins the rotation sequence, angles and signs of the model.  It
+imports nothing from the library; the field samples and grid nodes come from the oracle.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+F32 = np.float32
+RENORM_EVERY = 1024
+PHASES = 4
+
+
+def _coefficients(theta):
+    """(t, s) = (tan(theta/2), sin(theta)) of a rotation by theta, FP64."""
+    return np.tan(0.5 * theta), np.sin(theta)
+
+
+def _phases(c):
+    """PHASES FP32 values per FP64 coefficient whose mean is within 1/8 ulp of it."""
+    hi = c.astype(F32)
+    ulp = np.spacing(np.abs(hi)).astype(np.float64)
+    m = np.rint(PHASES * (c - hi.astype(np.float64)) / np.where(ulp > 0, ulp, 1.0))
+    return np.stack([(hi + np.where(j < np.abs(m), np.sign(m), 0.0) * ulp).astype(F32) for j in range(PHASES)])
+
+
+def _rotate(u, v, t, s, arithmetic):
+    """Rotation of (u, v) by theta (u' = u cos - v sin, v' = u sin + v cos) as three shears,
+    each component rounded once."""
+    if arithmetic is np.float64:
+        u1 = u - t * v
+        v1 = v + s * u1
+        return u - t * (v + v1), v1
+    d = np.float64
+    u1 = (d(u) - d(t) * d(v)).astype(F32)
+    v1 = (d(v) + d(s) * d(u1)).astype(F32)
+    w = (d(v) + d(v1)).astype(F32)
+    return (d(u) - d(t) * d(w)).astype(F32), v1
+
+
+def solve_grid(field, grid, n_steps, arithmetic=F32):
+    """n(p) on the grid (row-major, y rows) after n_steps second-order Strang steps in the
+    given arithmetic; NaN where |p + A(t_i)| or |p + A(t_f)| is 0 (masked points)."""
+    A, a_in, a_out, dt = oracle.field_table(field, n_steps)
+    px = np.array([oracle.grid_p(grid["px"][0], grid["px"][1], grid["nx"], i) for i in range(grid["nx"])])
+    py = np.array([oracle.grid_p(grid["py"][0], grid["py"][1], grid["ny"], j) for j in range(grid["ny"])])
+    PX, PY = (a.ravel() for a in np.meshgrid(px, py))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        e_in = np.hypot(PX + a_in, PY)
+        x = (-(PX + a_in) / e_in).astype(arithmetic)  # v_in: r = -P_in / |P_in|
+        y = (-PY / e_in).astype(arithmetic)
+    z = np.zeros_like(x)
+
+    def per_point(theta):
+        t, s = _coefficients(theta)
+        if arithmetic is np.float64:
+            return np.stack([t] * PHASES), np.stack([s] * PHASES)
+        return _phases(t), _phases(s)
+
+    tx, sx = per_point(2.0 * dt * PX)  # x rotation by the point's part of 2 dt P_x
+    ty, sy = per_point(2.0 * dt * PY)  # two merged half steps about y
+    th, sh = (c.astype(arithmetic) for c in _coefficients(dt * PY))  # opening and closing half steps
+    tf, sf = (c.astype(arithmetic) for c in _coefficients(2.0 * dt * A))  # field part, per step
+    z, x = _rotate(z, x, th, sh, arithmetic)
+    for k in range(int(n_steps)):
+        if arithmetic is not np.float64 and k > 0 and k % RENORM_EVERY == 0:
+            X, Y, Z = (c.astype(np.float64) for c in (x, y, z))
+            nr = np.sqrt(X * X + Y * Y + Z * Z)
+            x, y, z = ((c / nr).astype(F32) for c in (X, Y, Z))
+        h = k % PHASES
+        y, z = _rotate(y, z, tf[k], sf[k], arithmetic)
+        y, z = _rotate(y, z, tx[h], sx[h], arithmetic)
+        if k == n_steps - 1:
+            z, x = _rotate(z, x, th, sh, arithmetic)
+        else:
+            z, x = _rotate(z, x, ty[h], sy[h], arithmetic)
+    X, Y, Z = (c.astype(np.float64) for c in (x, y, z))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return 0.5 * (1.0 + (X * (PX + a_out) + Y * PY) / (np.sqrt(X * X + Y * Y + Z * Z) * np.hypot(PX + a_out, PY)))
+
+
+def error_stats(n, n_ref):
+    """(max |dn|, rms |dn|) over the points both define."""
+    ok = np.isfinite(n) & np.isfinite(n_ref)
+    e = np.abs(n[ok] - n_ref[ok])
+    return float(e.max()), float(np.sqrt(np.mean(e * e)))

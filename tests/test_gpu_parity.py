@@ -267,6 +267,23 @@ def test_checkpoint_file_restart(gpu, tmp_path, precision, scheme, field_kind, v
     other.close()
 
 
+def test_fp32_error_matches_the_rounding_model(gpu):
+    """The FP32 form's error against the oracle is the one the CPU model of its arithmetic
+    (tests/fp32_model.py: FP32 state and coefficients, each component rounded once per
+    rotation) predicts: on a 48^2 grid under the 8-cycle sin^2 pulse, at 4000 and 16000
+    Strang steps, the GPU's rms error within 0.6-1.6 times the model's and its largest
+    error within 0.4-2.5 times (both sides' roundings differ in detail, not in kind)."""
+    from tests import fp32_model
+
+    field, grid = wl.config1()["field"], {"nx": 48, "ny": 48, "px": (-2.0, 2.0), "py": (-2.0, 2.0)}
+    for N in (4000, 16000):
+        n_o = oracle.solve_grid(field, grid, N)[0]
+        gpu_mx, gpu_rms = fp32_model.error_stats(run(gpu, grid, field, N, "fp32")[0], n_o)
+        mod_mx, mod_rms = fp32_model.error_stats(fp32_model.solve_grid(field, grid, N), n_o)
+        print("N=%d: GPU FP32 max %.3e rms %.3e; model max %.3e rms %.3e" % (N, gpu_mx, gpu_rms, mod_mx, mod_rms))
+        assert 0.6 <= gpu_rms / mod_rms <= 1.6 and 0.4 <= gpu_mx / mod_mx <= 2.5, (N, gpu_rms, mod_rms, gpu_mx, mod_mx)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_midpoint_step_forms(gpu, precision):
     """Both forms of the midpoint step match the oracle: the tangent form (step angles
