@@ -40,9 +40,10 @@ def test_c_program_uses_the_abi(tmp_path):
 @pytest.mark.parametrize("precision,scheme", [(0, 0), (0, 1), (1, 0)])
 def test_c_program_solves_on_the_device(gpu, tmp_path, precision, scheme):
     """tests/c/abi_device.c: a ragged 37 x 29 grid, 1500 steps in two pd_propagate calls on
-    the default stream, pd_density and pd_density_static, from a plain C99 process with no
-    torch; its n(p) and rho against the FP64 oracle (FP64 1e-12 per point and relative on
-    rho, FP32 1e-5 per point)."""
+    the default stream (and a second handle restarted from the state saved between them,
+    pd_save_state / pd_load_state, bit for bit), pd_density and pd_density_static, from a
+    plain C99 process with no torch; its n(p) and rho against the FP64 oracle (FP64 1e-12
+    per point and relative on rho, FP32 1e-5 per point)."""
     import oracle
     from paper_1607_03062_amd import workloads as wl
 
