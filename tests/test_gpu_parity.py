@@ -2,11 +2,13 @@
 
 Tolerances:
   FP64 forms: |n_gpu - n_oracle| <= 1e-12 per point and |rho_gpu / rho_oracle - 1| <= 1e-12.
-    Both sides are FP64 with rounding ~1e-16 per operation; the error after N
-    unitary steps grows like sqrt(N) ulps (about 1e-14 at N = 80000), and the
-    GPU's factorised rotations add no truncation, so 1e-12 leaves two decades.
+    Both sides are FP64 with rounding ~1e-16 per operation; the difference grows
+    with the number of unitary steps N (7e-14 at N = 80000 on the 2048^2 benchmark
+    solve), and the GPU's factorised rotations add no truncation, so 1e-12 leaves
+    more than a decade.
   FP32 precision form: |n_gpu - n_oracle| <= 1e-5 per point (the bar set for
-    the FP32 form; FP32 rounding of the state random-walks to ~1e-6 after 80000 steps;
+    the FP32 form; FP32 rounding of the state grows to a few 1e-6 after 80000 steps,
+    as tests/fp32_model.py predicts;
     the default form rounds each component once per rotation; the fast form's plain
     shears, of alternating orientation, reach up to about 1.6x its worst-point error).
   p_y = 0 lines: exactly 0.0 on both sides (the sigma_x eigenstate is kept).
