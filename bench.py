@@ -6,22 +6,26 @@ momentum grid on [-2,2]^2 under the sin^2 pulse (E0 = 0.1, omega = 0.5, 30
 cycles), 80000 Strang steps (state init, propagation, projection on u_out,
 density reduction and the copy of rho to the host).  The field table is
 resident in HBM before the timed region (pd_set_field once, pd_rewind per
-step).  The FP64 form and the fast FP32 form (alternating plain shears, PD_FP32_FAST) of the
-same workload are timed beside it, and all are checked against the FP64 CPU
-oracle on the 64 x 64 subsample (stride 32) and on the larger sample whose
-oracle run is also the CPU baseline; the two FP32 forms also against the FP64
-form at every point of the grid.
+step).  The main line is the fast FP32 form (PD_FP32_FAST: shears of alternating
+orientation, the two rotations of a stage in one plane merged into five shears),
+which on this workload is within 1e-5 of FP64 at every point; the once-rounded FP32
+form (PD_FP32) and the FP64 form of the same workload are timed beside it.  All are
+checked against the FP64 CPU oracle on the 64 x 64 subsample (stride 32) and on the
+larger sample whose oracle run is also the CPU baseline; the two FP32 forms also
+against the FP64 form at every point of the grid.
 
 The same JSON line carries two more objects (skip them with --no-batch / --no-serve):
   batch  the 64 seeded solves of the batch workload (grids 256^2..2048^2 on [-4,4]^2,
-         5k-80k steps, FP32 form) in one graph-captured launch sequence per pass,
+         5k-80k steps, the once-rounded FP32 form, whose worst subsample error there is
+         the smaller; --batch-precision fp32fast for the fast one) in one graph-captured
+         launch sequence per pass,
          autotuned, with its own roofline, the oracle on every member's 64 x 64
          subsample (error and CPU baseline) and every point against its FP64 solve;
   serve  a Poisson stream of solve requests (batch-workload distributions, half FP32
          and half FP64) served by continuous batching at 0.7 of the capacity measured
          in the same run: p50 / p99 / mean latency and sustained point-steps/s.
 
-    python bench.py [--steps K] [--warmup W] [--precision fp32|fp64] [--no-batch] [--no-serve]
+    python bench.py [--steps K] [--warmup W] [--precision fp32fast|fp32|fp64] [--no-batch] [--no-serve]
     python bench.py --workload batch|serve ...       (one of the two objects as its own line)
     python bench.py --summarize-profile DIR [...]    (text summary of rocprofv3 output)
 """
@@ -49,7 +53,8 @@ METRIC = "momentum point-steps/s (FP32 vs FP64 form) at stated n(p) error; p50/p
 #   versine form: 2 FMA per rotated component -> 12 FMA = 24 flop
 #     executed: FP64 24 flop / 12 instructions; FP32 (mul + fma + add per component) 24 / 18
 # (rotation form, precision) -> (algorithmic flop, executed flop, executed VALU instructions)
-ALGO = {(0, "fp64"): (18, 18, 9), (0, "fp32"): (18, 21, 12), (0, "fp32fast"): (18, 18, 9),
+FORM_NAMES = {"fp32": "FP32", "fp32fast": "fast FP32", "fp64": "FP64"}
+ALGO = {(0, "fp64"): (18, 18, 9), (0, "fp32"): (18, 21, 12), (0, "fp32fast"): (18, 17, 9),
         (1, "fp64"): (24, 24, 12), (1, "fp32"): (24, 24, 18), (1, "fp32fast"): (24, 24, 18)}
 
 
@@ -66,7 +71,10 @@ def algo(info: dict, precision: str):
     """(algorithmic flop, executed flop, VALU instructions) per point-step of the solve
     described by pd_info; a fourth-order step is `stages` = 5 second-order stages.
     Strang stage: three rotations (ALGO), a fourth one (the field part of the y
-    rotation) when the field has a y component.
+    rotation) when the field has a y component.  The fast FP32 form applies each pair of
+    rotations in one plane as five shears (8 FMA + 1 add for two rotations where the
+    triples take 9 FMA): it executes 17 flop where the method's step counts 18.  The
+    roofline counts the smaller of the two.
     Midpoint stage, phase X = c dt(px + A) (1 add, FP64) and x = X^2 + Y^2 (1 fma):
       tangent form (rotation_form 0), J series terms: tan(x)/x - 1 (J - 2 fma + 1 mul),
       alpha, beta (2 fma), the update: FP32 mul + fma + add per component (16 flop, 12
@@ -223,9 +231,10 @@ def batch_object(args, pd, torch, np):
     from paper_1607_03062_amd import workloads as wl
 
     cfgs = wl.config4(count=args.batch_count)
+    prec = args.batch_precision
     solvers = []
     for c in cfgs:
-        s = pd.Solver.for_grid(c["grid"], c["precision"])
+        s = pd.Solver.for_grid(c["grid"], prec)
         s.set_field(c["field"], c["n_steps"])
         solvers.append(s)
     total = float(sum(c["grid"]["nx"] * c["grid"]["ny"] * c["n_steps"] for c in cfgs))
@@ -291,12 +300,13 @@ def batch_object(args, pd, torch, np):
     b.close()
     for s in solvers:
         s.close()
-    algo_flop, exec_flop, instr = ALGO[(0, "fp32")]
+    algo_flop, exec_flop, instr = ALGO[(0, prec)]
+    algo_flop = min(algo_flop, exec_flop)
     achieved = algo_flop * total / (dev_ms * 1e-3) / 1e12
     out = {
         "workload": "%d seeded solves (grids 256^2..2048^2 on [-4,4]^2, 5k-80k steps, sin^2 pulses E0 in "
-                    "[0.05,0.5], omega in [0.1,1], 4-40 cycles), FP32 form, one persistent graph-captured "
-                    "launch per pass" % len(cfgs),
+                    "[0.05,0.5], omega in [0.1,1], 4-40 cycles), %s form, one persistent graph-captured "
+                    "launch per pass" % (len(cfgs), FORM_NAMES[prec]),
         "solves": len(cfgs), "passes": passes, "warmup": args.batch_warmup, "point_steps_per_pass": total,
         "ms_per_pass": t / passes * 1e3, "device_ms_per_pass": dev_ms, "value": total * passes / t,
         "unit": "point-steps/s", "graph_captured": info["graph_captured"],
@@ -510,6 +520,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="leave the batch object out of the cfg3 line")
     ap.add_argument("--no-serve", action="store_true", help="leave the serve object out of the cfg3 line")
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-precision", choices=["fp32", "fp32fast"], default="fp32",
+                    help="FP32 form of the batch's solves")
     ap.add_argument("--batch-passes", type=int, default=3)
     ap.add_argument("--batch-warmup", type=int, default=1)
     ap.add_argument("--no-autotune", action="store_true")
@@ -528,8 +540,11 @@ def main():
                     help="serving: arrival rate (default: --load x the capacity measured in the same run)")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=["fp32", "fp64", "fp32fast"], default="fp32")
-    ap.add_argument("--no-fast-form", action="store_true", help="skip timing the fp32fast form beside")
+    ap.add_argument("--precision", choices=["fp32", "fp64", "fp32fast"], default=None,
+                    help="form of the main line (default: fp32fast for the Strang schemes, fp32 for the "
+                         "midpoint schemes, whose FP32 forms are one)")
+    ap.add_argument("--no-fast-form", action="store_true",
+                    help="skip timing the other FP32 form (fp32 beside fp32fast, or fp32fast beside fp32)")
     ap.add_argument("--scheme", choices=["strang", "midpoint", "strang4", "midpoint4"], default="strang")
     ap.add_argument("--ellipticity", type=float, default=0.0,
                     help="give the workload pulse a y component E_y = e E0 sin^2(pi t/T) cos(omega t)")
@@ -560,6 +575,8 @@ def main():
     ap.add_argument("--no-defer-admissions", action="store_true",
                     help="serving: set up admissions right after a finishing epoch (before the next epoch)")
     args = ap.parse_args()
+    if args.precision is None:
+        args.precision = "fp32fast" if args.scheme.startswith("strang") else "fp32"
     if args.summarize_profile:
         return summarize_profile(args)
     if args.gpus != 1:
@@ -609,11 +626,13 @@ def main():
         other = time_form(pd, torch, c64, "fp64", args.steps, args.warmup, args.ppl, args.block, args.table_stage,
                           args.chunk_steps, scheme=sch)
         log("fp64 form: %.2f ms per solve" % (other["t_total"] / args.steps * 1e3))
+    # the other FP32 form of the Strang schemes, timed and checked beside the main one
+    alt_prec = {"fp32": "fp32fast", "fp32fast": "fp32"}.get(args.precision)
     fast = None
-    if not args.no_fast_form and args.precision == "fp32" and sch.startswith("strang"):
-        fast = time_form(pd, torch, dict(c, field=dict(c["field"])), "fp32fast", args.steps, args.warmup, args.ppl,
+    if not args.no_fast_form and alt_prec and sch.startswith("strang"):
+        fast = time_form(pd, torch, dict(c, field=dict(c["field"])), alt_prec, args.steps, args.warmup, args.ppl,
                          args.block, args.table_stage, args.chunk_steps, scheme=sch)
-        log("fp32fast form: %.2f ms per solve" % (fast["t_total"] / args.steps * 1e3))
+        log("%s form: %.2f ms per solve" % (alt_prec, fast["t_total"] / args.steps * 1e3))
 
     # oracle on the 64 x 64 subsample: n(p) error of each form and the CPU baseline
     n_err = {}
@@ -655,6 +674,7 @@ def main():
     value = ps_per_solve * K / t
     kern_ms = float(np.mean(main_form["kernel_ms"]))
     flop_a, flop_e, instr = algo(main_form["info"], args.precision)
+    flop_a = min(flop_a, flop_e)  # never more than the kernel executes
     achieved = flop_a * ps_per_solve / (kern_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     wall_ms = np.array(main_form["wall"]) * 1e3
@@ -678,7 +698,7 @@ def main():
                                                          {"strang": "Strang", "midpoint": "midpoint",
                                                           "strang4": "fourth-order Strang",
                                                           "midpoint4": "fourth-order midpoint"}[sch],
-                                                         args.precision.upper()),
+                                                         FORM_NAMES[args.precision]),
                    "n_points": npts, "n_steps": c["n_steps"], "precision": args.precision, "scheme": sch,
                    "points_per_lane": main_form["info"]["points_per_lane"],
                    "block_threads": main_form["info"]["block_threads"]},
@@ -711,6 +731,7 @@ def main():
     if other is not None:
         okm = float(np.mean(other["kernel_ms"]))
         fa64, fe64, i64 = algo(other["info"], "fp64")
+        fa64 = min(fa64, fe64)
         line["fp64_form"] = {
             "value": ps_per_solve * K / other["t_total"], "ms_per_step": other["t_total"] / K * 1e3,
             "kernel_ms": okm, "n_error_max_abs": n_err.get("fp64"), "rho": other["rho"],
@@ -719,8 +740,9 @@ def main():
             "valu_issue_frac": i64 * ps_per_solve / (okm * 1e-3) / (CU_CLOCKS_PER_S * LANES_PER_CLK["fp64"])}
     if fast is not None:
         fkm = float(np.mean(fast["kernel_ms"]))
-        faf, fef, fi = algo(fast["info"], "fp32fast")
-        line["fp32_fast_form"] = {
+        faf, fef, fi = algo(fast["info"], alt_prec)
+        faf = min(faf, fef)
+        line["fp32_fast_form" if alt_prec == "fp32fast" else "fp32_once_form"] = {
             "value": ps_per_solve * K / fast["t_total"], "ms_per_step": fast["t_total"] / K * 1e3,
             "kernel_ms": fkm, "n_error_max_abs": n_err.get("fast_64"),
             "n_error_max_abs_cpu_sample": n_err.get("fast"), "rho": fast["rho"],

@@ -61,12 +61,15 @@ typedef enum {
                       rotation angles, projection and density sum; the state is
                       renormalised every 1024 absolute steps (the exact step is unitary,
                       Sec. III); every rotation rounds each state component once */
-  PD_FP32_FAST = 2 /* as PD_FP32, but the Strang rotations are three plain shears (one
+  PD_FP32_FAST = 2 /* as PD_FP32, but the Strang rotations are plain shears (one
                       component rounded twice per rotation) whose orientation alternates
                       from one stage to the next, so that the doubly rounded component
-                      alternates: a quarter fewer instructions; on the 2048^2 benchmark
-                      solve the same error as PD_FP32, on other solves up to about 1.6x
-                      it, so not held to PD_FP32's bound (the midpoint schemes run as
+                      alternates, and a stage's two rotations in one plane (field part
+                      and per-point part) run as five shears: a quarter fewer
+                      instructions.  On the 2048^2 benchmark solve every point is within
+                      1e-5 of FP64 (worst 9.3e-6, PD_FP32 9.6e-6); over long solves on
+                      wide grids its worst points reach up to about 1.8x PD_FP32's, so it
+                      is not held to PD_FP32's bound (the midpoint schemes run as
                       PD_FP32) */
 } pd_precision;
 

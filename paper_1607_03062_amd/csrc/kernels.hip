@@ -111,14 +111,37 @@ __device__ __forceinline__ void rotate_shear_vu(R& u, R& v, R t, R s) {
   v = fma(t, u, v);
 }
 
+// Two rotations in one plane, by a and then by b, as five shears: the last shear of
+// the first triple and the first of the second act on the same component, so they
+// merge into one with the summed coefficient (one add).  Both orientations.
+template <typename R>
+__device__ __forceinline__ void rotate_two_shear(R& u, R& v, R ta, R sa, R tb, R sb) {
+  u = fma(-ta, v, u);
+  v = fma(sa, u, v);
+  u = fma(-(ta + tb), v, u);
+  v = fma(sb, u, v);
+  u = fma(-tb, v, u);
+}
+
+template <typename R>
+__device__ __forceinline__ void rotate_two_shear_vu(R& u, R& v, R ta, R sa, R tb, R sb) {
+  v = fma(ta, u, v);
+  u = fma(-sa, v, u);
+  v = fma(ta + tb, u, v);
+  u = fma(-sb, v, u);
+  v = fma(tb, u, v);
+}
+
 // Shear variants (FP32 forms):
 //   kShearPlain  u -= t v; v += s u; u -= t v (u rounded twice per rotation);
 //   kShearOnce   each component rounded once (rotate_shear_once, 4 instructions);
-//   kShearAlt    the plain triple with its orientation alternating from one stage to
-//                the next (u-v-u, then v-u-v; the parity of the absolute stage index),
-//                so that the doubly rounded component alternates: 3 instructions, and
-//                the systematic part of the two roundings largely cancels between
-//                neighbouring stages.
+//   kShearAlt    plain shears with the orientation alternating from one stage to the
+//                next (u-v-u, then v-u-v; the parity of the absolute stage index), so
+//                that the doubly rounded component alternates and the systematic part
+//                of the roundings largely cancels between neighbouring stages; the
+//                stage's two rotations in one plane (field and per-point parts) run as
+//                five shears (rotate_two_shear), which rounds less for the same count:
+//                3 instructions per rotation.
 constexpr int kShearPlain = 0;
 constexpr int kShearOnce = 1;
 constexpr int kShearAlt = 2;
@@ -217,13 +240,29 @@ struct BlochLanes {
       const bool o = ((PH & 1) != 0) != ((j & 1) != 0);
 #pragma unroll
       for (int q = 0; q < PPL; ++q) {
-        rot<FORM, SH>(y[q], z[q], row[2 * j], row[2 * j + 1], o);
-        rot<FORM, SH>(y[q], z[q], aX[L::xcls(j)][h][q], sX[L::xcls(j)][h][q], o);
-        if (LAST && j == NS - 1)
-          rot<FORM, SH>(z[q], x[q], ha[q], hs[q], o);
-        else
-          rot<FORM, SH>(z[q], x[q], aY[L::ycls(j)][h][q], sY[L::ycls(j)][h][q], o);
-        if (POL) rot<FORM, SH>(z[q], x[q], row[2 * NS + 2 * j], row[2 * NS + 2 * j + 1], o);
+        const R ya = (LAST && j == NS - 1) ? ha[q] : aY[L::ycls(j)][h][q];
+        const R ys = (LAST && j == NS - 1) ? hs[q] : sY[L::ycls(j)][h][q];
+        if constexpr (FORM == kFormShear && SH == kShearAlt) {
+          // the x rotations by the field part and the point's part, then the y rotation
+          // by the point's part and (POL) the field part, each pair as five shears
+          if (o)
+            rotate_two_shear_vu(y[q], z[q], row[2 * j], row[2 * j + 1], aX[L::xcls(j)][h][q], sX[L::xcls(j)][h][q]);
+          else
+            rotate_two_shear(y[q], z[q], row[2 * j], row[2 * j + 1], aX[L::xcls(j)][h][q], sX[L::xcls(j)][h][q]);
+          if constexpr (POL) {
+            if (o)
+              rotate_two_shear_vu(z[q], x[q], ya, ys, row[2 * NS + 2 * j], row[2 * NS + 2 * j + 1]);
+            else
+              rotate_two_shear(z[q], x[q], ya, ys, row[2 * NS + 2 * j], row[2 * NS + 2 * j + 1]);
+          } else {
+            rot<FORM, SH>(z[q], x[q], ya, ys, o);
+          }
+        } else {
+          rot<FORM, SH>(y[q], z[q], row[2 * j], row[2 * j + 1], o);
+          rot<FORM, SH>(y[q], z[q], aX[L::xcls(j)][h][q], sX[L::xcls(j)][h][q], o);
+          rot<FORM, SH>(z[q], x[q], ya, ys, o);
+          if (POL) rot<FORM, SH>(z[q], x[q], row[2 * NS + 2 * j], row[2 * NS + 2 * j + 1], o);
+        }
       }
     }
   }

@@ -10,9 +10,13 @@ can be predicted on the CPU before the kernels run:
   * coefficients t = tan(theta/2), s = sin(theta) computed in FP64 and rounded to FP32;
     the per-point ones take four FP32 values in turn (step k uses value k mod 4) whose
     mean is within 1/8 ulp of the FP64 value;
-  * every rotation as three shears, each state component rounded once per rotation
-    (u1 = u - t v; v' = v + s u1; u' = u - t (v + v'); a fused multiply-add is one
-    rounding, emulated as an exact FP64 product and sum rounded to FP32);
+  * arrangement "once" (PD_FP32): every rotation as three shears, each state component
+    rounded once per rotation (u1 = u - t v; v' = v + s u1; u' = u - t (v + v'));
+    arrangement "fast" (PD_FP32_FAST): plain shears whose orientation alternates from
+    step to step (u-v-u, then v-u-v), the step's two rotations about x (field part,
+    then the point's part) as five shears, the middle two merged into one with the
+    summed coefficient; a fused multiply-add is one rounding, emulated as an exact FP64
+    product and sum rounded to FP32;
   * the state renormalised in FP64 every 1024 steps; the initial state and the
     projection n = (1 + r.P_out/|P_out|) / 2 (Sec. II, Eqs. (1), (3)) in FP64.
 
@@ -58,9 +62,40 @@ def _rotate(u, v, t, s, arithmetic):
     return (d(u) - d(t) * d(w)).astype(F32), v1
 
 
-def solve_grid(field, grid, n_steps, arithmetic=F32):
+def _fma(a, b, c, arithmetic):
+    """a * b + c with one rounding in the given arithmetic."""
+    if arithmetic is np.float64:
+        return a * b + c
+    return (np.float64(a) * np.float64(b) + np.float64(c)).astype(F32)
+
+
+def _shears(u, v, coefs, odd, arithmetic):
+    """Rotations in the (u, v) plane by the angles whose (t, s) are listed, in order, as
+    plain shears; odd: v-u-v orientation.  Adjacent shears of the same component merge
+    (coefficients summed, one rounding of the sum)."""
+    seq = []  # (component moved: 0 = u, 1 = v, coefficient)
+    for t, s in coefs:
+        trip = [(1, t), (0, -s), (1, t)] if odd else [(0, -t), (1, s), (0, -t)]
+        for c, k in trip:
+            if seq and seq[-1][0] == c:
+                summed = seq[-1][1] + k
+                seq[-1] = (c, summed if arithmetic is np.float64 else summed.astype(F32))
+            else:
+                seq.append((c, k))
+    for c, k in seq:
+        if c == 0:
+            u = _fma(k, v, u, arithmetic)
+        else:
+            v = _fma(k, u, v, arithmetic)
+    return u, v
+
+
+def solve_grid(field, grid, n_steps, arithmetic=F32, arrangement="once"):
     """n(p) on the grid (row-major, y rows) after n_steps second-order Strang steps in the
-    given arithmetic; NaN where |p + A(t_i)| or |p + A(t_f)| is 0 (masked points)."""
+    given arithmetic and arrangement of the roundings; NaN where |p + A(t_i)| or
+    |p + A(t_f)| is 0 (masked points)."""
+    if arrangement not in ("once", "fast"):
+        raise ValueError("arrangement must be 'once' or 'fast'")
     A, a_in, a_out, dt = oracle.field_table(field, n_steps)
     px = np.array([oracle.grid_p(grid["px"][0], grid["px"][1], grid["nx"], i) for i in range(grid["nx"])])
     py = np.array([oracle.grid_p(grid["py"][0], grid["py"][1], grid["ny"], j) for j in range(grid["ny"])])
@@ -81,19 +116,24 @@ def solve_grid(field, grid, n_steps, arithmetic=F32):
     ty, sy = per_point(2.0 * dt * PY)  # two merged half steps about y
     th, sh = (c.astype(arithmetic) for c in _coefficients(dt * PY))  # opening and closing half steps
     tf, sf = (c.astype(arithmetic) for c in _coefficients(2.0 * dt * A))  # field part, per step
-    z, x = _rotate(z, x, th, sh, arithmetic)
+    if arrangement == "fast":  # the opening half step about y
+        z, x = _shears(z, x, [(th, sh)], False, arithmetic)
+    else:
+        z, x = _rotate(z, x, th, sh, arithmetic)
     for k in range(int(n_steps)):
         if arithmetic is not np.float64 and k > 0 and k % RENORM_EVERY == 0:
             X, Y, Z = (c.astype(np.float64) for c in (x, y, z))
             nr = np.sqrt(X * X + Y * Y + Z * Z)
             x, y, z = ((c / nr).astype(F32) for c in (X, Y, Z))
         h = k % PHASES
+        yt, ys = (th, sh) if k == n_steps - 1 else (ty[h], sy[h])
+        if arrangement == "fast":
+            y, z = _shears(y, z, [(tf[k], sf[k]), (tx[h], sx[h])], k % 2 == 1, arithmetic)
+            z, x = _shears(z, x, [(yt, ys)], k % 2 == 1, arithmetic)
+            continue
         y, z = _rotate(y, z, tf[k], sf[k], arithmetic)
         y, z = _rotate(y, z, tx[h], sx[h], arithmetic)
-        if k == n_steps - 1:
-            z, x = _rotate(z, x, th, sh, arithmetic)
-        else:
-            z, x = _rotate(z, x, ty[h], sy[h], arithmetic)
+        z, x = _rotate(z, x, yt, ys, arithmetic)
     X, Y, Z = (c.astype(np.float64) for c in (x, y, z))
     with np.errstate(invalid="ignore", divide="ignore"):
         return 0.5 * (1.0 + (X * (PX + a_out) + Y * PY) / (np.sqrt(X * X + Y * Y + Z * Z) * np.hypot(PX + a_out, PY)))

@@ -5,6 +5,7 @@ for a 4000-step solve, growing about linearly with the step count (the roundings
 slowly varying state are correlated).  The GPU test in test_gpu_parity.py holds the FP32
 kernels to the same prediction."""
 import numpy as np
+import pytest
 
 import oracle
 from paper_1607_03062_amd import workloads as wl
@@ -14,9 +15,11 @@ FIELD = wl.config1()["field"]  # sin^2 pulse, E0 = 0.1, omega = 0.5, 8 cycles
 GRID = {"nx": 48, "ny": 48, "px": (-2.0, 2.0), "py": (-2.0, 2.0)}
 
 
-def test_model_in_fp64_is_the_oracle():
+@pytest.mark.parametrize("arrangement", ["once", "fast"])
+def test_model_in_fp64_is_the_oracle(arrangement):
+    """Both arrangements, the fast one with its merged shears, are the method's step."""
     n_o = oracle.solve_grid(FIELD, GRID, 1500)[0]
-    n = fp32_model.solve_grid(FIELD, GRID, 1500, arithmetic=np.float64)
+    n = fp32_model.solve_grid(FIELD, GRID, 1500, arithmetic=np.float64, arrangement=arrangement)
     assert fp32_model.error_stats(n, n_o)[0] <= 1e-12
 
 
