@@ -311,6 +311,22 @@ __device__ __forceinline__ void group_steps(Lanes& L, const Row* r) {
   }
 }
 
+// Steps U of a group whose rows are long (fourth order, y component), each row loaded
+// one step ahead: row U + 1 (or the next group's first, `after`) is requested before step
+// U's arithmetic, so two rows are live instead of two groups of them.
+template <typename Lanes, typename Row, int U, int G>
+__device__ __forceinline__ void group_steps_ahead(Lanes& L, const Row* __restrict__ g, const Row* __restrict__ after,
+                                                  Row& cur) {
+  if constexpr (U < G) {
+    const Row nxt = (U + 1 < G) ? g[U + 1] : after[0];
+    __builtin_amdgcn_sched_barrier(0);
+    L.template step<false, U % Lanes::P>(cur.v, nullptr, nullptr);
+    __builtin_amdgcn_sched_barrier(0);
+    cur = nxt;
+    group_steps_ahead<Lanes, Row, U + 1, G>(L, g, after, cur);
+  }
+}
+
 // Steps [k, k_full) with the table rows read by the scalar unit (SGPR operands).
 template <typename R, int PPL, int FORM, int NS, int POL, int SH>
 __device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM, NS, POL, SH>& L, const R* __restrict__ table,
@@ -321,6 +337,10 @@ __device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM, NS, POL, S
   const Row* __restrict__ tab = reinterpret_cast<const Row*>(table);
   constexpr int kRows = Lanes::kRow >= 8 ? 1 : 8 / (Lanes::kRow / 2);  // rows fetched together
   constexpr int kGroup = (kRows + P - 1) / P * P;                     // whole periods
+  // two sets of a group's rows fit the scalar registers for short rows, or groups of one
+  // row; the long rows of the FP32 forms (groups of a whole coefficient period) go one
+  // row ahead instead
+  constexpr bool kTwoSets = kGroup == 1 || kGroup * Lanes::kRow * (int)sizeof(R) <= 32 * 4;
   while (k < k_full) {
     long long seg = k_full;
     if (sizeof(R) == 4) {
@@ -338,7 +358,22 @@ __device__ __forceinline__ void steps_scalar(BlochLanes<R, PPL, FORM, NS, POL, S
     // every load in flight) and its latency is hidden behind that set's other steps; the
     // scheduling barriers keep the loads there.  The clamped index re-reads the last
     // group instead of branching.
-    while (k + kGroup <= seg) {
+    if constexpr (!kTwoSets) {
+      // long rows: one row ahead.  Rows k .. k + n kGroup are read; the last of them is
+      // at most seg <= the last step's row, so every read is inside the table.
+      while (k + kGroup <= seg) {
+        const long long left = (seg - k) / kGroup;
+        const int n = left < (1 << 30) ? (int)left : (1 << 30);
+        const Row* __restrict__ g = tab + k;
+        Row cur = g[0];
+        for (int i = 0; i < n; ++i) {
+          const Row* __restrict__ gi = g + (long long)i * kGroup;
+          group_steps_ahead<Lanes, Row, 0, kGroup>(L, gi, gi + kGroup, cur);
+        }
+        k += (long long)n * kGroup;
+      }
+    }
+    while (kTwoSets && k + kGroup <= seg) {
       const long long left = (seg - k) / kGroup;
       const int n = left < (1 << 30) ? (int)left : (1 << 30);
       const Row* __restrict__ g = tab + k;
