@@ -143,17 +143,24 @@ def test_every_point_of_a_long_solve_against_the_oracle(gpu):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32fast"])
-@pytest.mark.parametrize("scheme", ["strang", "midpoint"])
-def test_short_chunks_cover_every_group_count(gpu, precision, scheme):
+@pytest.mark.parametrize("scheme,ellipticity", [("strang", 0.0), ("midpoint", 0.0), ("strang4", 0.0),
+                                                ("strang4", 0.5), ("strang", 0.5)])
+def test_short_chunks_cover_every_group_count(gpu, precision, scheme, ellipticity):
     """The step loops run whole groups of steps (8 or 16 Strang steps, 4 midpoint steps) from
-    two row sets in turn, then single steps.  Chunks of 1-40 steps starting at every phase
-    give ranges with no whole group, one, an odd and an even number of them, each with and
-    without single steps around them; the result is the single launch bit for bit."""
+    two row sets in turn, or, for the long rows of the fourth-order and y-component FP32
+    solves, groups of 4 steps each loading its next row one step ahead; then single steps.
+    Chunks of 1-40 steps starting at every phase give ranges with no whole group, one, an
+    odd and an even number of them, each with and without single steps around them; the
+    result is the single launch bit for bit."""
     chunks = [5, 8, 16, 24, 17, 15, 9, 33, 64, 7, 40, 3, 32, 1, 31, 48, 4, 12, 20, 2]
     N = sum(chunks)
-    single = run(gpu, RAGGED, RAGGED_FIELD, N, precision, scheme)
-    chunked = run(gpu, RAGGED, RAGGED_FIELD, N, precision, scheme, chunks=chunks)
+    field = dict(RAGGED_FIELD, ellipticity=ellipticity) if ellipticity else RAGGED_FIELD
+    single = run(gpu, RAGGED, field, N, precision, scheme)
+    chunked = run(gpu, RAGGED, field, N, precision, scheme, chunks=chunks)
     assert np.array_equal(single[0], chunked[0]) and single[1] == chunked[1]
+    if scheme == "strang4" or ellipticity:
+        n_o = oracle.solve_grid(field, RAGGED, N, scheme)[0]
+        assert np.max(np.abs(single[0] - n_o)) <= (FP64_N_ABS if precision == "fp64" else FP32_N_ABS)
 
 
 @pytest.mark.parametrize("precision,scheme,N,k", [("fp32", "strang", 3000, 1500), ("fp64", "strang", 2777, 1024),
