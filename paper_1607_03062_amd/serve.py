@@ -637,6 +637,7 @@ class Server:
                     waiting.remove(r)
                     r.status, r.reason = w
                     r.done_s = now
+                    r.checkpoint = None  # a retried request's host copy goes with it
             for name in list(self.active):
                 r = self.active[name]
                 w = self._withdrawn(r, now)
