@@ -71,3 +71,19 @@ def test_c_program_solves_on_the_device(gpu, tmp_path, precision, scheme):
     else:
         assert err <= 1e-5, err
     assert vals["rho"] == vals["rho_static"]
+
+
+@pytest.mark.gpu
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_c_program_runs_a_batch_on_the_device(gpu, tmp_path):
+    """tests/c/abi_batch.c: four members (FP32, FP64 and fast FP32 Strang in the persistent
+    kernel, an FP64 midpoint member in its own launch) run by pd_batch_run twice (capture,
+    replay) and by pd_batch_step_each epochs of uneven limits, from a plain C99 process;
+    every rho and n(p) equals the member's solve alone bit for bit."""
+    exe = tmp_path / "abi_batch"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "c", "abi_batch.c"), "-L", LIB_DIR, "-lpd",
+                    "-Wl,-rpath," + LIB_DIR, "-o", str(exe)], check=True)
+    print("abi_batch", flush=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "batch ok" in r.stdout, r.stdout[-3000:] + r.stderr[-2000:]
