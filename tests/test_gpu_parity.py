@@ -9,8 +9,9 @@ Tolerances:
   FP32 precision form: |n_gpu - n_oracle| <= 1e-5 per point (the bar set for
     the FP32 form; FP32 rounding of the state grows to a few 1e-6 after 80000 steps,
     as tests/fp32_model.py predicts;
-    the default form rounds each component once per rotation; the fast form's plain
-    shears, of alternating orientation, reach up to about 1.6x its worst-point error).
+    the once-rounded form rounds each component once per rotation; the fast form's
+    shears, of alternating orientation with same-plane rotations merged, reach up to
+    about 1.8x its worst-point error on long solves over wide grids).
   p_y = 0 lines: exactly 0.0 on both sides (the sigma_x eigenstate is kept).
   Launch shape, chunking and repeats: bit-identical n and rho.
 """
