@@ -420,7 +420,8 @@ def serve_object(args, pd, torch, np):
                                             args.epoch_steps, epoch_ms),
         "requests": args.requests, "rate_per_s": rate, "load": rate / capacity_rps, "value": res.point_steps_per_s,
         "unit": "point-steps/s", "p50_ms": res.p50_ms, "p99_ms": res.p99_ms, "mean_ms": res.mean_ms,
-        "completed": res.completed, "rejected": res.rejected, "makespan_s": res.makespan_s, "epochs": res.epochs,
+        "completed": res.completed, "rejected": res.rejected, "cancelled": res.cancelled, "expired": res.expired,
+        "failed": res.failed, "retried": res.retried, "makespan_s": res.makespan_s, "epochs": res.epochs,
         "mean_active": res.mean_active, "peak_bytes": res.peak_bytes, "budget_bytes": res.budget_bytes,
         "handles_reused": reused, "policy": args.policy, "epoch_ms": epoch_ms, "epoch_steps": args.epoch_steps,
         "background_setup": not args.no_background_setup, "defer_admissions": not args.no_defer_admissions,
