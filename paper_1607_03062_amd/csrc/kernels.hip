@@ -21,7 +21,9 @@
 // A plane rotation by phi is applied either as three shears (Paeth's
 // decomposition; one FMA each, coefficients tan(phi/2) and sin(phi)), or, when
 // some angle of the solve is too large for the shears to stay well conditioned,
-// in versine form with h = cos(phi) - 1 and s = sin(phi).
+// in versine form with h = cos(phi) - 1 and s = sin(phi).  The fast FP32 form runs
+// two successive rotations in one plane (a stage's field and per-point parts) as
+// five shears, the two adjacent shears of the same component merged.
 // The projection on u_out is n = |u_out^dagger psi|^2 = (1 + r.r_u) / 2 with
 // r_u = P_out / |P_out| the Bloch vector of u_out (Sec. II, Eqs. (1), (3)); r
 // is normalised first (the exact steps are unitary, Sec. III).
