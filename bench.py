@@ -206,9 +206,11 @@ def time_form(pd, torch, c, precision, steps, warmup, ppl, block, stage=0, chunk
     kern_ms = [a.elapsed_time(b) for a, b in zip(starts, ends)]
     import numpy as np
 
-    n = np.empty(c["grid"]["nx"] * c["grid"]["ny"])
+    # n(p) into pinned host memory (a new page-locked buffer), as a caller that moves
+    # results off the device would allocate it
+    n = torch.empty(c["grid"]["nx"] * c["grid"]["ny"], dtype=torch.float64, pin_memory=True).numpy()
     copy_s = []
-    for _ in range(2):  # reduction + copy of n(p) to (pageable) host memory; the first pass touches the pages
+    for _ in range(2):  # reduction + copy of n(p) to the host; the second pass is reported
         w0 = time.perf_counter()
         s.density(n_out=n, stream=st)
         copy_s.append(time.perf_counter() - w0)
