@@ -234,8 +234,9 @@ pd_status pd_propagate(pd_grid g, long long max_steps, void* stream);
 /* After the last step: sums n(p) into rho with a fixed-order reduction (the
    result does not depend on the launch shape), optionally copies n(p) to
    n_out (n_points doubles; device memory if n_out_on_device, else host
-   memory), and writes rho to the host double *rho_out (may be NULL).  When
-   rho_out or a host n_out is given the call waits for stream. */
+   memory, pageable or, for a copy at the full host-link rate, page-locked), and
+   writes rho to the host double *rho_out (may be NULL).  When rho_out or a host
+   n_out is given the call waits for stream. */
 pd_status pd_density(pd_grid g, double* n_out, int n_out_on_device, double* rho_out, void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture,
