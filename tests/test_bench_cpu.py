@@ -86,3 +86,14 @@ def test_traffic_lookup_follows_the_kernel_source():
             assert got >= 2048 * 2048 * 8
         else:
             assert got is None
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    """The benchmark runs on one GPU; --gpus 2 exits with status 2 and says why, before
+    touching a device."""
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, env=dict(os.environ, HIP_VISIBLE_DEVICES=""))
+    assert r.returncode == 2 and "one GPU" in r.stderr, (r.returncode, r.stderr[-500:])
