@@ -57,7 +57,7 @@ def check_parity(n, rho, n_o, grid, precision, valley_factor=4.0):
 # Fourth order
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32fast"])
 @pytest.mark.parametrize("scheme", ["strang4", "midpoint4"])
 def test_fourth_order_parity(gpu, scheme, precision):
     """Ragged 37 x 53 grid, 1500 steps of five stages (crosses the FP32 renormalisation step 1024)."""
@@ -79,7 +79,7 @@ def test_fourth_order_config1(gpu, scheme):
     assert np.all(n.reshape(64, 64)[32] == 0.0) and info["n_masked"] == 1
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32fast"])
 @pytest.mark.parametrize("scheme", ["strang4", "midpoint4"])
 def test_fourth_order_shapes_and_chunks(gpu, scheme, precision):
     """Every launch shape and a chunked solve give the same bits."""
@@ -111,7 +111,7 @@ def test_fourth_order_versine_form(gpu):
 # Elliptic polarisation
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32fast"])
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_elliptic_sin2_parity(gpu, scheme, precision):
     N = 1300 if scheme.endswith("4") else 2600
@@ -251,7 +251,7 @@ def test_kminus_batch_member(gpu):
 # Snapshots
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32fast"])
 @pytest.mark.parametrize("scheme", SCHEMES)
 @pytest.mark.parametrize("field", ["linear", "elliptic"])
 def test_snapshots_match_oracle(gpu, scheme, precision, field):
