@@ -37,7 +37,8 @@ def _sample():
 
 
 @pytest.mark.parametrize("scheme,precision,ppl", [
-    ("strang", "fp32", 1), ("strang", "fp64", 0), ("strang", "fp64", 1), ("midpoint", "fp32", 1),
+    ("strang", "fp32", 1), ("strang", "fp32fast", 1), ("strang", "fp64", 0), ("strang", "fp64", 1),
+    ("midpoint", "fp32", 1),
 ])
 def test_full_maximum_grid(gpu, scheme, precision, ppl):
     import torch
@@ -105,7 +106,7 @@ def test_snapshot_on_maximum_grid(gpu):
 
 
 @pytest.mark.parametrize("shape", [(NMAX, 1), (1, NMAX), (NMAX, 3)])
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32fast"])
 def test_thin_grids_at_maximum_extent(gpu, shape, precision):
     nx, ny = shape
     g = {"nx": nx, "ny": ny, "px": (-3.0, 2.5), "py": (-1.5, 1.0)}
